@@ -1,0 +1,86 @@
+"""Oracle coefficient tables of the digit-space and lifting polynomials.
+
+Test infrastructure only (see the package docstring).
+
+* F_EQ(x, 0) = 1 - x^(p-1) over Z_p (Fermat's little theorem, Theorem 1 and Eq. 2;
+  restated for comparison with zero in the Method's comparison subsection).
+* F_LT(x, 0) = (p+1)/2 x^(p-1) + sum_{i odd, 1 <= i <= p-2} c_i x^i with
+  c_i = sum_{j=1}^{(p-1)/2} j^(p-1-i)  (Method, comparison subsection).
+* G_{p,2}: a polynomial with G(z0 + p z1) = z0 mod p^2 for balanced z0 (Lemma 3).
+  The paper defers the construction; the reading used here is the monic form
+  G(x) = x^p + p H(x) mod p^2, where H in F_p[x] (degree <= p-1) interpolates
+  (z - z^p)/p mod p at every balanced z.  Then G(z) = z mod p^2 on balanced z and
+  G'(z) = 0 mod p, which gives Lemma 3's property by Taylor expansion; its degree
+  p meets Lemma 3's bound (e-1)(p-1)+1 for e = 2.
+All coefficient lists are ascending (index i is the coefficient of x^i), values in [0, modulus).
+"""
+from __future__ import annotations
+
+
+def f_eq(p: int) -> list:
+    c = [0] * p
+    c[0] = 1
+    c[p - 1] = p - 1
+    return c
+
+
+def f_lt(p: int) -> list:
+    c = [0] * p
+    c[p - 1] = (p + 1) // 2 % p
+    for i in range(1, p - 1, 2):
+        c[i] = sum(pow(j, p - 1 - i, p) for j in range(1, (p - 1) // 2 + 1)) % p
+    return c
+
+
+def _poly_mul(a, b, m):
+    out = [0] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        if x:
+            for j, y in enumerate(b):
+                out[i + j] = (out[i + j] + x * y) % m
+    return out
+
+
+def lagrange(points, values, m):
+    """Coefficients of the unique polynomial of degree < len(points) through the points, mod prime m."""
+    n = len(points)
+    result = [0] * n
+    for i, (xi, yi) in enumerate(zip(points, values)):
+        if yi % m == 0:
+            continue
+        num = [1]
+        den = 1
+        for j, xj in enumerate(points):
+            if j != i:
+                num = _poly_mul(num, [(-xj) % m, 1], m)
+                den = den * (xi - xj) % m
+        scale = yi * pow(den, -1, m) % m
+        for k in range(n):
+            result[k] = (result[k] + scale * num[k]) % m
+    return result
+
+
+def g_p2(p: int) -> list:
+    """Coefficients of G_{p,2} mod p^2 (length p + 1)."""
+    zs = list(range(-(p - 1) // 2, (p - 1) // 2 + 1))
+    phi = [((z - z ** p) // p) % p for z in zs]
+    H = lagrange([z % p for z in zs], phi, p)
+    t = p * p
+    G = [(p * h) % t for h in H] + [0]
+    G[p] = (G[p] + 1) % t
+    return G
+
+
+def g_poly(p: int, e: int) -> list:
+    if e == 1:
+        return [0, 1]  # the identity: digit extraction mod p is the value itself
+    if e == 2:
+        return g_p2(p)
+    raise NotImplementedError("G_{p,e} for e >= 3 is not built")
+
+
+def eval_mod(coeffs, x: int, m: int) -> int:
+    acc = 0
+    for c in reversed(coeffs):
+        acc = (acc * x + c) % m
+    return acc

@@ -1,0 +1,211 @@
+"""Oracle polynomial evaluation and the space-switching composites.
+
+Test infrastructure only (see the package docstring).
+
+Polynomial evaluation follows the baby-step/giant-step form of Paterson-Stockmeyer
+(Theorem 2).  The paper does not spell out the schedule; the reading fixed here,
+which decides every ciphertext bit, is:
+
+  degree D, k = smallest power of two with 2 k^2 >= D + 1, g = ceil((D+1)/k);
+  baby powers x^i (2 <= i <= k) and giant powers y^j (y = x^k, 2 <= j <= g-1) by the
+  power rule: h = 2^floor(log2 i); x^i = x^(i/2) x^(i/2) if i = h, else x^h x^(i-h);
+  every product is: bring both operands to the lower level by single-prime
+  modulus switches, relinearised product, one modulus switch;
+  inner sums I_j = sum_{i=1}^{k-1} c_{jk+i} x^i over nonzero coefficients only,
+  each power first brought to the lowest level among the powers used, scalar
+  products accumulated in increasing i, then the constant c_{jk} added;
+  an inner sum with no power term contributes c_{jk} y^j as a scalar product;
+  outer sum over j = 1..g-1 in increasing j (each term I_j * y^j a product as
+  above), operands brought to the lower level before each addition, I_0 added last.
+
+Composites (Method section, r = 2 is the built case; the loops are general):
+  space_reduce = Algorithm 3: a_i = G_{p,r-i}(b); b = DivideByP(b - a_i); then
+                 ChangeModToP on every digit;
+  compare      = Algorithm 4: LT = LT_{r-1}, EQ = EQ_{r-1}; for i = r-2..0:
+                 LT = LT + EQ * LT_i (EQ = EQ * EQ_i only while still needed);
+                 EQ_i = 1 - x_i^(p-1) with the power from the power rule;
+  space_raise  = RaiseModToP2R: plaintext modulus back to p^r, then G_{p,r}.
+"""
+from __future__ import annotations
+
+from . import bgv as B
+from . import polys
+
+
+class Counter:
+    def __init__(self):
+        self.mul = 0
+        self.max_depth = 0
+
+
+def _mul(P, keys, a, b, cnt=None):
+    lv = min(a.level, b.level)
+    a = B.align(P, a, lv)
+    b = B.align(P, b, lv)
+    r = B.mul_relin(P, keys.relin, a, b)
+    if cnt is not None:
+        cnt.mul += 1
+    return B.mod_switch(P, r)
+
+
+def _add(P, a, b):
+    lv = min(a.level, b.level)
+    return B.add(P, B.align(P, a, lv), B.align(P, b, lv))
+
+
+def bsgs_shape(D: int):
+    k = 1
+    while 2 * k * k < D + 1:
+        k *= 2
+    g = -(-(D + 1) // k)
+    return k, g
+
+
+def _power_rule(table, i, P, keys, cnt):
+    if i in table:
+        return table[i]
+    h = 1 << (i.bit_length() - 1)
+    if i == h:
+        half = _power_rule(table, i // 2, P, keys, cnt)
+        table[i] = _mul(P, keys, half, half, cnt)
+    else:
+        table[i] = _mul(P, keys, _power_rule(table, h, P, keys, cnt),
+                        _power_rule(table, i - h, P, keys, cnt), cnt)
+    return table[i]
+
+
+def power(P, keys, x, e, cnt=None):
+    """x^e by the power rule (e >= 1)."""
+    table = {1: x}
+    return _power_rule(table, e, P, keys, cnt)
+
+
+def eval_poly(P, keys, x, coeffs, cnt=None):
+    """Evaluate sum_i coeffs[i] x^i (coefficients mod t = p^t_exp of x)."""
+    t = P.t(x.t_exp)
+    c = [int(v) % t for v in coeffs]
+    D = len(c) - 1
+    while D > 0 and c[D] == 0:
+        D -= 1
+    k, g = bsgs_shape(D)
+    baby = {1: x}
+    for i in range(2, k + 1):
+        _power_rule(baby, i, P, keys, cnt)
+    giant = {1: baby[k]}
+    for j in range(2, g):
+        _power_rule(giant, j, P, keys, cnt)
+
+    def coef(n):
+        return c[n] if n <= D else 0
+
+    inner = []
+    for j in range(g):
+        used = [i for i in range(1, k) if coef(j * k + i) != 0]
+        const = coef(j * k)
+        if not used:
+            inner.append(("const", const))
+            continue
+        lv = min(baby[i].level for i in used)
+        acc = None
+        for i in used:
+            term = B.mul_scalar(P, B.align(P, baby[i], lv), coef(j * k + i))
+            acc = term if acc is None else B.add(P, acc, term)
+        if const != 0:
+            acc = B.add_const(P, acc, const)
+        inner.append(("ct", acc))
+
+    result = None
+    for j in range(1, g):
+        kind, v = inner[j]
+        if kind == "const":
+            if v == 0:
+                continue
+            term = B.mul_scalar(P, giant[j], v)
+        else:
+            term = _mul(P, keys, v, giant[j], cnt)
+        result = term if result is None else _add(P, result, term)
+    kind, v = inner[0]
+    if kind == "const":
+        if result is None:
+            raise ValueError("constant polynomial: nothing to evaluate")
+        if v != 0:
+            result = B.add_const(P, result, v)
+    else:
+        result = v if result is None else _add(P, result, v)
+    return result
+
+
+def space_reduce(P, keys, a, cnt=None):
+    """Algorithm 3: digits a_0..a_{r-1} of a (plaintext modulus p^r) as t = p ciphertexts."""
+    r = a.t_exp
+    b = a
+    digits = []
+    for i in range(r - 1):
+        ai = eval_poly(P, keys, b, polys.g_poly(P.p, r - i), cnt)
+        bb = B.align(P, b, ai.level)
+        b = B.divide_by_p(P, B.sub(P, bb, ai))
+        digits.append(ai)
+    digits.append(b)
+    return [B.change_mod_to_p(P, d) for d in digits]
+
+
+def _eq_digit(P, keys, x, cnt):
+    y = power(P, keys, x, P.p - 1, cnt)
+    return B.add_const(P, B.neg(P, y), 1)
+
+
+def compare(P, keys, digits, op="lt", cnt=None):
+    """Algorithm 4 over the digits (least significant first); op 'lt' or 'eq'."""
+    r = len(digits)
+    if op == "eq":
+        eq = _eq_digit(P, keys, digits[r - 1], cnt)
+        for i in range(r - 2, -1, -1):
+            eq = _mul(P, keys, eq, _eq_digit(P, keys, digits[i], cnt), cnt)
+        return eq
+    flt = polys.f_lt(P.p)
+    lts = [eval_poly(P, keys, dg, flt, cnt) for dg in digits]
+    lt = lts[r - 1]
+    eq = _eq_digit(P, keys, digits[r - 1], cnt) if r > 1 else None
+    for i in range(r - 2, -1, -1):
+        lt = _add(P, lt, _mul(P, keys, eq, lts[i], cnt))
+        if i > 0:
+            eq = _mul(P, keys, eq, _eq_digit(P, keys, digits[i], cnt), cnt)
+    return lt
+
+
+def space_raise(P, keys, a, cnt=None):
+    """RaiseModToP2R: tag t = p^r, then G_{p,r} clears the higher digits."""
+    x = B.raise_tag(P, a)
+    return eval_poly(P, keys, x, polys.g_poly(P.p, P.r), cnt)
+
+
+def less_than(P, keys, x, y, cnt=None):
+    """[x < y] in the number space (t = p^r), through reduce -> compare -> raise."""
+    d = B.sub(P, x, y) if y is not None else x
+    return space_raise(P, keys, compare(P, keys, space_reduce(P, keys, d, cnt), "lt", cnt), cnt)
+
+
+def masked_product(P, keys, x, y, v, cnt=None):
+    """v * [x < y]  (the tiny primitive pipeline)."""
+    return _mul(P, keys, less_than(P, keys, x, y, cnt), v, cnt)
+
+
+def relu(P, keys, x, cnt=None):
+    """x * (1 - [x < 0])."""
+    lt = less_than(P, keys, x, None, cnt)
+    return _mul(P, keys, x, B.add_const(P, B.neg(P, lt), 1), cnt)
+
+
+def filter_product(P, keys, a, tq, b, c, cnt=None):
+    """[a < tq] * (b * c) for one ciphertext of rows."""
+    bc = _mul(P, keys, b, c, cnt)
+    return _mul(P, keys, less_than(P, keys, a, tq, cnt), bc, cnt)
+
+
+def rotate_and_sum(P, keys, ct):
+    """Every slot ends up holding the sum of all slots: row rotations by 2^i, then the row swap."""
+    i = 1
+    while i < P.ell // 2:
+        ct = B.add(P, ct, B.rotate(P, keys.galois, ct, i))
+        i *= 2
+    return B.add(P, ct, B.rotate(P, keys.galois, ct, "conj"))

@@ -1,0 +1,118 @@
+"""Pins for the oracle's polynomial evaluation and space-switching composites:
+encrypted brute force over all of Z_{p^2} at tiny rings."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import bgv as B
+from oracle import polys
+from oracle import space as S
+from tests.oracle_ctx import tiny5, tiny17
+
+
+def _balanced_digits(v, p):
+    h = (p - 1) // 2
+    z0 = ((v + h) % p) - h
+    z1 = ((v - z0) // p + h) % p - h
+    return z0, z1
+
+
+def _centered(v, m):
+    v %= m
+    return v - m if v > (m - 1) // 2 else v
+
+
+@pytest.mark.parametrize("deg", [1, 2, 5, 16, 17, 31])
+def test_bsgs_matches_horner_and_theorem2_depth(deg):
+    c = tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(deg)
+    coeffs = [int(x) for x in g.integers(0, t, size=deg + 1)]
+    coeffs[deg] = coeffs[deg] or 1
+    xs = [int(x) for x in g.integers(0, t, size=P.ell)]
+    cnt = S.Counter()
+    out = S.eval_poly(P, c.keys, c.enc(xs), coeffs, cnt)
+    assert c.dec(out) == [polys.eval_mod(coeffs, x, t) for x in xs]
+    depth = P.L - out.level
+    assert depth <= math.ceil(math.log2(deg)) + 1 if deg > 1 else depth <= 1
+    k, gg = S.bsgs_shape(deg)
+    assert cnt.mul <= (k - 1) + (gg - 2) + (gg - 1)
+
+
+@pytest.mark.parametrize("ctx", [tiny5, tiny17])
+def test_space_reduce_brute_force(ctx):
+    c = ctx()
+    P, p, t = c.P, c.P.p, c.P.t_full
+    for start in range(0, t, P.ell):
+        vals = [(start + i) % t for i in range(P.ell)]
+        dg = S.space_reduce(P, c.keys, c.enc(vals))
+        assert [d.t_exp for d in dg] == [1, 1]
+        got0, got1 = c.dec(dg[0]), c.dec(dg[1])
+        for v, a0, a1 in zip(vals, got0, got1):
+            z0, z1 = _balanced_digits(v, p)
+            assert (a0, a1) == (z0 % p, z1 % p)
+
+
+@pytest.mark.parametrize("ctx", [tiny5, tiny17])
+def test_compare_brute_force(ctx):
+    """LT and EQ of every d in Z_{p^2} against zero: LT = [centered(d) < 0], EQ = [d = 0]."""
+    c = ctx()
+    P, p, t = c.P, c.P.p, c.P.t_full
+    step = P.ell if P.ell > 2 else 2
+    for start in range(0, t, step):
+        vals = [(start + i) % t for i in range(P.ell)]
+        dg = S.space_reduce(P, c.keys, c.enc(vals))
+        lt = c.dec(S.compare(P, c.keys, dg, "lt"))
+        eq = c.dec(S.compare(P, c.keys, dg, "eq"))
+        assert lt == [1 if _centered(v, t) < 0 else 0 for v in vals]
+        assert eq == [1 if v == 0 else 0 for v in vals]
+
+
+@pytest.mark.parametrize("ctx", [tiny5, tiny17])
+def test_space_raise_clears_high_digits(ctx):
+    """Raise of k + p*junk (tagged p) returns centered_p(k) mod p^2."""
+    c = ctx()
+    P, p, t = c.P, c.P.p, c.P.t_full
+    g = np.random.default_rng(11)
+    for _ in range(3):
+        ks = [int(x) for x in g.integers(0, p, size=P.ell)]
+        junk = [int(x) for x in g.integers(0, p, size=P.ell)]
+        ct = B.change_mod_to_p(P, c.enc([(k + p * j) % t for k, j in zip(ks, junk)]))
+        out = S.space_raise(P, c.keys, ct)
+        assert out.t_exp == P.r
+        assert c.dec(out) == [_centered(k, p) % t for k in ks]
+
+
+def test_masked_product_pipeline_small_p():
+    """v * [x < y] through reduce -> compare -> raise -> multiply (all pairs for p = 5)."""
+    c = tiny5()
+    P, p, t = c.P, c.P.p, c.P.t_full
+    pairs = [(x, y) for x in range(p) for y in range(p)]
+    for i in range(0, len(pairs), P.ell):
+        chunk = pairs[i:i + P.ell]
+        chunk += [(0, 0)] * (P.ell - len(chunk))
+        xs = [a for a, _ in chunk]
+        ys = [b for _, b in chunk]
+        vs = [(3 * a + b + 1) % t for a, b in chunk]
+        out = S.masked_product(P, c.keys, c.enc(xs), c.enc(ys), c.enc(vs))
+        assert out.level >= 1
+        assert c.dec(out) == [v if a < b else 0 for v, a, b in zip(vs, xs, ys)]
+
+
+def test_relu_and_filter_sum_pipelines():
+    c = tiny17()
+    P, t = c.P, c.P.t_full
+    xs = [-100, -1, 0, 1, 17, 144, -144, 55]
+    out = S.relu(P, c.keys, c.enc([x % t for x in xs]))
+    assert out.level >= 1
+    assert c.dec(out) == [max(x, 0) % t for x in xs]
+    a = [3, 90, 200, 4, 16, 1, 2, 150]
+    b = [5, 6, 7, 8, 9, 10, 11, 12]
+    cc = [2, 3, 4, 5, 6, 7, 8, 9]
+    thr = 100
+    prod = S.filter_product(P, c.keys, c.enc(a), c.enc([thr] * P.ell), c.enc(b), c.enc(cc))
+    assert c.dec(prod) == [(x * y if v < thr else 0) % t for v, x, y in zip(a, b, cc)]
+    total = S.rotate_and_sum(P, c.keys, prod)
+    expect = sum(x * y for v, x, y in zip(a, b, cc) if v < thr) % t
+    assert c.dec(total) == [expect] * P.ell
