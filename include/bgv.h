@@ -1,0 +1,208 @@
+/*
+ * bgv.h -- C-ABI of the MI355X (gfx950) space-switching BGV library.
+ *
+ * The library evaluates the exact RNS arithmetic that carries every homomorphic
+ * multiplication of the space-switching method (arXiv 2604.19890): negacyclic
+ * NTT/INTT over 50-bit primes, pointwise modular products, hybrid key switching
+ * (relinearisation and slot rotation), modulus switching, and on top of them the
+ * reduction Z_{p^r} -> Z_p (Algorithm 3), the digit-wise comparison (Algorithm 4)
+ * and modulus raising Z_p -> Z_{p^r} (Method, modulus-raising subsection).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Ring: Z_Q[X]/(X^N + 1), N = 2^log_n; the paper's general cyclotomic Phi_m
+ *   (Background, BGV subsection) taken at m = 2N.  Plaintext modulus p^r with
+ *   p = 1 (mod 4); ell = 2^(v2(p-1)-1) slots, each holding a constant of Z_{p^r}.
+ * Primes: the first L + K primes below 2^50 that are 1 mod lcm(2N, p^r), in
+ *   descending order; q_0..q_{L-1} carry the ciphertext, the last K are the
+ *   special primes of hybrid key switching (digit size alpha = K).
+ * Ciphertext batches (bgv_ct): `d` is a DEVICE buffer owned by the caller that
+ *   holds `n` ciphertexts back to back, each laid out [2][level][N] as uint64
+ *   residues in [0, q_i), in evaluation form (negacyclic NTT under the smallest
+ *   primitive 2N-th root psi_i of q_i, bit-reversed order: word j of limb i is
+ *   c(psi_i^(2 brv(j) + 1)) mod q_i).  `cap_words` is the number of uint64 words
+ *   the buffer can hold; every entry point that writes a batch checks it and
+ *   returns BGV_E_ARG rather than writing past it.  `t_exp` is the current
+ *   plaintext-modulus exponent (t = p^t_exp).
+ * Streams: every device operation is enqueued on the context's stream (a
+ *   hipStream_t given at creation or by bgv_set_stream) and returns before the
+ *   work completes.  Argument, level and plaintext-modulus errors are detected on
+ *   the host before anything is enqueued.  Device faults surface at bgv_sync.
+ *   An output batch may alias an input batch of the same operation.
+ *   A context is not thread-safe; use one context per host thread.
+ * Randomness: the library never samples.  Secret keys, key-switching and
+ *   encryption randomness come in as host arrays from the caller's seeded
+ *   generator.
+ * Errors: every entry point returns a bgv_status; bgv_last_error gives a
+ *   message for the last failure on a context.
+ */
+#ifndef BGV_H
+#define BGV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BGV_OK = 0,
+  BGV_E_ARG = 1,         /* null pointer, bad size, buffer too small, bad op code */
+  BGV_E_PARAM = 2,       /* unsupported ring / plaintext / chain parameters     */
+  BGV_E_LEVEL = 3,       /* level mismatch, or no level left to switch down      */
+  BGV_E_PTXT_MOD = 4,    /* plaintext-modulus exponents differ or are invalid    */
+  BGV_E_NOKEY = 5,       /* no Galois key for the requested rotation             */
+  BGV_E_OOM = 6,         /* device or host allocation failed                     */
+  BGV_E_DEVICE = 7,      /* a HIP runtime call failed                            */
+  BGV_E_UNSUPPORTED = 8  /* a case the library does not build (e.g. r >= 3)      */
+} bgv_status;
+
+typedef struct {
+  int32_t log_n; /* N = 2^log_n, 4 <= log_n <= 16                                 */
+  int32_t p;     /* plaintext prime, p = 1 mod 4                                  */
+  int32_t r;     /* plaintext exponent, t = p^r (r = 2 is the built reduction)    */
+  int32_t L;     /* ciphertext primes                                             */
+  int32_t K;     /* special primes for hybrid key switching; digit size alpha = K */
+} bgv_params;
+
+typedef struct {
+  uint64_t* d;       /* device buffer, n x [2][level][N] uint64, evaluation form */
+  int64_t cap_words; /* capacity of d in uint64 words                            */
+  int32_t n;         /* ciphertexts in the batch (>= 1)                          */
+  int32_t level;     /* active primes q_0..q_{level-1}                           */
+  int32_t t_exp;     /* plaintext modulus p^t_exp                                */
+  int32_t _pad;
+} bgv_ct;
+
+typedef struct {
+  int32_t N, log_n, p, r, L, K, alpha, dnum; /* dnum = ceil(L / alpha)       */
+  int32_t slots, d;                          /* ell slots of degree d = N/ell */
+  int64_t t;                                 /* p^r                          */
+} bgv_info;
+
+typedef struct bgv_ctx bgv_ctx;
+typedef struct bgv_keys bgv_keys;
+
+#define BGV_ROW_SWAP (-1) /* rotation step that swaps the two slot rows (X -> X^(2N-1)) */
+#define BGV_OP_LT 0
+#define BGV_OP_EQ 1
+
+/* ---- context -------------------------------------------------------------
+ * bgv_ctx_create: derives the prime chain, NTT roots and twiddles, slot roots,
+ *   base-conversion constants and the coefficient tables of G_{p,2}, F_LT, F_EQ,
+ *   and uploads the device tables.  `hip_stream` is a hipStream_t (NULL = the
+ *   null stream).  BGV_E_PARAM for unsupported parameters (p = 3 mod 4, ring too
+ *   small for p, not enough 50-bit primes, L + K > 64).  The context owns all of
+ *   its memory; bgv_ctx_destroy frees it (after synchronising its stream).     */
+bgv_status bgv_ctx_create(const bgv_params* prm, void* hip_stream, bgv_ctx** out);
+void bgv_ctx_destroy(bgv_ctx* ctx);
+bgv_status bgv_set_stream(bgv_ctx* ctx, void* hip_stream);
+bgv_status bgv_ctx_info(const bgv_ctx* ctx, bgv_info* out);
+/* primes (L + K values, q_0..q_{L-1} then the special primes) into host `out` */
+bgv_status bgv_ctx_primes(const bgv_ctx* ctx, uint64_t* out);
+/* words of one ciphertext at `level` (2 * level * N) */
+int64_t bgv_ct_words(const bgv_ctx* ctx, int32_t level);
+bgv_status bgv_sync(bgv_ctx* ctx);
+const char* bgv_last_error(const bgv_ctx* ctx);
+
+/* ---- keys ----------------------------------------------------------------
+ * Hybrid key-switching keys (digit j = primes j*alpha .. min((j+1)*alpha, L)-1):
+ *   ksk_j = (b_j, a_j),  b_j = -a_j s + t e_j + [prime in digit j] P s'  (mod every
+ *   one of the L + K primes, P = product of the special primes), with s' = s^2 for
+ *   relinearisation and s' = s(X^g) for the Galois element g of a rotation.
+ * Host inputs: s [N] ternary; a [n_keys][dnum][L+K][N] residues (< the prime of
+ *   their row); e [n_keys][dnum][N] small signed errors.  Key order: relinearisation,
+ *   then one key per entry of `steps` (row rotation by steps[i] slots, i.e.
+ *   g = 5^steps[i] mod 2N; BGV_ROW_SWAP allowed), then the row swap if with_conj.
+ * Keys live in device memory owned by the returned object (evaluation form).  */
+bgv_status bgv_keygen(bgv_ctx* ctx, const int8_t* s, const uint64_t* a, const int32_t* e,
+                      const int32_t* steps, int32_t n_steps, int32_t with_conj, bgv_keys** out);
+void bgv_keys_destroy(bgv_keys* keys);
+int64_t bgv_keys_bytes(const bgv_keys* keys);
+
+/* ---- encryption (Algorithm 1) and decryption (Algorithm 2) ---------------
+ * bgv_encrypt: out->n ciphertexts at level L with t = p^r.  Host inputs per
+ *   ciphertext b: slots[b*ell ..] values mod p^r (encoded as m(X) = M(X^d), M the
+ *   interpolant of the slots at the slot roots, coefficients lifted to the
+ *   centered range); c1[b] [L][N] uniform residues; e[b] [N] small errors.
+ *   c0 = m + t e - c1 s.  s is host [N] ternary.
+ * bgv_decrypt: synchronises the stream, then writes in->n * ell slot values
+ *   (mod p^t_exp) to host `slots`; if `nonconst` is not NULL it receives one flag
+ *   per slot that is 1 when the slot is not a constant of Z_{p^t_exp}.          */
+bgv_status bgv_encrypt(bgv_ctx* ctx, const int8_t* s, const uint64_t* slots, const uint64_t* c1,
+                       const int32_t* e, bgv_ct* out);
+bgv_status bgv_decrypt(bgv_ctx* ctx, const int8_t* s, const bgv_ct* in, uint64_t* slots,
+                       uint8_t* nonconst);
+
+/* ---- linear operations (slot-wise) ----------------------------------------
+ * add/sub need equal level (BGV_E_LEVEL) and t_exp (BGV_E_PTXT_MOD); b may be a
+ * single ciphertext (b->n == 1) broadcast against a batch.  Constants are lifted
+ * to the centered range mod p^t_exp.  bgv_add_const adds c to every slot.
+ * bgv_divide_by_p: DivideByP (Method, reduction subsection) -- multiply by
+ * p^-1 mod each q_i and lower t_exp by one; the caller guarantees every slot is
+ * 0 mod p.  bgv_set_t_exp changes only the tag: ChangeModToP (t_exp = 1, Lemma 4)
+ * or the first half of modulus raising (t_exp = r).                           */
+bgv_status bgv_add(bgv_ctx* ctx, const bgv_ct* a, const bgv_ct* b, bgv_ct* out);
+bgv_status bgv_sub(bgv_ctx* ctx, const bgv_ct* a, const bgv_ct* b, bgv_ct* out);
+bgv_status bgv_negate(bgv_ctx* ctx, const bgv_ct* a, bgv_ct* out);
+bgv_status bgv_mul_scalar(bgv_ctx* ctx, const bgv_ct* a, int64_t c, bgv_ct* out);
+bgv_status bgv_add_const(bgv_ctx* ctx, const bgv_ct* a, int64_t c, bgv_ct* out);
+bgv_status bgv_divide_by_p(bgv_ctx* ctx, const bgv_ct* a, bgv_ct* out);
+bgv_status bgv_set_t_exp(bgv_ctx* ctx, bgv_ct* ct, int32_t t_exp);
+
+/* ---- products, rotations, modulus switching -------------------------------
+ * bgv_mul_relin: tensor product and relinearisation by hybrid key switching
+ *   (ModUp of each digit, inner product with the key, ModDown with the t-corrected
+ *   delta); output at the input level, no modulus switch inside.
+ * bgv_rotate: X -> X^g on both components, then key switching of the second under
+ *   the Galois key (BGV_E_NOKEY if no key for the step).
+ * bgv_mod_switch: drop the top prime: w = centered([c_top t^-1]_{q_top}),
+ *   c_i <- (c_i - t w) q_top^-1.  BGV_E_LEVEL at level 1.
+ * bgv_mod_switch_to: the same single-prime step repeated down to `level`
+ *   (bit-identical to repeated bgv_mod_switch, computed in one fused pass).     */
+bgv_status bgv_mul_relin(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* a, const bgv_ct* b,
+                         bgv_ct* out);
+bgv_status bgv_rotate(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, int32_t step,
+                      bgv_ct* out);
+bgv_status bgv_mod_switch(bgv_ctx* ctx, const bgv_ct* in, bgv_ct* out);
+bgv_status bgv_mod_switch_to(bgv_ctx* ctx, const bgv_ct* in, int32_t level, bgv_ct* out);
+
+/* ---- polynomial evaluation and space switching ----------------------------
+ * bgv_eval_poly: sum_i coeffs[i] x^i (coefficients reduced mod p^t_exp) by the
+ *   baby-step/giant-step Paterson-Stockmeyer form (Theorem 2) with the schedule
+ *   documented in the library's design notes; every product is followed by one
+ *   modulus switch.  The output level is input level minus the schedule depth;
+ *   BGV_E_LEVEL if the chain is too short.
+ * bgv_space_reduce: Algorithm 3 for r = 2: digits[0] = G_{p,2}(in) and
+ *   digits[1] = DivideByP(in - digits[0]), both tagged t = p (ChangeModToP); the
+ *   digits are the balanced base-p digits of each slot.  `digits` has r entries.
+ * bgv_compare: Algorithm 4 on r digit batches (least significant first), op
+ *   BGV_OP_LT ([value < 0] on the centered range of Z_{p^r}) or BGV_OP_EQ.
+ * bgv_space_raise: RaiseModToP2R -- tag t = p^r, then G_{p,r}; a slot holding k
+ *   mod p becomes centered_p(k) mod p^r.
+ * bgv_less_than: reduce -> compare(LT) -> raise of (x - y), or of x if y is NULL.
+ * bgv_rotate_sum: every slot receives the sum of all slots (row rotations by
+ *   1, 2, 4, .., ell/4 and the row swap; all those keys are needed).           */
+bgv_status bgv_eval_poly(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, const int64_t* coeffs,
+                         int32_t degree, bgv_ct* out);
+bgv_status bgv_space_reduce(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, bgv_ct* digits);
+bgv_status bgv_compare(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* digits, int32_t r, int32_t op,
+                       bgv_ct* out);
+bgv_status bgv_space_raise(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, bgv_ct* out);
+bgv_status bgv_less_than(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* x, const bgv_ct* y,
+                         bgv_ct* out);
+bgv_status bgv_rotate_sum(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, bgv_ct* out);
+
+/* ---- raw NTT access (the transform on its own, for tests and bandwidth runs)
+ * bgv_ntt: in place on a DEVICE array holding n_polys polynomials of `level` limbs
+ *   each ([n_polys][level][N] uint64 residues, limb i under q_i); forward (coefficient
+ *   -> evaluation form, layout as for ciphertexts) when inverse == 0, else inverse.
+ *   cap_words is the capacity of d.                                              */
+bgv_status bgv_ntt(bgv_ctx* ctx, uint64_t* d, int64_t cap_words, int32_t n_polys, int32_t level,
+                   int32_t inverse);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BGV_H */

@@ -31,6 +31,7 @@ def _load():
     lib.o_mulmod_scalar.argtypes = [u64p, u64, u64p, i64, u64]
     lib.o_ntt_def.argtypes = [u64p, u64p, i64, u64, u64]
     lib.o_intt_def.argtypes = [u64p, u64p, i64, u64, u64, u64p]
+    lib.o_ntt_def_at.argtypes = [u64p, i64p, i64, u64p, i64, u64, u64]
     return lib
 
 
@@ -110,4 +111,12 @@ def intt_def(a, q, psi):
     out = np.empty_like(a)
     scratch = np.empty(2 * a.shape[0], dtype=np.uint64)
     _lib.o_intt_def(_p(a), _p(out), a.shape[0], int(q), int(psi), _p(scratch))
+    return out
+
+
+def ntt_def_at(a, q, psi, idx):
+    a = _u64(a)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(len(idx), dtype=np.uint64)
+    _lib.o_ntt_def_at(_p(a), _p(idx, ctypes.c_int64), len(idx), _p(out), a.shape[0], int(q), int(psi))
     return out

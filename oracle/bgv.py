@@ -453,3 +453,84 @@ def keygen(P: Params, s, key_rand, steps=(), with_conj=False) -> Keys:
         a, e = key_rand[1 + i]
         gal[g] = keygen_switch(P, s64, automorph_int(s64, g), a, e)
     return Keys(relin, gal)
+
+
+# ----------------------------------------------------------------------------- sampled outputs
+# The same computations restricted to a set of output coefficient indices, for
+# checks at ring sizes where the full schoolbook products take too long.  Every
+# step is coefficient-wise except the ring products, which are evaluated only at
+# the requested indices; inputs that feed a product are still used in full.
+
+def mod_down_cols(P: Params, u: np.ndarray, level: int, t: int) -> np.ndarray:
+    """mod_down applied to selected columns: u [level+K][S] -> [level][S] (columns are independent)."""
+    return mod_down(_SubP(P, u.shape[1]), u, level, t)
+
+
+class _SubP:
+    """View of Params with N replaced by a column count (coefficient-wise steps only)."""
+
+    def __init__(self, P, ncols):
+        self._P = P
+        self.N = ncols
+
+    def __getattr__(self, k):
+        return getattr(self._P, k)
+
+
+def key_switch_at(P: Params, x: np.ndarray, key: SwitchKey, level: int, t_exp: int, idx) -> tuple:
+    """key_switch(x) evaluated only at coefficient indices idx (x is the full [level][N] input)."""
+    digits = P.digits(level)
+    ups = [mod_up(P, x, level, dg) for dg in digits]
+    key_rows = list(range(level)) + [P.L + k for k in range(len(P.P))]
+    idx = np.asarray(idx, dtype=np.int64)
+    u = np.empty((2, level + len(P.P), len(idx)), dtype=np.uint64)
+    for m, row in enumerate(key_rows):
+        q = P.primes[row]
+        A = np.stack([ups[j][m] for j in range(len(digits))])
+        for c, kk in enumerate((key.b, key.a)):
+            B = np.stack([kk[j, row] for j in range(len(digits))])
+            u[c, m] = R.negacyclic_dot_at(A, B, q, idx)
+    t = P.t(t_exp)
+    return mod_down_cols(P, u[0], level, t), mod_down_cols(P, u[1], level, t)
+
+
+def mul_relin_at(P: Params, rk: SwitchKey, a: Ct, b: Ct, idx) -> np.ndarray:
+    """mul_relin(a, b) at coefficient indices idx: array [2][level][len(idx)]."""
+    _check_pair(a, b)
+    lv = a.level
+    idx = np.asarray(idx, dtype=np.int64)
+    d2 = np.empty((lv, P.N), dtype=np.uint64)
+    d01 = np.empty((2, lv, len(idx)), dtype=np.uint64)
+    for i, q in enumerate(P.q[:lv]):
+        d2[i] = R.negacyclic_dot(a.c[1, i], b.c[1, i], q)
+        d01[0, i] = R.negacyclic_dot_at(a.c[0, i], b.c[0, i], q, idx)
+        d01[1, i] = R.negacyclic_dot_at(np.stack([a.c[0, i], a.c[1, i]]), np.stack([b.c[1, i], b.c[0, i]]), q, idx)
+    u0, u1 = key_switch_at(P, d2, rk, lv, a.t_exp, idx)
+    q = _qcol(P.q[:lv])
+    return np.stack([(d01[0] + u0) % q, (d01[1] + u1) % q])
+
+
+def rotate_at(P: Params, gk: dict, a: Ct, step, idx) -> np.ndarray:
+    g = galois_elt(P, step)
+    primes = P.q[: a.level]
+    c0 = automorph_limbs(P, a.c[0], g, primes)
+    c1 = automorph_limbs(P, a.c[1], g, primes)
+    idx = np.asarray(idx, dtype=np.int64)
+    u0, u1 = key_switch_at(P, c1, gk[g], a.level, a.t_exp, idx)
+    q = _qcol(primes)
+    return np.stack([(c0[:, idx] + u0) % q, u1])
+
+
+def encrypt_at(P: Params, s, slots, c1, e, idx) -> np.ndarray:
+    """c0 of Algorithm 1 at coefficient indices idx: [L][len(idx)] (c1 is the input itself)."""
+    t = P.t_full
+    m = encode(P, slots, P.r)
+    me = m + t * np.asarray(e, dtype=np.int64)
+    sm = np.asarray(s, dtype=np.int64)
+    idx = np.asarray(idx, dtype=np.int64)
+    out = np.empty((P.L, len(idx)), dtype=np.uint64)
+    for i, q in enumerate(P.q):
+        s_res = np.mod(sm, np.int64(q)).astype(np.uint64)
+        c1s = R.negacyclic_dot_at(np.asarray(c1[i], dtype=np.uint64), s_res, q, idx)
+        out[i] = (np.mod(me[idx], np.int64(q)).astype(np.uint64) + np.uint64(q) - c1s) % np.uint64(q)
+    return out

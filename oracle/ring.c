@@ -15,6 +15,7 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 typedef unsigned __int128 u128;
 
@@ -68,22 +69,31 @@ void o_negacyclic_dot_at(const uint64_t* a, const uint64_t* b, int64_t n_terms, 
   }
 }
 
-/* Product with a small signed polynomial (e.g. the ternary secret): exact integer sums. */
+/* Product with a small signed polynomial (e.g. the ternary secret): exact integer sums
+ * c_k = sum_j s_j a_{k-j} (with a_{k-j} -> -a_{k-j+N} when k < j), taken over the nonzero s_j. */
 void o_negacyclic_mul_small(const uint64_t* a, const int64_t* s, uint64_t* out, int64_t N, uint64_t q) {
+  int64_t nz = 0;
+  for (int64_t j = 0; j < N; ++j) nz += s[j] != 0;
+  int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (nz ? nz : 1));
+  nz = 0;
+  for (int64_t j = 0; j < N; ++j)
+    if (s[j]) pos[nz++] = j;
 #pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < N; ++k) {
-    u128 pos = 0, neg = 0;
-    for (int64_t i = 0; i < N; ++i) {
-      int64_t sv;
-      int sign;
-      if (i <= k) { sv = s[k - i]; sign = 1; } else { sv = s[N + k - i]; sign = -1; }
-      if (sv == 0) continue;
-      u128 term = (u128)a[i] * (uint64_t)(sv < 0 ? -sv : sv);
-      if ((sv < 0) == (sign < 0)) pos += term; else neg += term;
+    u128 plus = 0, minus = 0;
+    for (int64_t t = 0; t < nz; ++t) {
+      const int64_t j = pos[t];
+      const int64_t sv = s[j];
+      const uint64_t mag = (uint64_t)(sv < 0 ? -sv : sv);
+      int neg = sv < 0;
+      uint64_t av;
+      if (j <= k) av = a[k - j]; else { av = a[N + k - j]; neg = !neg; }
+      if (neg) minus += (u128)av * mag; else plus += (u128)av * mag;
     }
-    uint64_t p = (uint64_t)(pos % q), m = (uint64_t)(neg % q);
+    uint64_t p = (uint64_t)(plus % q), m = (uint64_t)(minus % q);
     out[k] = p >= m ? p - m : p + q - m;
   }
+  free(pos);
 }
 
 /* Elementwise helpers. */
@@ -135,5 +145,19 @@ void o_intt_def(const uint64_t* ahat, uint64_t* out, int64_t N, uint64_t q, uint
       acc += (u128)ahat[j] * scratch[e];
     }
     out[i] = mulmod((uint64_t)(acc % q), n_inv, q);
+  }
+}
+
+/* Forward NTT by definition at selected output indices only. */
+void o_ntt_def_at(const uint64_t* a, const int64_t* idx, int64_t n_idx, uint64_t* out, int64_t N, uint64_t q,
+                  uint64_t psi) {
+  int logn = 0;
+  while (((int64_t)1 << logn) < N) ++logn;
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < n_idx; ++s) {
+    uint64_t w = o_powmod(psi, (uint64_t)(2 * bitrev(idx[s], logn) + 1), q);
+    uint64_t acc = 0;
+    for (int64_t i = N - 1; i >= 0; --i) acc = (mulmod(acc, w, q) + a[i]) % q;
+    out[s] = acc;
   }
 }

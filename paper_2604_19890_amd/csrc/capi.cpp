@@ -1,0 +1,403 @@
+// extern "C" entry points: argument validation, then the operation layer.
+// Every check that can fail runs on the host before any work is enqueued.
+#include <cstring>
+#include <new>
+
+#include "host_nt.hpp"
+#include "ops.hpp"
+
+#define BGV_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+bgv_status fail(bgv_ctx* c, bgv_status st, const char* msg) {
+  if (c && msg) c->err = msg;
+  return st;
+}
+
+bgv_status check_in(bgv_ctx* c, const bgv_ct* x, const char* name) {
+  if (!x || !x->d) return fail(c, BGV_E_ARG, name);
+  if (x->n < 1) return fail(c, BGV_E_ARG, "batch count must be >= 1");
+  if (x->level < 1 || x->level > c->prm.L) return fail(c, BGV_E_LEVEL, "level out of range");
+  if (x->t_exp < 1 || x->t_exp > c->prm.r) return fail(c, BGV_E_PTXT_MOD, "t_exp out of range");
+  if (x->cap_words < (int64_t)x->n * (int64_t)ct_words(c, x->level)) return fail(c, BGV_E_ARG, "input buffer too small");
+  return BGV_OK;
+}
+
+bgv_status check_out(bgv_ctx* c, bgv_ct* out, int n, int level) {
+  if (!out || !out->d) return fail(c, BGV_E_ARG, "null output");
+  if (out->cap_words < (int64_t)n * (int64_t)ct_words(c, level)) return fail(c, BGV_E_ARG, "output buffer too small");
+  return BGV_OK;
+}
+
+CtV view(const bgv_ct* x) {
+  CtV v;
+  v.d = x->d;
+  v.n = x->n;
+  v.level = x->level;
+  v.t_exp = x->t_exp;
+  return v;
+}
+
+void set_out(bgv_ct* out, int n, int level, int t_exp) {
+  out->n = n;
+  out->level = level;
+  out->t_exp = t_exp;
+}
+
+CipherP borrow(const bgv_ct* x) {
+  auto p = std::make_shared<Cipher>();
+  p->v = view(x);
+  return p;
+}
+
+// write an owned result into a caller batch
+bgv_status deliver(bgv_ctx* c, const CipherP& r, bgv_ct* out) {
+  bgv_status st = check_out(c, out, r->v.n, r->v.level);
+  if (st != BGV_OK) return st;
+  CtV o = r->v;
+  o.d = out->d;
+  op_copy(c, r->v, o);
+  set_out(out, r->v.n, r->v.level, r->v.t_exp);
+  return BGV_OK;
+}
+
+template <class F>
+bgv_status guarded(bgv_ctx* c, F f) {
+  try {
+    return f();
+  } catch (const OpError& e) {
+    if (c && c->err.empty()) c->err = "operation failed";
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    return fail(c, BGV_E_OOM, "host allocation failed");
+  }
+}
+
+#define CHECK(x)                     \
+  do {                               \
+    bgv_status _s = (x);             \
+    if (_s != BGV_OK) return _s;     \
+  } while (0)
+
+#define NEED_CTX(c) \
+  if (!(c)) return BGV_E_ARG;  \
+  (c)->err.clear();
+
+}  // namespace
+
+BGV_EXPORT bgv_status bgv_ctx_create(const bgv_params* prm, void* stream, bgv_ctx** out) {
+  if (!prm || !out) return BGV_E_ARG;
+  bgv_ctx* c = new (std::nothrow) bgv_ctx();
+  if (!c) return BGV_E_OOM;
+  bgv_status st;
+  try {
+    st = ctx_build(c, prm, (hipStream_t)stream);
+  } catch (const std::bad_alloc&) {
+    st = BGV_E_OOM;
+  }
+  if (st != BGV_OK) {
+    *out = c;  // lets the caller read bgv_last_error; bgv_ctx_destroy frees it
+    return st;
+  }
+  *out = c;
+  return BGV_OK;
+}
+
+BGV_EXPORT void bgv_ctx_destroy(bgv_ctx* c) {
+  if (!c) return;
+  ctx_free(c);
+  delete c;
+}
+
+BGV_EXPORT bgv_status bgv_set_stream(bgv_ctx* c, void* stream) {
+  NEED_CTX(c);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  c->stream = (hipStream_t)stream;
+  return BGV_OK;
+}
+
+BGV_EXPORT bgv_status bgv_ctx_info(const bgv_ctx* c, bgv_info* o) {
+  if (!c || !o) return BGV_E_ARG;
+  o->N = c->N;
+  o->log_n = c->logN;
+  o->p = c->prm.p;
+  o->r = c->prm.r;
+  o->L = c->prm.L;
+  o->K = c->prm.K;
+  o->alpha = c->alpha;
+  o->dnum = c->dnum;
+  o->slots = c->ell;
+  o->d = c->dslot;
+  o->t = c->t_full;
+  return BGV_OK;
+}
+
+BGV_EXPORT bgv_status bgv_ctx_primes(const bgv_ctx* c, uint64_t* out) {
+  if (!c || !out) return BGV_E_ARG;
+  std::memcpy(out, c->primes.data(), c->primes.size() * sizeof(uint64_t));
+  return BGV_OK;
+}
+
+BGV_EXPORT int64_t bgv_ct_words(const bgv_ctx* c, int32_t level) {
+  if (!c || level < 1) return 0;
+  return (int64_t)ct_words(c, level);
+}
+
+BGV_EXPORT bgv_status bgv_sync(bgv_ctx* c) {
+  NEED_CTX(c);
+  hipError_t e = c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    c->err = std::string("device error: ") + hipGetErrorString(e);
+    return BGV_E_DEVICE;
+  }
+  return BGV_OK;
+}
+
+BGV_EXPORT const char* bgv_last_error(const bgv_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+BGV_EXPORT bgv_status bgv_keygen(bgv_ctx* c, const int8_t* s, const uint64_t* a, const int32_t* e,
+                                 const int32_t* steps, int32_t n_steps, int32_t with_conj, bgv_keys** out) {
+  NEED_CTX(c);
+  if (!s || !a || !e || !out || n_steps < 0 || (n_steps > 0 && !steps)) return fail(c, BGV_E_ARG, "bad keygen arguments");
+  std::vector<int> gal;
+  for (int i = 0; i < n_steps; ++i) gal.push_back(galois_elt(c, steps[i]));
+  if (with_conj) gal.push_back(galois_elt(c, BGV_ROW_SWAP));
+  bgv_keys* k = new (std::nothrow) bgv_keys();
+  if (!k) return BGV_E_OOM;
+  k->ctx = c;
+  bgv_status st = guarded(c, [&] { return op_keygen(c, s, a, e, gal, k); });
+  if (st != BGV_OK) {
+    bgv_keys_destroy(k);
+    return st;
+  }
+  *out = k;
+  return BGV_OK;
+}
+
+BGV_EXPORT void bgv_keys_destroy(bgv_keys* k) {
+  if (!k) return;
+  if (k->ctx && k->ctx->stream) (void)hipStreamSynchronize(k->ctx->stream);
+  if (k->relin) (void)hipFree(k->relin);
+  for (auto& kv : k->galois) (void)hipFree(kv.second);
+  delete k;
+}
+
+BGV_EXPORT int64_t bgv_keys_bytes(const bgv_keys* k) { return k ? k->bytes : 0; }
+
+BGV_EXPORT bgv_status bgv_encrypt(bgv_ctx* c, const int8_t* s, const uint64_t* slots, const uint64_t* c1,
+                                  const int32_t* e, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!s || !slots || !c1 || !e || !out || out->n < 1) return fail(c, BGV_E_ARG, "bad encrypt arguments");
+  CHECK(check_out(c, out, out->n, c->prm.L));
+  set_out(out, out->n, c->prm.L, c->prm.r);
+  return guarded(c, [&] { return op_encrypt(c, s, slots, c1, e, view(out)); });
+}
+
+BGV_EXPORT bgv_status bgv_decrypt(bgv_ctx* c, const int8_t* s, const bgv_ct* in, uint64_t* slots, uint8_t* nonconst) {
+  NEED_CTX(c);
+  CHECK(check_in(c, in, "null input"));
+  if (!s || !slots) return fail(c, BGV_E_ARG, "bad decrypt arguments");
+  return guarded(c, [&] { return op_decrypt(c, s, view(in), slots, nonconst); });
+}
+
+static bgv_status binary_check(bgv_ctx* c, const bgv_ct* a, const bgv_ct* b) {
+  CHECK(check_in(c, a, "null a"));
+  CHECK(check_in(c, b, "null b"));
+  if (a->level != b->level) return fail(c, BGV_E_LEVEL, "operands at different levels");
+  if (a->t_exp != b->t_exp) return fail(c, BGV_E_PTXT_MOD, "operands with different plaintext moduli");
+  if (b->n != a->n && b->n != 1) return fail(c, BGV_E_ARG, "batch sizes differ");
+  return BGV_OK;
+}
+
+static bgv_status addsub(bgv_ctx* c, const bgv_ct* a, const bgv_ct* b, bgv_ct* out, int op) {
+  NEED_CTX(c);
+  CHECK(binary_check(c, a, b));
+  CHECK(check_out(c, out, a->n, a->level));
+  bgv_ct A = *a, B = *b;
+  bgv_status st = guarded(c, [&] {
+    CtV o = view(&A);
+    o.d = out->d;
+    op_add_sub(c, view(&A), view(&B), o, op);
+    return BGV_OK;
+  });
+  if (st == BGV_OK) set_out(out, A.n, A.level, A.t_exp);
+  return st;
+}
+
+BGV_EXPORT bgv_status bgv_add(bgv_ctx* c, const bgv_ct* a, const bgv_ct* b, bgv_ct* out) { return addsub(c, a, b, out, 0); }
+BGV_EXPORT bgv_status bgv_sub(bgv_ctx* c, const bgv_ct* a, const bgv_ct* b, bgv_ct* out) { return addsub(c, a, b, out, 1); }
+
+template <class F>
+static bgv_status unary(bgv_ctx* c, const bgv_ct* a, bgv_ct* out, int out_level, int out_t, F f) {
+  NEED_CTX(c);
+  CHECK(check_in(c, a, "null input"));
+  CHECK(check_out(c, out, a->n, out_level));
+  bgv_ct A = *a;
+  bgv_status st = guarded(c, [&] {
+    CtV o = view(&A);
+    o.d = out->d;
+    o.level = out_level;
+    o.t_exp = out_t;
+    f(view(&A), o);
+    return BGV_OK;
+  });
+  if (st == BGV_OK) set_out(out, A.n, out_level, out_t);
+  return st;
+}
+
+BGV_EXPORT bgv_status bgv_negate(bgv_ctx* c, const bgv_ct* a, bgv_ct* out) {
+  if (!a) return BGV_E_ARG;
+  return unary(c, a, out, a->level, a->t_exp, [&](const CtV& x, const CtV& o) { op_negate(c, x, o); });
+}
+
+BGV_EXPORT bgv_status bgv_mul_scalar(bgv_ctx* c, const bgv_ct* a, int64_t k, bgv_ct* out) {
+  if (!a) return BGV_E_ARG;
+  return unary(c, a, out, a->level, a->t_exp, [&](const CtV& x, const CtV& o) { op_mul_scalar(c, x, k, o); });
+}
+
+BGV_EXPORT bgv_status bgv_add_const(bgv_ctx* c, const bgv_ct* a, int64_t k, bgv_ct* out) {
+  if (!a) return BGV_E_ARG;
+  return unary(c, a, out, a->level, a->t_exp, [&](const CtV& x, const CtV& o) { op_add_const(c, x, k, o); });
+}
+
+BGV_EXPORT bgv_status bgv_divide_by_p(bgv_ctx* c, const bgv_ct* a, bgv_ct* out) {
+  if (!a) return BGV_E_ARG;
+  if (a->t_exp < 2) return fail(c, BGV_E_PTXT_MOD, "DivideByP needs t = p^k with k >= 2");
+  return unary(c, a, out, a->level, a->t_exp - 1, [&](const CtV& x, const CtV& o) { op_divide_by_p(c, x, o); });
+}
+
+BGV_EXPORT bgv_status bgv_set_t_exp(bgv_ctx* c, bgv_ct* ct, int32_t t_exp) {
+  NEED_CTX(c);
+  if (!ct) return BGV_E_ARG;
+  if (t_exp < 1 || t_exp > c->prm.r) return fail(c, BGV_E_PTXT_MOD, "t_exp out of range");
+  ct->t_exp = t_exp;
+  return BGV_OK;
+}
+
+BGV_EXPORT bgv_status bgv_mul_relin(bgv_ctx* c, const bgv_keys* k, const bgv_ct* a, const bgv_ct* b, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k || !k->relin) return fail(c, BGV_E_NOKEY, "no relinearisation key");
+  CHECK(binary_check(c, a, b));
+  CHECK(check_out(c, out, a->n, a->level));
+  bgv_ct A = *a, B = *b;
+  bgv_status st = guarded(c, [&] {
+    CtV o = view(&A);
+    o.d = out->d;
+    op_mul_relin(c, k, view(&A), view(&B), o);
+    return BGV_OK;
+  });
+  if (st == BGV_OK) set_out(out, A.n, A.level, A.t_exp);
+  return st;
+}
+
+BGV_EXPORT bgv_status bgv_rotate(bgv_ctx* c, const bgv_keys* k, const bgv_ct* in, int32_t step, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k) return fail(c, BGV_E_NOKEY, "no keys");
+  CHECK(check_in(c, in, "null input"));
+  const int g = galois_elt(c, step);
+  if (!k->galois.count(g)) return fail(c, BGV_E_NOKEY, "no Galois key for this rotation");
+  return unary(c, in, out, in->level, in->t_exp, [&](const CtV& x, const CtV& o) { op_rotate(c, k, x, g, o); });
+}
+
+BGV_EXPORT bgv_status bgv_mod_switch(bgv_ctx* c, const bgv_ct* in, bgv_ct* out) {
+  NEED_CTX(c);
+  CHECK(check_in(c, in, "null input"));
+  if (in->level < 2) return fail(c, BGV_E_LEVEL, "no prime left to drop");
+  return unary(c, in, out, in->level - 1, in->t_exp, [&](const CtV& x, const CtV& o) { op_mod_switch(c, x, o); });
+}
+
+BGV_EXPORT bgv_status bgv_mod_switch_to(bgv_ctx* c, const bgv_ct* in, int32_t level, bgv_ct* out) {
+  NEED_CTX(c);
+  CHECK(check_in(c, in, "null input"));
+  if (level < 1 || level > in->level) return fail(c, BGV_E_LEVEL, "target level out of range");
+  return unary(c, in, out, level, in->t_exp, [&](const CtV& x, const CtV& o) { op_mod_switch_to(c, x, level, o); });
+}
+
+BGV_EXPORT bgv_status bgv_eval_poly(bgv_ctx* c, const bgv_keys* k, const bgv_ct* in, const int64_t* coeffs,
+                                    int32_t degree, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k || !coeffs || degree < 1 || !out) return fail(c, BGV_E_ARG, "bad eval_poly arguments");
+  CHECK(check_in(c, in, "null input"));
+  std::vector<int64_t> cf(coeffs, coeffs + degree + 1);
+  return guarded(c, [&] {
+    CipherP r = ev_eval_poly(c, k, borrow(in), cf);
+    return deliver(c, r, out);
+  });
+}
+
+BGV_EXPORT bgv_status bgv_space_reduce(bgv_ctx* c, const bgv_keys* k, const bgv_ct* in, bgv_ct* digits) {
+  NEED_CTX(c);
+  if (!k || !digits) return fail(c, BGV_E_ARG, "bad space_reduce arguments");
+  CHECK(check_in(c, in, "null input"));
+  if (in->t_exp != 2) return fail(c, BGV_E_UNSUPPORTED, "the reduction is built for t = p^2");
+  return guarded(c, [&] {
+    std::vector<CipherP> d = ev_space_reduce(c, k, borrow(in));
+    for (size_t i = 0; i < d.size(); ++i) CHECK(check_out(c, &digits[i], d[i]->v.n, d[i]->v.level));
+    for (size_t i = 0; i < d.size(); ++i) CHECK(deliver(c, d[i], &digits[i]));
+    return BGV_OK;
+  });
+}
+
+BGV_EXPORT bgv_status bgv_compare(bgv_ctx* c, const bgv_keys* k, const bgv_ct* digits, int32_t r, int32_t op,
+                                  bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k || !digits || r < 1 || r > c->prm.r || (op != BGV_OP_LT && op != BGV_OP_EQ))
+    return fail(c, BGV_E_ARG, "bad compare arguments");
+  std::vector<CipherP> d;
+  for (int i = 0; i < r; ++i) {
+    CHECK(check_in(c, &digits[i], "null digit"));
+    if (digits[i].t_exp != 1) return fail(c, BGV_E_PTXT_MOD, "digits must have t = p");
+    if (digits[i].n != digits[0].n) return fail(c, BGV_E_ARG, "digit batches differ");
+    d.push_back(borrow(&digits[i]));
+  }
+  return guarded(c, [&] { return deliver(c, ev_compare(c, k, d, op), out); });
+}
+
+BGV_EXPORT bgv_status bgv_space_raise(bgv_ctx* c, const bgv_keys* k, const bgv_ct* in, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k) return fail(c, BGV_E_ARG, "no keys");
+  CHECK(check_in(c, in, "null input"));
+  if (in->t_exp != 1) return fail(c, BGV_E_PTXT_MOD, "raising starts from t = p");
+  return guarded(c, [&] { return deliver(c, ev_space_raise(c, k, borrow(in)), out); });
+}
+
+BGV_EXPORT bgv_status bgv_less_than(bgv_ctx* c, const bgv_keys* k, const bgv_ct* x, const bgv_ct* y, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k) return fail(c, BGV_E_ARG, "no keys");
+  CHECK(check_in(c, x, "null x"));
+  if (y) CHECK(binary_check(c, x, y));
+  if (x->t_exp != 2) return fail(c, BGV_E_UNSUPPORTED, "the reduction is built for t = p^2");
+  return guarded(c, [&] {
+    CipherP d = borrow(x);
+    if (y) {
+      CipherP t = new_cipher(c, x->n, x->level, x->t_exp);
+      op_add_sub(c, view(x), view(y), t->v, 1);
+      d = t;
+    }
+    std::vector<CipherP> dg = ev_space_reduce(c, k, d);
+    return deliver(c, ev_space_raise(c, k, ev_compare(c, k, dg, BGV_OP_LT)), out);
+  });
+}
+
+BGV_EXPORT bgv_status bgv_rotate_sum(bgv_ctx* c, const bgv_keys* k, const bgv_ct* in, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k) return fail(c, BGV_E_NOKEY, "no keys");
+  CHECK(check_in(c, in, "null input"));
+  for (int i = 1; i < c->ell / 2; i *= 2)
+    if (!k->galois.count(galois_elt(c, i))) return fail(c, BGV_E_NOKEY, "missing a power-of-two rotation key");
+  if (!k->galois.count(galois_elt(c, BGV_ROW_SWAP))) return fail(c, BGV_E_NOKEY, "missing the row-swap key");
+  return guarded(c, [&] { return deliver(c, ev_rotate_sum(c, k, borrow(in)), out); });
+}
+
+BGV_EXPORT bgv_status bgv_ntt(bgv_ctx* c, uint64_t* d, int64_t cap_words, int32_t n_polys, int32_t level,
+                              int32_t inverse) {
+  NEED_CTX(c);
+  if (!d || n_polys < 1 || level < 1 || level > c->Ltot) return fail(c, BGV_E_ARG, "bad ntt arguments");
+  if (cap_words < (int64_t)n_polys * level * c->N) return fail(c, BGV_E_ARG, "buffer too small");
+  return guarded(c, [&] {
+    op_ntt(c, d, n_polys, level, inverse != 0);
+    return BGV_OK;
+  });
+}

@@ -1,0 +1,302 @@
+// Context creation: prime chain, NTT tables, base-conversion constants, slot
+// structure and the coefficient tables of the space-switching polynomials.
+#include "ctx.hpp"
+
+#include <cstring>
+#include <numeric>
+
+#include "host_nt.hpp"
+#include "ops.hpp"
+
+using namespace hnt;
+
+bool hip_ok(bgv_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+
+void* DevPool::get(size_t bytes) {
+  const size_t gran = (size_t)1 << 20;
+  bytes = (bytes + gran - 1) / gran * gran;
+  auto it = free_.lower_bound(bytes);
+  // reuse a cached block of the same size class (up to 2x larger)
+  if (it != free_.end() && it->first <= 2 * bytes) {
+    void* p = it->second;
+    free_.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    // give back the cache and retry once
+    for (auto& kv : free_) {
+      (void)hipFree(kv.second);
+      for (auto a = all_.begin(); a != all_.end(); ++a)
+        if (a->first == kv.second) {
+          held -= a->second;
+          all_.erase(a);
+          break;
+        }
+    }
+    free_.clear();
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  }
+  all_.push_back({p, bytes});
+  held += bytes;
+  return p;
+}
+
+void DevPool::put(void* p, size_t bytes) {
+  if (!p) return;
+  for (auto& a : all_)
+    if (a.first == p) {
+      free_.insert({a.second, p});
+      return;
+    }
+  (void)bytes;
+}
+
+void DevPool::release() {
+  for (auto& a : all_) (void)hipFree(a.first);
+  all_.clear();
+  free_.clear();
+  held = 0;
+}
+
+namespace {
+
+// Solve V c = y over Z_m (m a prime power) by Gaussian elimination, pivots units.
+bool solve_mod(std::vector<std::vector<int64_t>> A, std::vector<int64_t> y, int64_t m, int64_t p,
+               std::vector<int64_t>& out) {
+  const int n = (int)y.size();
+  for (int col = 0; col < n; ++col) {
+    int piv = -1;
+    for (int r = col; r < n; ++r)
+      if (A[r][col] % p != 0) {
+        piv = r;
+        break;
+      }
+    if (piv < 0) return false;
+    std::swap(A[piv], A[col]);
+    std::swap(y[piv], y[col]);
+    const int64_t inv = (int64_t)invmod((uint64_t)((A[col][col] % m + m) % m), (uint64_t)m);
+    for (int k = col; k < n; ++k) A[col][k] = (int64_t)((__int128)A[col][k] * inv % m);
+    y[col] = (int64_t)((__int128)y[col] * inv % m);
+    for (int r = 0; r < n; ++r) {
+      if (r == col || A[r][col] == 0) continue;
+      const int64_t f = A[r][col];
+      for (int k = col; k < n; ++k) A[r][k] = ((A[r][k] - (int64_t)((__int128)f * A[col][k] % m)) % m + m) % m;
+      y[r] = ((y[r] - (int64_t)((__int128)f * y[col] % m)) % m + m) % m;
+    }
+  }
+  out = y;
+  return true;
+}
+
+// unique polynomial of degree < p through (z, f(z)) for every z in Z_p
+bool interpolate_fp(int64_t p, const std::vector<int64_t>& zs, const std::vector<int64_t>& vals,
+                    std::vector<int64_t>& coeffs) {
+  const int n = (int)zs.size();
+  std::vector<std::vector<int64_t>> V(n, std::vector<int64_t>(n));
+  for (int i = 0; i < n; ++i) {
+    int64_t z = ((zs[i] % p) + p) % p, pw = 1;
+    for (int k = 0; k < n; ++k) {
+      V[i][k] = pw;
+      pw = pw * z % p;
+    }
+  }
+  std::vector<int64_t> y(n);
+  for (int i = 0; i < n; ++i) y[i] = ((vals[i] % p) + p) % p;
+  return solve_mod(V, y, p, p, coeffs);
+}
+
+}  // namespace
+
+// F_LT: the interpolant over Z_p of [z < 0] on the balanced representatives.
+// G_{p,2} = x^p + p H(x) with H the interpolant of (z - z^p)/p on balanced z:
+// then G(z) = z mod p^2 and G'(z) = 0 mod p for every balanced z, so
+// G(z0 + p z1) = z0 mod p^2 (Lemma 3 with e = 2, degree p = (e-1)(p-1)+1).
+static bool build_poly_tables(bgv_ctx* c) {
+  const int64_t p = c->prm.p;
+  std::vector<int64_t> zs, lt, phi;
+  for (int64_t z = -(p - 1) / 2; z <= (p - 1) / 2; ++z) {
+    zs.push_back(z);
+    lt.push_back(z < 0 ? 1 : 0);
+    // (z - z^p)/p mod p computed with exact 128-bit arithmetic on z^p mod p^2
+    const int64_t t2 = p * p;
+    int64_t zz = ((z % t2) + t2) % t2, pw = 1;
+    for (int64_t k = 0; k < p; ++k) pw = (int64_t)((__int128)pw * zz % t2);
+    int64_t diff = ((zz - pw) % t2 + t2) % t2;  // divisible by p (Fermat)
+    phi.push_back((diff / p) % p);
+  }
+  if (!interpolate_fp(p, zs, lt, c->flt)) return false;
+  std::vector<int64_t> H;
+  if (!interpolate_fp(p, zs, phi, H)) return false;
+  const int64_t t2 = p * p;
+  c->g2.assign(p + 1, 0);
+  for (int64_t k = 0; k < p; ++k) c->g2[k] = (p * H[k]) % t2;
+  c->g2[p] = (c->g2[p] + 1) % t2;
+  return true;
+}
+
+static bool build_slots(bgv_ctx* c) {
+  const int64_t p = c->prm.p;
+  int v = 0;
+  for (int64_t x = p - 1; x % 2 == 0; x /= 2) ++v;
+  c->ell = 1 << (v - 1);
+  if (2 * c->N < (1 << v)) return false;
+  c->dslot = c->N / c->ell;
+  int64_t zb = 0;
+  for (int64_t z = 2; z < p; ++z)
+    if ((int64_t)powmod((uint64_t)z, (uint64_t)c->ell, (uint64_t)p) == p - 1) {
+      zb = z;
+      break;
+    }
+  if (!zb) return false;
+  int64_t e = 1;
+  for (int i = 1; i < c->prm.r; ++i) e *= p;
+  c->zeta = (int64_t)powmod((uint64_t)zb, (uint64_t)e, (uint64_t)c->t_full);
+  const int64_t two_l = 2 * c->ell;
+  c->slot_exp.clear();
+  for (int rho = 0; rho < 2; ++rho)
+    for (int k = 0; k < c->ell / 2; ++k) {
+      int64_t ex = (int64_t)powmod(5, (uint64_t)k, (uint64_t)two_l);
+      c->slot_exp.push_back(rho == 0 ? ex : (two_l - ex) % two_l);
+    }
+  return true;
+}
+
+template <class T>
+static bool upload(bgv_ctx* c, T** dst, const std::vector<T>& v) {
+  if (!hip_ok(c, hipMalloc((void**)dst, v.size() * sizeof(T)), "hipMalloc table")) return false;
+  return hip_ok(c, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy table");
+}
+
+bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream) {
+  c->prm = *prm;
+  c->stream = stream;
+  if (prm->log_n < 4 || prm->log_n > 16) { c->err = "log_n must be in [4, 16]"; return BGV_E_PARAM; }
+  if (prm->p < 5 || prm->p % 4 != 1 || prm->p > 65521) { c->err = "p must be a prime = 1 mod 4 below 2^16"; return BGV_E_PARAM; }
+  if (!is_prime((uint64_t)prm->p)) { c->err = "p is not prime"; return BGV_E_PARAM; }
+  if (prm->r < 1 || prm->r > 4) { c->err = "r must be in [1, 4]"; return BGV_E_PARAM; }
+  if (prm->L < 1 || prm->K < 1 || prm->K > 8 || prm->L + prm->K > 64) { c->err = "need L >= 1, 1 <= K <= 8, L + K <= 64"; return BGV_E_PARAM; }
+  c->logN = prm->log_n;
+  c->N = 1 << prm->log_n;
+  c->alpha = prm->K;
+  c->dnum = (prm->L + c->alpha - 1) / c->alpha;
+  c->Ltot = prm->L + prm->K;
+  c->tpow.assign(prm->r + 1, 1);
+  for (int e = 1; e <= prm->r; ++e) c->tpow[e] = c->tpow[e - 1] * prm->p;
+  c->t_full = c->tpow[prm->r];
+  if (c->t_full >= ((int64_t)1 << 31)) { c->err = "p^r must be below 2^31"; return BGV_E_PARAM; }
+  if (!build_slots(c)) { c->err = "ring too small for this p"; return BGV_E_PARAM; }
+  const uint64_t M = (uint64_t)(2 * c->N) / gcd((uint64_t)(2 * c->N), (uint64_t)c->t_full) * (uint64_t)c->t_full;
+  if (!prime_chain(M, c->Ltot, c->primes)) { c->err = "not enough 50-bit primes = 1 mod lcm(2N, p^r)"; return BGV_E_PARAM; }
+  if (!build_poly_tables(c)) { c->err = "polynomial table construction failed"; return BGV_E_PARAM; }
+
+  const int N = c->N, Lt = c->Ltot, L = prm->L, K = prm->K;
+  std::vector<PrimeD> pd(Lt);
+  std::vector<double> tw((size_t)Lt * N), itw((size_t)Lt * N);
+  c->psi.resize(Lt);
+  std::vector<uint64_t> pw(N);
+  for (int m = 0; m < Lt; ++m) {
+    const uint64_t q = c->primes[m];
+    const uint64_t psi = min_root_2n(q, (uint64_t)N);
+    c->psi[m] = psi;
+    pd[m].q = (double)q;
+    pd[m].qinv = 1.0 / (double)q;
+    pd[m].ninv = (double)invmod((uint64_t)N, q);
+    pd[m].pad = 0.0;
+    const uint64_t ipsi = invmod(psi, q);
+    pw[0] = 1;
+    for (int k = 1; k < N; ++k) pw[k] = mulmod(pw[k - 1], psi, q);
+    for (int k = 0; k < N; ++k) tw[(size_t)m * N + k] = (double)pw[bitrev((uint32_t)k, c->logN)];
+    pw[0] = 1;
+    for (int k = 1; k < N; ++k) pw[k] = mulmod(pw[k - 1], ipsi, q);
+    for (int k = 0; k < N; ++k) itw[(size_t)m * N + k] = (double)pw[bitrev((uint32_t)k, c->logN)];
+  }
+
+  // ModUp tables
+  const int A = c->alpha;
+  std::vector<double> mu((size_t)(L + 1) * c->dnum * A * (1 + Lt), 0.0);
+  for (int lv = 1; lv <= L; ++lv) {
+    for (int j = 0; j * A < lv; ++j) {
+      const int lo = j * A, hi = std::min(lo + A, lv);
+      double* inv = &mu[c->modup_inv_off(lv, j)];
+      double* basis = &mu[c->modup_basis_off(lv, j)];
+      for (int a = 0; a < hi - lo; ++a) {
+        const int i = lo + a;
+        const uint64_t qi = c->primes[i];
+        uint64_t qh_mod_qi = 1;
+        for (int b = lo; b < hi; ++b)
+          if (b != i) qh_mod_qi = mulmod(qh_mod_qi, c->primes[b] % qi, qi);
+        inv[a] = (double)invmod(qh_mod_qi, qi);
+        for (int m = 0; m < Lt; ++m) {
+          const uint64_t pm = c->primes[m];
+          uint64_t v = 1;
+          for (int b = lo; b < hi; ++b)
+            if (b != i) v = mulmod(v, c->primes[b] % pm, pm);
+          basis[(size_t)a * Lt + m] = (double)v;
+        }
+      }
+    }
+  }
+  // ModDown tables: phat_inv [K], phat_mod [K][L], pinv_q [L], pmod_q [L]
+  std::vector<double> md((size_t)K + (size_t)K * L + 2 * (size_t)L, 0.0);
+  for (int k = 0; k < K; ++k) {
+    const uint64_t pk = c->primes[L + k];
+    uint64_t v = 1;
+    for (int k2 = 0; k2 < K; ++k2)
+      if (k2 != k) v = mulmod(v, c->primes[L + k2] % pk, pk);
+    md[k] = (double)invmod(v, pk);
+    for (int i = 0; i < L; ++i) {
+      const uint64_t qi = c->primes[i];
+      uint64_t w = 1;
+      for (int k2 = 0; k2 < K; ++k2)
+        if (k2 != k) w = mulmod(w, c->primes[L + k2] % qi, qi);
+      md[K + (size_t)k * L + i] = (double)w;
+    }
+  }
+  for (int i = 0; i < L; ++i) {
+    const uint64_t qi = c->primes[i];
+    uint64_t P = 1;
+    for (int k = 0; k < K; ++k) P = mulmod(P, c->primes[L + k] % qi, qi);
+    md[K + (size_t)K * L + i] = (double)invmod(P, qi);
+    md[K + (size_t)K * L + L + i] = (double)P;
+  }
+  // modulus switching: msw[top][i] = q_top^-1 mod q_i
+  std::vector<double> msw((size_t)L * L, 0.0);
+  for (int top = 0; top < L; ++top)
+    for (int i = 0; i < L; ++i)
+      if (i != top) msw[(size_t)top * L + i] = (double)invmod(c->primes[top] % c->primes[i], c->primes[i]);
+  // t constants [r+1][2][Lt] and the host copy of t^-1
+  std::vector<double> tc((size_t)(prm->r + 1) * 2 * Lt);
+  c->h_tinv.assign((size_t)(prm->r + 1) * Lt, 0.0);
+  c->h_tmod.assign((size_t)(prm->r + 1) * Lt, 0.0);
+  for (int e = 0; e <= prm->r; ++e)
+    for (int m = 0; m < Lt; ++m) {
+      const uint64_t q = c->primes[m];
+      const uint64_t tm = (uint64_t)c->tpow[e] % q;
+      const double ti = (double)invmod(tm, q);
+      tc[((size_t)e * 2 + 0) * Lt + m] = ti;
+      tc[((size_t)e * 2 + 1) * Lt + m] = (double)tm;
+      c->h_tinv[(size_t)e * Lt + m] = ti;
+      c->h_tmod[(size_t)e * Lt + m] = (double)tm;
+    }
+
+  if (!upload(c, &c->d_prime, pd) || !upload(c, &c->d_tw, tw) || !upload(c, &c->d_itw, itw) ||
+      !upload(c, &c->d_modup, mu) || !upload(c, &c->d_moddown, md) || !upload(c, &c->d_msw, msw) ||
+      !upload(c, &c->d_tconst, tc))
+    return BGV_E_DEVICE;
+  if (!build_encoder(c)) { c->err = "slot encoder construction failed"; return BGV_E_PARAM; }
+  return BGV_OK;
+}
+
+void ctx_free(bgv_ctx* c) {
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  c->pool.release();
+  void* ptrs[] = {c->d_prime, c->d_tw, c->d_itw, c->d_modup, c->d_moddown, c->d_msw, c->d_tconst};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}

@@ -1,0 +1,129 @@
+// Internal state of a context and of a key set; launcher declarations.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/bgv.h"
+#include "common.hpp"
+
+// Caching device allocator.  A context runs on one stream, so a buffer returned
+// to the cache may be handed out again at once: later work on the same stream
+// runs after every earlier use of it.
+struct DevPool {
+  std::multimap<size_t, void*> free_;
+  std::vector<std::pair<void*, size_t>> all_;
+  size_t held = 0;
+  void* get(size_t bytes);
+  void put(void* p, size_t bytes);
+  void release();
+};
+
+struct bgv_ctx {
+  bgv_params prm;
+  int N = 0, logN = 0, ell = 0, dslot = 0, alpha = 0, dnum = 0, Ltot = 0;
+  int64_t t_full = 0;
+  std::vector<uint64_t> primes;  // q_0..q_{L-1}, then the K special primes
+  std::vector<uint64_t> psi;     // NTT root per prime
+  std::vector<int64_t> tpow;     // p^e for e = 0..r
+  hipStream_t stream = nullptr;
+  std::string err;
+  DevPool pool;
+
+  // device tables
+  PrimeD* d_prime = nullptr;  // [Ltot]
+  double* d_tw = nullptr;     // [Ltot][N]  psi^brv(k)
+  double* d_itw = nullptr;    // [Ltot][N]  psi^-brv(k)
+  // ModUp: for level l in [1, L] and digit j: inverse table [alpha] and
+  // basis table [alpha][Ltot] (Qhat_i mod prime m), at offset modup_off(l, j)
+  double* d_modup = nullptr;
+  // ModDown: phat_inv [K], phat_mod [K][L], pinv_q [L]
+  double* d_moddown = nullptr;
+  // modulus switching: qinv_tab [L][L] (q_top^-1 mod q_i at [top][i])
+  double* d_msw = nullptr;
+  // t-dependent scalars: tinv_tab [r+1][Ltot] (t^-1 mod prime), tmod_tab [r+1][Ltot]
+  double* d_tconst = nullptr;
+
+  // host copies of scalar tables used to build kernel arguments
+  std::vector<double> h_tinv, h_tmod;  // [r+1][Ltot]
+
+  // polynomial tables (ascending coefficients)
+  std::vector<int64_t> g2;    // G_{p,2} mod p^2
+  std::vector<int64_t> flt;   // F_LT mod p
+  // slot structure
+  std::vector<int64_t> slot_exp;  // exponent e_j of slot j (root zeta^e_j)
+  int64_t zeta = 0;
+  std::vector<int64_t> encoder;   // [ell][ell] inverse Vandermonde of the slot roots mod p^r
+
+  size_t modup_inv_off(int level, int j) const {
+    return ((size_t)(level * dnum + j)) * (size_t)alpha * (1 + Ltot);
+  }
+  size_t modup_basis_off(int level, int j) const { return modup_inv_off(level, j) + alpha; }
+};
+
+struct bgv_keys {
+  bgv_ctx* ctx = nullptr;
+  // each key: [dnum][2][Ltot][N] uint64 in evaluation form; component 0 = b, 1 = a
+  uint64_t* relin = nullptr;
+  std::map<int, uint64_t*> galois;  // Galois element g -> key
+  int64_t bytes = 0;
+};
+
+// ------------------------------------------------------------------ launchers
+namespace lk {
+// NTT over n_limbs limbs of length N at d (limb l uses the prime given by lm).
+void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse);
+
+// out = a (op) b elementwise per limb; op 0 add, 1 sub; b_bcast: b has one ciphertext
+void add_sub(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n, int level, int op,
+             bool b_bcast);
+void negate(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level);
+// out = a * s_i per limb (s per prime given as a double table of size level)
+void mul_scalar(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);
+// add s_i to every word of component 0
+void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);
+// tensor: d [n][3][level][N] from a, b [n][2][level][N]
+void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, int n, int level, bool b_bcast);
+// ModUp of the coefficient-form limbs x [n][level][N] -> y [n][dnum'][level+K][N] (coefficient form,
+// own-digit rows left untouched)
+void mod_up(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level);
+// copy the evaluation-form own-digit rows of x (ciphertext b at x + b*x_ct_stride, rows [level][N]) into y
+void mod_up_copy_own(bgv_ctx* c, const uint64_t* x_eval, int64_t x_ct_stride, uint64_t* y, int n, int level);
+// u [n][2][level+K][N] = sum_j y[n][j][m] * key[j][c][row(m)]
+void key_inner(bgv_ctx* c, const uint64_t* y, const uint64_t* key, uint64_t* u, int n, int level);
+// delta rows: from the coefficient-form special limbs up [n*2][K][N]
+// write dl [n][2][level][N] (coefficient form) = FBC_{P->Q}([u_P t^-1]_P)
+void mod_down_delta(bgv_ctx* c, const uint64_t* u_coeff, uint64_t* dl, int n, int level, int t_exp);
+// out[n][2][level] = add[n][c][i] + (u[n][c][i] - t dl[n][c][i]) * P^-1   (evaluation form)
+// add points at [n][3][level][N] tensor output (components 0, 1) or [n][2][level][N] with add_stride
+void mod_down_final(bgv_ctx* c, const uint64_t* u, const uint64_t* dl, const uint64_t* addsrc,
+                    int64_t add_ct_stride, uint64_t* out, int n, int level, int t_exp);
+// single drop: w rows from the coefficient-form top limbs top [n][2][N]:
+// wrow [n][2][level-1][N] = centered([top t^-1]_{q_top}) mod q_i  (coefficient form)
+void msw_w(bgv_ctx* c, const uint64_t* top, uint64_t* wrow, int n, int level, int t_exp);
+// out [n][2][level-1] = (a_i - t w_i) q_top^-1 (evaluation form)
+void msw_final(bgv_ctx* c, const uint64_t* a, const uint64_t* w, uint64_t* out, int n, int level, int t_exp);
+// multi-drop in coefficient form: x [n][2][level][N] -> y [n][2][to][N]
+void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int to, int t_exp);
+// copy limb rows: y[b][c][i] = x[b][c][i] for i < to_level (x has from_level rows)
+void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from_level, int to_level, int comps);
+// automorphism in evaluation form on n*2 polys of `level` limbs
+void automorph(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n_polys, int level, int g);
+// signed small integers (int64 [N] per poly) -> residues [n_polys][rows][N] under primes given by lm
+void from_signed(bgv_ctx* c, const int64_t* v, uint64_t* y, int n_polys, int rows, LimbMap lm);
+// elementwise: out = a*b (+ sign * c*d) style helpers for encryption / keys
+void mul_pointwise(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n_limbs, LimbMap lm,
+                   int64_t a_stride_limbs_bcast);
+// decrypt phase: v[n][level] = c0 + c1 * S (S [level][N] evaluation form of s)
+void phase(bgv_ctx* c, const uint64_t* ct, const uint64_t* S, uint64_t* v, int n, int level);
+// encryption: c0 = M - C1*S  with M [n][L][N], C1 [n][L][N], S [L][N]; writes ct [n][2][L][N]
+void enc_combine(bgv_ctx* c, const uint64_t* M, const uint64_t* C1, const uint64_t* S, uint64_t* ct, int n);
+// key: b = -A*S + t*E + [m in digit j] (P mod q_m) S'
+void key_combine(bgv_ctx* c, const uint64_t* A, const uint64_t* S, const uint64_t* E, const uint64_t* Sp,
+                 uint64_t* key, int dnum);
+}  // namespace lk
+
+bool hip_ok(bgv_ctx* c, hipError_t e, const char* what);

@@ -1,0 +1,533 @@
+// Elementwise and base-conversion kernels of the BGV hot path (gfx950).
+//
+// Layout of a ciphertext batch: [n][2][level][N] uint64 residues; limb i of a
+// component uses prime q_i.  Evaluation-form kernels work word by word; the
+// base-conversion kernels (ModUp, ModDown, modulus switching) work on
+// coefficient-form limbs produced by the INTT, one coefficient per thread.
+#include "ctx.hpp"
+
+namespace {
+
+constexpr int BS = 256;
+
+struct Tab64 {
+  double v[64];
+};
+
+inline dim3 grid_for(int N, int y, int z = 1) { return dim3(N >= BS ? N / BS : 1, y, z); }
+inline int block_for(int N) { return N >= BS ? BS : N; }
+
+__global__ void k_add_sub(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b, uint64_t* __restrict__ out,
+                          int level, int N, int op, int b_bcast, const PrimeD* __restrict__ pc) {
+  const int limb = blockIdx.y;
+  const int pi = limb % level;
+  const double q = pc[pi].q;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t ia = (size_t)limb * N + n0;
+  const size_t ib = (size_t)(b_bcast ? limb % (2 * level) : limb) * N + n0;
+  double x = u2d(a[ia]), y = u2d(b[ib]);
+  double r = op == 0 ? x + y : x - y;
+  r = r >= q ? r - q : r;
+  r = r < 0.0 ? r + q : r;
+  out[ia] = d2u(r);
+}
+
+__global__ void k_negate(const uint64_t* __restrict__ a, uint64_t* __restrict__ out, int level, int N,
+                         const PrimeD* __restrict__ pc) {
+  const int limb = blockIdx.y;
+  const double q = pc[limb % level].q;
+  const size_t i = (size_t)limb * N + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double x = u2d(a[i]);
+  out[i] = d2u(x == 0.0 ? 0.0 : q - x);
+}
+
+__global__ void k_mul_scalar(const uint64_t* __restrict__ a, uint64_t* __restrict__ out, int level, int N, Tab64 s,
+                             const PrimeD* __restrict__ pc) {
+  const int limb = blockIdx.y;
+  const int pi = limb % level;
+  const double q = pc[pi].q, qinv = pc[pi].qinv;
+  const size_t i = (size_t)limb * N + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  out[i] = d2u(canon(mul_lazy(u2d(a[i]), s.v[pi], q, qinv), q));
+}
+
+__global__ void k_add_const(const uint64_t* __restrict__ a, uint64_t* __restrict__ out, int level, int N, Tab64 s,
+                            const PrimeD* __restrict__ pc) {
+  const int limb = blockIdx.y;
+  const int pi = limb % level;
+  const int comp = (limb / level) & 1;
+  const double q = pc[pi].q;
+  const size_t i = (size_t)limb * N + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double x = u2d(a[i]);
+  if (comp == 0) {
+    x += s.v[pi];
+    x = x >= q ? x - q : x;
+  }
+  out[i] = d2u(x);
+}
+
+// d[b][0] = a0 b0, d[b][1] = a0 b1 + a1 b0, d[b][2] = a1 b1
+__global__ void k_tensor(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b, uint64_t* __restrict__ d,
+                         int level, int N, int b_bcast, const PrimeD* __restrict__ pc) {
+  const int ct = blockIdx.y / level;
+  const int i = blockIdx.y % level;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t L2 = (size_t)level * N;
+  const uint64_t* A = a + (size_t)ct * 2 * L2 + (size_t)i * N + n0;
+  const uint64_t* B = b + (size_t)(b_bcast ? 0 : ct) * 2 * L2 + (size_t)i * N + n0;
+  uint64_t* D = d + (size_t)ct * 3 * L2 + (size_t)i * N + n0;
+  const double a0 = u2d(A[0]), a1 = u2d(A[L2]), b0 = u2d(B[0]), b1 = u2d(B[L2]);
+  D[0] = d2u(canon(mul_lazy(a0, b0, q, qinv), q));
+  const double m = mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv);
+  D[L2] = d2u(canon(red(m, q, qinv), q));
+  D[2 * L2] = d2u(canon(mul_lazy(a1, b1, q, qinv), q));
+}
+
+// ModUp: x [n][level][N] coefficient form -> y [n][dn][level+K][N].  For digit j
+// with primes D_j: v_i = [x_i Qhat_i^-1]_{q_i} (in [0, q_i)), and for every target
+// prime m outside D_j: y_m = sum_i v_i (Qhat_i mod m) mod m.
+__global__ void k_mod_up(const uint64_t* __restrict__ x, uint64_t* __restrict__ y, int level, int N, int alpha,
+                         int dn, int K, int Lfull, int Ltot, const double* __restrict__ tab, size_t tab_stride_lvl,
+                         size_t tab_stride_dig, const PrimeD* __restrict__ pc) {
+  const int ct = blockIdx.y / dn;
+  const int j = blockIdx.y % dn;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lo = j * alpha;
+  const int hi = min(lo + alpha, level);
+  const int na = hi - lo;
+  const double* inv = tab + (size_t)level * tab_stride_lvl + (size_t)j * tab_stride_dig;
+  const double* basis = inv + alpha;
+  const uint64_t* X = x + (size_t)ct * level * N + n0;
+  double v[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    if (a < na) {
+      const int i = lo + a;
+      const double q = pc[i].q, qinv = pc[i].qinv;
+      v[a] = canon(mul_lazy(u2d(X[(size_t)i * N]), inv[a], q, qinv), q);
+    } else {
+      v[a] = 0.0;
+    }
+  }
+  const int rows = level + K;
+  uint64_t* Y = y + ((size_t)ct * dn + j) * rows * N + n0;
+  for (int m = 0; m < rows; ++m) {
+    if (m >= lo && m < hi) continue;
+    const int pm = m < level ? m : Lfull + (m - level);
+    const double q = pc[pm].q, qinv = pc[pm].qinv;
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (a < na) acc += mul_lazy(v[a], basis[(size_t)a * Ltot + pm], q, qinv);
+    }
+    Y[(size_t)m * N] = to_u(acc, q, qinv);
+  }
+}
+
+// y[ct][j][m] = x_eval[ct][m] for the primes m of digit j
+__global__ void k_mod_up_copy_own(const uint64_t* __restrict__ x, int64_t x_ct_stride, uint64_t* __restrict__ y,
+                                  int level, int N, int alpha, int dn, int K) {
+  const int ct = blockIdx.y / dn;
+  const int j = blockIdx.y % dn;
+  const int lo = j * alpha;
+  const int hi = min(lo + alpha, level);
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rows = level + K;
+  for (int m = lo; m < hi; ++m)
+    y[(((size_t)ct * dn + j) * rows + m) * N + n0] = x[(size_t)ct * x_ct_stride + (size_t)m * N + n0];
+}
+
+// u[ct][c][m] = sum_j y[ct][j][m] * key[j][c][row(m)]  (evaluation form).
+// CB ciphertexts per thread share each key word.
+template <int CB>
+__global__ void k_key_inner(const uint64_t* __restrict__ y, const uint64_t* __restrict__ key, uint64_t* __restrict__ u,
+                            int level, int N, int dn, int K, int Lfull, int Ltot, int n_ct,
+                            const PrimeD* __restrict__ pc) {
+  const int m = blockIdx.y;
+  const int rows = level + K;
+  const int pm = m < level ? m : Lfull + (m - level);
+  const double q = pc[pm].q, qinv = pc[pm].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ct0 = blockIdx.z * CB;
+  double acc0[CB], acc1[CB];
+#pragma unroll
+  for (int b = 0; b < CB; ++b) acc0[b] = acc1[b] = 0.0;
+  for (int j = 0; j < dn; ++j) {
+    const double kb = u2d(key[(((size_t)j * 2 + 0) * Ltot + pm) * N + n0]);
+    const double ka = u2d(key[(((size_t)j * 2 + 1) * Ltot + pm) * N + n0]);
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      if (ct0 + b < n_ct) {
+        const double yy = u2d(y[(((size_t)(ct0 + b) * dn + j) * rows + m) * N + n0]);
+        acc0[b] += mul_lazy(yy, kb, q, qinv);
+        acc1[b] += mul_lazy(yy, ka, q, qinv);
+        if ((j & 3) == 3) {
+          acc0[b] = red(acc0[b], q, qinv);
+          acc1[b] = red(acc1[b], q, qinv);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < CB; ++b) {
+    if (ct0 + b < n_ct) {
+      uint64_t* U = u + ((size_t)(ct0 + b) * 2 * rows + m) * N + n0;
+      U[0] = to_u(acc0[b], q, qinv);
+      U[(size_t)rows * N] = to_u(acc1[b], q, qinv);
+    }
+  }
+}
+
+// ModDown correction: from the coefficient-form special rows up [n*2][K][N], w_k = [u_k t^-1]_{p_k},
+// v_k = [w_k Phat_k^-1]_{p_k} (both in [0, p_k)), dl_i = sum_k v_k (Phat_k mod q_i) mod q_i.
+__global__ void k_mod_down_delta(const uint64_t* __restrict__ u, uint64_t* __restrict__ dl, int level, int N, int K,
+                                 int Lfull, const double* __restrict__ md, const double* __restrict__ tinv,
+                                 const PrimeD* __restrict__ pc) {
+  const int cc = blockIdx.y;  // ct * 2 + comp
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t* U = u + (size_t)cc * K * N + n0;
+  const double* phat_inv = md;
+  const double* phat_mod = md + K;  // [K][Lfull]
+  double v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < K) {
+      const int pk = Lfull + k;
+      const double q = pc[pk].q, qinv = pc[pk].qinv;
+      const double w = canon(mul_lazy(u2d(U[(size_t)k * N]), tinv[pk], q, qinv), q);
+      v[k] = canon(mul_lazy(w, phat_inv[k], q, qinv), q);
+    } else {
+      v[k] = 0.0;
+    }
+  }
+  uint64_t* D = dl + (size_t)cc * level * N + n0;
+  for (int i = 0; i < level; ++i) {
+    const double q = pc[i].q, qinv = pc[i].qinv;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k < K) acc += mul_lazy(v[k], phat_mod[(size_t)k * Lfull + i], q, qinv);
+    }
+    D[(size_t)i * N] = to_u(acc, q, qinv);
+  }
+}
+
+// out[ct][c][i] = add[ct][c][i] + (u[ct][c][i] - t dl[ct][c][i]) P^-1  (evaluation form);
+// components c >= add_comps get no addend.
+__global__ void k_mod_down_final(const uint64_t* __restrict__ u, const uint64_t* __restrict__ dl,
+                                 const uint64_t* __restrict__ add, int64_t add_ct_stride, int add_comps,
+                                 uint64_t* __restrict__ out, int level, int N, int K, const double* __restrict__ pinv,
+                                 const double* __restrict__ tmod, const PrimeD* __restrict__ pc) {
+  const int i = blockIdx.y % level;
+  const int cc = blockIdx.y / level;  // ct * 2 + comp
+  const int ct = cc >> 1, comp = cc & 1;
+  const int rows = level + K;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double uu = u2d(u[((size_t)cc * rows + i) * N + n0]);
+  const double dd = u2d(dl[((size_t)cc * level + i) * N + n0]);
+  const double diff = uu - mul_lazy(dd, tmod[i], q, qinv);  // |.| < 2q
+  double r = mul_lazy(red(diff, q, qinv), pinv[i], q, qinv);
+  if (comp < add_comps) r += u2d(add[(size_t)ct * add_ct_stride + ((size_t)comp * level + i) * N + n0]);
+  out[((size_t)cc * level + i) * N + n0] = to_u(r, q, qinv);
+}
+
+// single modulus switch, part 1: top [n*2][N] coefficient form -> w rows [n*2][level-1][N]
+__global__ void k_msw_w(const uint64_t* __restrict__ top, uint64_t* __restrict__ w, int level, int N,
+                        double tinv_top, const PrimeD* __restrict__ pc) {
+  const int cc = blockIdx.y;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int it = level - 1;
+  const double qt = pc[it].q, qtinv = pc[it].qinv;
+  double wt = canon(mul_lazy(u2d(top[(size_t)cc * N + n0]), tinv_top, qt, qtinv), qt);
+  const double half = (qt - 1.0) * 0.5;
+  wt = wt > half ? wt - qt : wt;  // centered, |wt| < 2^49 <= every q_i
+  uint64_t* W = w + (size_t)cc * (level - 1) * N + n0;
+  for (int i = 0; i < level - 1; ++i) {
+    const double q = pc[i].q;
+    W[(size_t)i * N] = d2u(wt < 0.0 ? wt + q : wt);
+  }
+}
+
+// single modulus switch, part 2: out_i = (a_i - t w_i) q_top^-1   (evaluation form)
+__global__ void k_msw_final(const uint64_t* __restrict__ a, const uint64_t* __restrict__ w, uint64_t* __restrict__ out,
+                            int level, int N, const double* __restrict__ qinv_top, const double* __restrict__ tmod,
+                            const PrimeD* __restrict__ pc) {
+  const int lv = level - 1;
+  const int i = blockIdx.y % lv;
+  const int cc = blockIdx.y / lv;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double x = u2d(a[((size_t)cc * level + i) * N + n0]);
+  const double ww = u2d(w[((size_t)cc * lv + i) * N + n0]);
+  const double diff = x - mul_lazy(ww, tmod[i], q, qinv);
+  out[((size_t)cc * lv + i) * N + n0] = to_u(mul_lazy(red(diff, q, qinv), qinv_top[i], q, qinv), q, qinv);
+}
+
+// repeated modulus switch in coefficient form: x [n*2][level][N] -> y [n*2][to][N]
+__global__ void k_msw_multi(const uint64_t* __restrict__ x, uint64_t* __restrict__ y, int level, int to, int N,
+                            const double* __restrict__ msw, int L, const double* __restrict__ tinv,
+                            const double* __restrict__ tmod, const PrimeD* __restrict__ pc) {
+  const int cc = blockIdx.y;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t* X = x + (size_t)cc * level * N + n0;
+  double wv[64];
+  const int nd = level - to;
+  // w for each dropped prime, from the top down; the current value of limb `top`
+  // is its input transformed by every drop above it
+  for (int d = 0; d < nd; ++d) {
+    const int top = level - 1 - d;
+    const double q = pc[top].q, qinv = pc[top].qinv;
+    double cur = u2d(X[(size_t)top * N]);
+    for (int e = 0; e < d; ++e) {
+      const int up = level - 1 - e;
+      const double diff = cur - mul_lazy(wv[e] < 0.0 ? wv[e] + q : wv[e], tmod[top], q, qinv);
+      cur = mul_lazy(red(diff, q, qinv), msw[(size_t)up * L + top], q, qinv);
+    }
+    double wt = canon(mul_lazy(canon(red(cur, q, qinv), q), tinv[top], q, qinv), q);
+    const double half = (q - 1.0) * 0.5;
+    wv[d] = wt > half ? wt - q : wt;
+  }
+  uint64_t* Y = y + (size_t)cc * to * N + n0;
+  for (int i = 0; i < to; ++i) {
+    const double q = pc[i].q, qinv = pc[i].qinv;
+    double cur = u2d(X[(size_t)i * N]);
+    for (int e = 0; e < nd; ++e) {
+      const int up = level - 1 - e;
+      const double diff = cur - mul_lazy(wv[e] < 0.0 ? wv[e] + q : wv[e], tmod[i], q, qinv);
+      cur = mul_lazy(red(diff, q, qinv), msw[(size_t)up * L + i], q, qinv);
+    }
+    Y[(size_t)i * N] = to_u(cur, q, qinv);
+  }
+}
+
+__global__ void k_copy_rows(const uint64_t* __restrict__ x, uint64_t* __restrict__ y, int from, int to, int N) {
+  const int i = blockIdx.y % to;
+  const int cc = blockIdx.y / to;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  y[((size_t)cc * to + i) * N + n0] = x[((size_t)cc * from + i) * N + n0];
+}
+
+__device__ __forceinline__ uint32_t brv32(uint32_t v, int bits) { return __brev(v) >> (32 - bits); }
+
+// X -> X^g in evaluation form: slot j holds a(psi^(2 brv(j)+1)); the image holds
+// a(psi^((2 brv(j)+1) g)), i.e. the input slot j' with 2 brv(j')+1 = (2 brv(j)+1) g mod 2N.
+__global__ void k_automorph(const uint64_t* __restrict__ x, uint64_t* __restrict__ y, int logN, int g) {
+  const int N = 1 << logN;
+  const size_t limb = blockIdx.y;
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t e = 2 * brv32(j, logN) + 1;
+  const uint32_t e2 = (uint32_t)(((uint64_t)e * (uint32_t)g) & (uint32_t)(2 * N - 1));
+  const uint32_t jp = brv32((e2 - 1) >> 1, logN);
+  y[limb * N + j] = x[limb * N + jp];
+}
+
+__global__ void k_from_signed(const int64_t* __restrict__ v, uint64_t* __restrict__ y, int rows, int N, LimbMap lm,
+                              const PrimeD* __restrict__ pc) {
+  const int b = blockIdx.y / rows;
+  const int r = blockIdx.y % rows;
+  const int pi = limb_prime(lm, r);
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double q = pc[pi].q, qinv = pc[pi].qinv;
+  const int64_t s = v[(size_t)b * N + n0];
+  // small integers (|s| < 2^52) are exact as doubles
+  y[((size_t)b * rows + r) * N + n0] = to_u((double)s, q, qinv);
+}
+
+__global__ void k_phase(const uint64_t* __restrict__ ct, const uint64_t* __restrict__ S, uint64_t* __restrict__ v,
+                        int level, int N, const PrimeD* __restrict__ pc) {
+  const int i = blockIdx.y % level;
+  const int b = blockIdx.y / level;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t* C = ct + (size_t)b * 2 * level * N + (size_t)i * N + n0;
+  const double c0 = u2d(C[0]), c1 = u2d(C[(size_t)level * N]);
+  const double s = u2d(S[(size_t)i * N + n0]);
+  v[((size_t)b * level + i) * N + n0] = to_u(c0 + mul_lazy(c1, s, q, qinv), q, qinv);
+}
+
+// ct[b] = (M[b] - C1[b] S, C1[b]) over L primes
+__global__ void k_enc_combine(const uint64_t* __restrict__ M, const uint64_t* __restrict__ C1,
+                              const uint64_t* __restrict__ S, uint64_t* __restrict__ ct, int L, int N,
+                              const PrimeD* __restrict__ pc) {
+  const int i = blockIdx.y % L;
+  const int b = blockIdx.y / L;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double m = u2d(M[((size_t)b * L + i) * N + n0]);
+  const uint64_t c1w = C1[((size_t)b * L + i) * N + n0];
+  const double s = u2d(S[(size_t)i * N + n0]);
+  uint64_t* out = ct + (size_t)b * 2 * L * N + (size_t)i * N + n0;
+  out[0] = to_u(m - mul_lazy(u2d(c1w), s, q, qinv), q, qinv);
+  out[(size_t)L * N] = c1w;
+}
+
+// key[j][0][m] = -A[j][m] S[m] + t E[j][m] + [m in digit j] (P mod q_m) Sp[m];  key[j][1][m] = A[j][m]
+__global__ void k_key_combine(const uint64_t* __restrict__ A, const uint64_t* __restrict__ S,
+                              const uint64_t* __restrict__ E, const uint64_t* __restrict__ Sp,
+                              uint64_t* __restrict__ key, int Ltot, int L, int N, int alpha, double tfull_unused,
+                              const double* __restrict__ tmod_full, const double* __restrict__ pmod,
+                              const PrimeD* __restrict__ pc) {
+  const int m = blockIdx.y % Ltot;
+  const int j = blockIdx.y / Ltot;
+  const double q = pc[m].q, qinv = pc[m].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t off = ((size_t)j * Ltot + m) * N + n0;
+  const double a = u2d(A[off]);
+  const double s = u2d(S[(size_t)m * N + n0]);
+  const double e = u2d(E[off]);
+  double r = mul_lazy(e, tmod_full[m], q, qinv) - mul_lazy(a, s, q, qinv);
+  if (m < L && m / alpha == j) r += mul_lazy(u2d(Sp[(size_t)m * N + n0]), pmod[m], q, qinv);
+  key[(((size_t)j * 2 + 0) * Ltot + m) * N + n0] = to_u(r, q, qinv);
+  key[(((size_t)j * 2 + 1) * Ltot + m) * N + n0] = A[off];
+  (void)tfull_unused;
+}
+
+__global__ void k_mul_pointwise(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                                uint64_t* __restrict__ out, int N, LimbMap lm, const PrimeD* __restrict__ pc) {
+  const int limb = blockIdx.y;
+  const int pi = limb_prime(lm, limb);
+  const double q = pc[pi].q, qinv = pc[pi].qinv;
+  const size_t i = (size_t)limb * N + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  out[i] = d2u(canon(mul_lazy(u2d(a[i]), u2d(b[i]), q, qinv), q));
+}
+
+}  // namespace
+
+namespace lk {
+
+void add_sub(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n, int level, int op, bool bb) {
+  hipLaunchKernelGGL(k_add_sub, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, a, b, out, level,
+                     c->N, op, bb ? 1 : 0, c->d_prime);
+}
+
+void negate(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level) {
+  hipLaunchKernelGGL(k_negate, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, a, out, level, c->N,
+                     c->d_prime);
+}
+
+void mul_scalar(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s) {
+  Tab64 t;
+  for (int i = 0; i < 64; ++i) t.v[i] = i < level ? s[i] : 0.0;
+  hipLaunchKernelGGL(k_mul_scalar, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, a, out, level,
+                     c->N, t, c->d_prime);
+}
+
+void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s) {
+  Tab64 t;
+  for (int i = 0; i < 64; ++i) t.v[i] = i < level ? s[i] : 0.0;
+  hipLaunchKernelGGL(k_add_const, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, a, out, level,
+                     c->N, t, c->d_prime);
+}
+
+void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, int n, int level, bool bb) {
+  hipLaunchKernelGGL(k_tensor, grid_for(c->N, n * level), dim3(block_for(c->N)), 0, c->stream, a, b, d, level, c->N,
+                     bb ? 1 : 0, c->d_prime);
+}
+
+void mod_up(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level) {
+  const int dn = (level + c->alpha - 1) / c->alpha;
+  const size_t s_dig = (size_t)c->alpha * (1 + c->Ltot);
+  const size_t s_lvl = (size_t)c->dnum * s_dig;
+  hipLaunchKernelGGL(k_mod_up, grid_for(c->N, n * dn), dim3(block_for(c->N)), 0, c->stream, x, y, level, c->N,
+                     c->alpha, dn, c->prm.K, c->prm.L, c->Ltot, c->d_modup, s_lvl, s_dig, c->d_prime);
+}
+
+void mod_up_copy_own(bgv_ctx* c, const uint64_t* x, int64_t x_ct_stride, uint64_t* y, int n, int level) {
+  const int dn = (level + c->alpha - 1) / c->alpha;
+  hipLaunchKernelGGL(k_mod_up_copy_own, grid_for(c->N, n * dn), dim3(block_for(c->N)), 0, c->stream, x, x_ct_stride, y,
+                     level, c->N, c->alpha, dn, c->prm.K);
+}
+
+void key_inner(bgv_ctx* c, const uint64_t* y, const uint64_t* key, uint64_t* u, int n, int level) {
+  const int dn = (level + c->alpha - 1) / c->alpha;
+  const int rows = level + c->prm.K;
+  int cb = n >= 4 ? 4 : (n >= 2 ? 2 : 1);
+  dim3 grid = grid_for(c->N, rows, (n + cb - 1) / cb);
+  dim3 blk(block_for(c->N));
+  if (cb == 4)
+    hipLaunchKernelGGL((k_key_inner<4>), grid, blk, 0, c->stream, y, key, u, level, c->N, dn, c->prm.K, c->prm.L,
+                       c->Ltot, n, c->d_prime);
+  else if (cb == 2)
+    hipLaunchKernelGGL((k_key_inner<2>), grid, blk, 0, c->stream, y, key, u, level, c->N, dn, c->prm.K, c->prm.L,
+                       c->Ltot, n, c->d_prime);
+  else
+    hipLaunchKernelGGL((k_key_inner<1>), grid, blk, 0, c->stream, y, key, u, level, c->N, dn, c->prm.K, c->prm.L,
+                       c->Ltot, n, c->d_prime);
+}
+
+void mod_down_delta(bgv_ctx* c, const uint64_t* u, uint64_t* dl, int n, int level, int t_exp) {
+  hipLaunchKernelGGL(k_mod_down_delta, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, u, dl, level,
+                     c->N, c->prm.K, c->prm.L, c->d_moddown, c->d_tconst + (size_t)2 * t_exp * c->Ltot, c->d_prime);
+}
+
+void mod_down_final(bgv_ctx* c, const uint64_t* u, const uint64_t* dl, const uint64_t* add, int64_t add_stride,
+                    uint64_t* out, int n, int level, int t_exp) {
+  // add_stride < 0 encodes "only component 0 gets an addend" with |add_stride| the ct stride
+  int comps = add_stride < 0 ? 1 : 2;
+  int64_t stride = add_stride < 0 ? -add_stride : add_stride;
+  const double* pinv = c->d_moddown + c->prm.K + (size_t)c->prm.K * c->prm.L;
+  hipLaunchKernelGGL(k_mod_down_final, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, u, dl, add,
+                     stride, comps, out, level, c->N, c->prm.K, pinv,
+                     c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
+}
+
+void msw_w(bgv_ctx* c, const uint64_t* top, uint64_t* w, int n, int level, int t_exp) {
+  const double tinv_top = c->h_tinv[(size_t)t_exp * c->Ltot + (level - 1)];
+  hipLaunchKernelGGL(k_msw_w, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, top, w, level, c->N,
+                     tinv_top, c->d_prime);
+}
+
+void msw_final(bgv_ctx* c, const uint64_t* a, const uint64_t* w, uint64_t* out, int n, int level, int t_exp) {
+  hipLaunchKernelGGL(k_msw_final, grid_for(c->N, n * 2 * (level - 1)), dim3(block_for(c->N)), 0, c->stream, a, w, out,
+                     level, c->N, c->d_msw + (size_t)(level - 1) * c->prm.L,
+                     c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
+}
+
+void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int to, int t_exp) {
+  hipLaunchKernelGGL(k_msw_multi, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, x, y, level, to, c->N,
+                     c->d_msw, c->prm.L, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
+                     c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
+}
+
+void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from, int to, int comps) {
+  hipLaunchKernelGGL(k_copy_rows, grid_for(c->N, n * comps * to), dim3(block_for(c->N)), 0, c->stream, x, y, from, to,
+                     c->N);
+}
+
+void automorph(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n_polys, int level, int g) {
+  hipLaunchKernelGGL(k_automorph, grid_for(c->N, n_polys * level), dim3(block_for(c->N)), 0, c->stream, x, y, c->logN,
+                     g);
+}
+
+void from_signed(bgv_ctx* c, const int64_t* v, uint64_t* y, int n_polys, int rows, LimbMap lm) {
+  hipLaunchKernelGGL(k_from_signed, grid_for(c->N, n_polys * rows), dim3(block_for(c->N)), 0, c->stream, v, y, rows,
+                     c->N, lm, c->d_prime);
+}
+
+void mul_pointwise(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n_limbs, LimbMap lm,
+                   int64_t) {
+  hipLaunchKernelGGL(k_mul_pointwise, grid_for(c->N, n_limbs), dim3(block_for(c->N)), 0, c->stream, a, b, out, c->N, lm,
+                     c->d_prime);
+}
+
+void phase(bgv_ctx* c, const uint64_t* ct, const uint64_t* S, uint64_t* v, int n, int level) {
+  hipLaunchKernelGGL(k_phase, grid_for(c->N, n * level), dim3(block_for(c->N)), 0, c->stream, ct, S, v, level, c->N,
+                     c->d_prime);
+}
+
+void enc_combine(bgv_ctx* c, const uint64_t* M, const uint64_t* C1, const uint64_t* S, uint64_t* ct, int n) {
+  hipLaunchKernelGGL(k_enc_combine, grid_for(c->N, n * c->prm.L), dim3(block_for(c->N)), 0, c->stream, M, C1, S, ct,
+                     c->prm.L, c->N, c->d_prime);
+}
+
+void key_combine(bgv_ctx* c, const uint64_t* A, const uint64_t* S, const uint64_t* E, const uint64_t* Sp,
+                 uint64_t* key, int dnum) {
+  // tmod for t = p^r and P mod q_m live in the t-constant table and the ModDown table area
+  const double* tmod_full = c->d_tconst + ((size_t)2 * c->prm.r + 1) * c->Ltot;
+  const double* pmod = c->d_moddown + c->prm.K + (size_t)c->prm.K * c->prm.L + c->prm.L;
+  hipLaunchKernelGGL(k_key_combine, grid_for(c->N, dnum * c->Ltot), dim3(block_for(c->N)), 0, c->stream, A, S, E, Sp,
+                     key, c->Ltot, c->prm.L, c->N, c->alpha, 0.0, tmod_full, pmod, c->d_prime);
+}
+
+}  // namespace lk

@@ -1,0 +1,628 @@
+// Operation layer of the library: key switching, modulus switching, encryption,
+// decryption, key generation, the Paterson-Stockmeyer evaluator and the
+// space-switching composites.  Every device step is a kernel on the context's
+// stream; this file only sequences them and manages temporaries.
+#include "ops.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "host_nt.hpp"
+
+using hnt::centered;
+using hnt::invmod;
+using hnt::mulmod;
+using hnt::powmod;
+
+Scratch::Scratch(bgv_ctx* cc, size_t words) : c(cc) {
+  bytes = words * sizeof(uint64_t);
+  d = (uint64_t*)c->pool.get(bytes ? bytes : 8);
+  if (!d) throw OpError{BGV_E_OOM};
+}
+
+Scratch::~Scratch() {
+  if (d) c->pool.put(d, bytes);
+}
+
+CipherP new_cipher(bgv_ctx* c, int n, int level, int t_exp) {
+  auto p = std::make_shared<Cipher>();
+  p->buf = std::make_shared<Scratch>(c, (size_t)n * ct_words(c, level));
+  p->v.d = p->buf->d;
+  p->v.n = n;
+  p->v.level = level;
+  p->v.t_exp = t_exp;
+  return p;
+}
+
+static void check_hip(bgv_ctx* c, hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    throw OpError{BGV_E_DEVICE};
+  }
+}
+
+void op_copy(bgv_ctx* c, const CtV& in, const CtV& out) {
+  if (in.d == out.d) return;
+  check_hip(c, hipMemcpyAsync(out.d, in.d, (size_t)in.n * ct_words(c, in.level) * 8, hipMemcpyDeviceToDevice, c->stream),
+            "copy");
+}
+
+CipherP clone(bgv_ctx* c, const CtV& x) {
+  CipherP r = new_cipher(c, x.n, x.level, x.t_exp);
+  op_copy(c, x, r->v);
+  return r;
+}
+
+static LimbMap lm_chain(const bgv_ctx* c, int level) { return LimbMap{level, level, c->prm.L, 0, 1, 0}; }
+
+void op_ntt(bgv_ctx* c, uint64_t* d, int n_polys, int level, bool inverse) {
+  lk::ntt(c, d, n_polys * level, lm_chain(c, level), inverse);
+}
+
+void op_add_sub(bgv_ctx* c, const CtV& a, const CtV& b, const CtV& out, int op) {
+  lk::add_sub(c, a.d, b.d, out.d, a.n, a.level, op, b.n == 1 && a.n > 1);
+}
+
+void op_negate(bgv_ctx* c, const CtV& a, const CtV& out) { lk::negate(c, a.d, out.d, a.n, a.level); }
+
+static void scalar_table(const bgv_ctx* c, int64_t k, int level, double* s) {
+  for (int i = 0; i < level; ++i) {
+    const int64_t q = (int64_t)c->primes[i];
+    int64_t v = k % q;
+    if (v < 0) v += q;
+    s[i] = (double)v;
+  }
+}
+
+void op_mul_scalar(bgv_ctx* c, const CtV& a, int64_t k, const CtV& out) {
+  double s[64];
+  scalar_table(c, centered(k, c->tpow[a.t_exp]), a.level, s);
+  lk::mul_scalar(c, a.d, out.d, a.n, a.level, s);
+}
+
+void op_add_const(bgv_ctx* c, const CtV& a, int64_t k, const CtV& out) {
+  double s[64];
+  scalar_table(c, centered(k, c->tpow[a.t_exp]), a.level, s);
+  lk::add_const(c, a.d, out.d, a.n, a.level, s);
+}
+
+void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out) {
+  double s[64];
+  for (int i = 0; i < a.level; ++i) s[i] = (double)invmod((uint64_t)c->prm.p, c->primes[i]);
+  lk::mul_scalar(c, a.d, out.d, a.n, a.level, s);
+}
+
+// Hybrid key switching of the polynomial x (ciphertext b at x_eval + b * x_stride, [level][N]
+// evaluation form) under `key`; out[b][comp] = add[b][comp] (comp < add_comps) + switched[comp].
+static void key_switch(bgv_ctx* c, const uint64_t* key, const uint64_t* x_eval, int64_t x_stride, int n, int level,
+                       int t_exp, const uint64_t* add, int64_t add_stride, int add_comps, uint64_t* out) {
+  const int N = c->N, K = c->prm.K, L = c->prm.L, A = c->alpha;
+  const int dn = (level + A - 1) / A, rows = level + K;
+  Scratch X(c, (size_t)n * level * N);
+  check_hip(c,
+            hipMemcpy2DAsync(X.d, (size_t)level * N * 8, x_eval, (size_t)x_stride * 8, (size_t)level * N * 8, n,
+                             hipMemcpyDeviceToDevice, c->stream),
+            "gather");
+  op_ntt(c, X.d, n, level, true);
+  Scratch Y(c, (size_t)n * dn * rows * N);
+  lk::mod_up(c, X.d, Y.d, n, level);
+  lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0}, false);
+  lk::mod_up_copy_own(c, x_eval, x_stride, Y.d, n, level);
+  Scratch U(c, (size_t)n * 2 * rows * N);
+  lk::key_inner(c, Y.d, key, U.d, n, level);
+  Scratch Up(c, (size_t)n * 2 * K * N);
+  check_hip(c,
+            hipMemcpy2DAsync(Up.d, (size_t)K * N * 8, U.d + (size_t)level * N, (size_t)rows * N * 8, (size_t)K * N * 8,
+                             (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
+            "gather special");
+  lk::ntt(c, Up.d, n * 2 * K, LimbMap{K, 0, L, 0, 1, 0}, true);
+  Scratch DL(c, (size_t)n * 2 * level * N);
+  lk::mod_down_delta(c, Up.d, DL.d, n, level, t_exp);
+  op_ntt(c, DL.d, n * 2, level, false);
+  lk::mod_down_final(c, U.d, DL.d, add, add_comps == 2 ? add_stride : -add_stride, out, n, level, t_exp);
+}
+
+void op_mul_relin(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
+  const int n = a.n, lv = a.level, N = c->N;
+  Scratch D(c, (size_t)n * 3 * lv * N);
+  lk::tensor(c, a.d, b.d, D.d, n, lv, b.n == 1 && n > 1);
+  const int64_t st = (int64_t)3 * lv * N;
+  key_switch(c, keys->relin, D.d + (size_t)2 * lv * N, st, n, lv, a.t_exp, D.d, st, 2, out.d);
+}
+
+int galois_elt(const bgv_ctx* c, int step) {
+  const uint64_t two_n = 2 * (uint64_t)c->N;
+  if (step == BGV_ROW_SWAP) return (int)(two_n - 1);
+  const int half = c->ell / 2;
+  int s = ((step % half) + half) % half;
+  return (int)powmod(5, (uint64_t)s, two_n);
+}
+
+void op_rotate(bgv_ctx* c, const bgv_keys* keys, const CtV& in, int g, const CtV& out) {
+  const int n = in.n, lv = in.level, N = c->N;
+  auto it = keys->galois.find(g);
+  if (it == keys->galois.end()) throw OpError{BGV_E_NOKEY};
+  Scratch R(c, (size_t)n * 2 * lv * N);
+  lk::automorph(c, in.d, R.d, n * 2, lv, g);
+  const int64_t st = (int64_t)2 * lv * N;
+  key_switch(c, it->second, R.d + (size_t)lv * N, st, n, lv, in.t_exp, R.d, st, 1, out.d);
+}
+
+void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out) {
+  const int n = in.n, lv = in.level, N = c->N;
+  if (lv < 2) throw OpError{BGV_E_LEVEL};
+  Scratch T(c, (size_t)n * 2 * N);
+  check_hip(c,
+            hipMemcpy2DAsync(T.d, (size_t)N * 8, in.d + (size_t)(lv - 1) * N, (size_t)lv * N * 8, (size_t)N * 8,
+                             (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
+            "gather top");
+  lk::ntt(c, T.d, n * 2, LimbMap{1, 1, c->prm.L, 0, 1, lv - 1}, true);
+  Scratch W(c, (size_t)n * 2 * (lv - 1) * N);
+  lk::msw_w(c, T.d, W.d, n, lv, in.t_exp);
+  op_ntt(c, W.d, n * 2, lv - 1, false);
+  if (out.d == in.d) {
+    Scratch O(c, (size_t)n * 2 * (lv - 1) * N);
+    lk::msw_final(c, in.d, W.d, O.d, n, lv, in.t_exp);
+    check_hip(c, hipMemcpyAsync(out.d, O.d, (size_t)n * 2 * (lv - 1) * N * 8, hipMemcpyDeviceToDevice, c->stream),
+              "copy");
+  } else {
+    lk::msw_final(c, in.d, W.d, out.d, n, lv, in.t_exp);
+  }
+}
+
+void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out) {
+  const int n = in.n, lv = in.level, N = c->N;
+  if (to > lv || to < 1) throw OpError{BGV_E_LEVEL};
+  if (to == lv) {
+    op_copy(c, in, out);
+    return;
+  }
+  if (to == lv - 1) {
+    op_mod_switch(c, in, out);
+    return;
+  }
+  Scratch X(c, (size_t)n * 2 * lv * N);
+  check_hip(c, hipMemcpyAsync(X.d, in.d, (size_t)n * 2 * lv * N * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+  op_ntt(c, X.d, n * 2, lv, true);
+  lk::msw_multi(c, X.d, out.d, n, lv, to, in.t_exp);
+  op_ntt(c, out.d, n * 2, to, false);
+}
+
+// ------------------------------------------------------------------ encoding
+
+// Slot encoder: the inverse of the Vandermonde matrix V[j][k] = zeta_j^k over
+// Z_{p^r}, found by Gauss-Jordan elimination (the slot roots are distinct mod p,
+// so every pivot is a unit).  encode(v) = Vinv v gives the coefficients of M(Y).
+bool build_encoder(bgv_ctx* c) {
+  const int l = c->ell;
+  const int64_t t = c->t_full, p = c->prm.p;
+  std::vector<std::vector<int64_t>> A(l, std::vector<int64_t>(2 * l, 0));
+  for (int j = 0; j < l; ++j) {
+    const int64_t z = (int64_t)powmod((uint64_t)c->zeta, (uint64_t)c->slot_exp[j], (uint64_t)t);
+    int64_t pw = 1;
+    for (int k = 0; k < l; ++k) {
+      A[j][k] = pw;
+      pw = (int64_t)((__int128)pw * z % t);
+    }
+    A[j][l + j] = 1;
+  }
+  for (int col = 0; col < l; ++col) {
+    int piv = -1;
+    for (int r = col; r < l; ++r)
+      if (A[r][col] % p) {
+        piv = r;
+        break;
+      }
+    if (piv < 0) return false;
+    std::swap(A[piv], A[col]);
+    const int64_t inv = (int64_t)invmod((uint64_t)A[col][col], (uint64_t)t);
+    for (int k = 0; k < 2 * l; ++k) A[col][k] = (int64_t)((__int128)A[col][k] * inv % t);
+    for (int r = 0; r < l; ++r) {
+      if (r == col || A[r][col] == 0) continue;
+      const int64_t f = A[r][col];
+      for (int k = 0; k < 2 * l; ++k) A[r][k] = ((A[r][k] - (int64_t)((__int128)f * A[col][k] % t)) % t + t) % t;
+    }
+  }
+  // the inverse sits in the right half: row k of Vinv maps slot values to coefficient k
+  std::vector<int64_t>& Vinv = c->encoder;
+  Vinv.assign((size_t)l * l, 0);
+  for (int k = 0; k < l; ++k)
+    for (int j = 0; j < l; ++j) Vinv[(size_t)k * l + j] = A[k][l + j];
+  return true;
+}
+
+static void encode_slots(const bgv_ctx* c, const uint64_t* v, int64_t* m) {
+  const int l = c->ell;
+  const int64_t t = c->t_full;
+  std::memset(m, 0, sizeof(int64_t) * c->N);
+  for (int k = 0; k < l; ++k) {
+    __int128 acc = 0;
+    for (int j = 0; j < l; ++j) acc += (__int128)c->encoder[(size_t)k * l + j] * (int64_t)(v[j] % (uint64_t)t);
+    m[(size_t)k * c->dslot] = centered((int64_t)(acc % t), t);
+  }
+}
+
+bgv_status op_encrypt(bgv_ctx* c, const int8_t* s, const uint64_t* slots, const uint64_t* c1, const int32_t* e,
+                      const CtV& out) {
+  const int n = out.n, L = c->prm.L, N = c->N;
+  std::vector<int64_t> me((size_t)n * N), s64(N);
+  for (int b = 0; b < n; ++b) {
+    encode_slots(c, slots + (size_t)b * c->ell, &me[(size_t)b * N]);
+    for (int k = 0; k < N; ++k) me[(size_t)b * N + k] += c->t_full * (int64_t)e[(size_t)b * N + k];
+  }
+  for (int k = 0; k < N; ++k) s64[k] = s[k];
+  Scratch dme(c, (size_t)n * N), ds(c, (size_t)N), M(c, (size_t)n * L * N), S(c, (size_t)L * N),
+      C1(c, (size_t)n * L * N);
+  check_hip(c, hipMemcpyAsync(dme.d, me.data(), me.size() * 8, hipMemcpyHostToDevice, c->stream), "upload");
+  check_hip(c, hipMemcpyAsync(ds.d, s64.data(), s64.size() * 8, hipMemcpyHostToDevice, c->stream), "upload");
+  check_hip(c, hipMemcpyAsync(C1.d, c1, (size_t)n * L * N * 8, hipMemcpyHostToDevice, c->stream), "upload");
+  lk::from_signed(c, (const int64_t*)dme.d, M.d, n, L, lm_chain(c, L));
+  op_ntt(c, M.d, n, L, false);
+  lk::from_signed(c, (const int64_t*)ds.d, S.d, 1, L, lm_chain(c, L));
+  op_ntt(c, S.d, 1, L, false);
+  op_ntt(c, C1.d, n, L, false);
+  lk::enc_combine(c, M.d, C1.d, S.d, out.d, n);
+  check_hip(c, hipStreamSynchronize(c->stream), "sync");
+  return BGV_OK;
+}
+
+bgv_status op_decrypt(bgv_ctx* c, const int8_t* s, const CtV& in, uint64_t* slots, uint8_t* nonconst) {
+  const int n = in.n, lv = in.level, N = c->N;
+  std::vector<int64_t> s64(N);
+  for (int k = 0; k < N; ++k) s64[k] = s[k];
+  Scratch ds(c, (size_t)N), S(c, (size_t)lv * N), V(c, (size_t)n * lv * N);
+  check_hip(c, hipMemcpyAsync(ds.d, s64.data(), s64.size() * 8, hipMemcpyHostToDevice, c->stream), "upload");
+  lk::from_signed(c, (const int64_t*)ds.d, S.d, 1, lv, lm_chain(c, lv));
+  op_ntt(c, S.d, 1, lv, false);
+  lk::phase(c, in.d, S.d, V.d, n, lv);
+  op_ntt(c, V.d, n, lv, true);
+  std::vector<uint64_t> hv((size_t)n * lv * N);
+  check_hip(c, hipMemcpyAsync(hv.data(), V.d, hv.size() * 8, hipMemcpyDeviceToHost, c->stream), "download");
+  check_hip(c, hipStreamSynchronize(c->stream), "sync");
+
+  // CRT to the centered integer mod Q_lv, reduced mod t: with y_i = [v_i Qhat_i^-1]_{q_i},
+  // V = sum y_i Qhat_i - k Q where k = round(sum y_i / q_i) (V is tiny against Q).
+  const int64_t t = c->tpow[in.t_exp];
+  std::vector<uint64_t> qhinv(lv);
+  std::vector<int64_t> qh_t(lv);
+  int64_t Q_t = 1;
+  for (int i = 0; i < lv; ++i) {
+    const uint64_t qi = c->primes[i];
+    uint64_t qh = 1;
+    int64_t qht = 1;
+    for (int j = 0; j < lv; ++j)
+      if (j != i) {
+        qh = mulmod(qh, c->primes[j] % qi, qi);
+        qht = (int64_t)((__int128)qht * (int64_t)(c->primes[j] % (uint64_t)t) % t);
+      }
+    qhinv[i] = invmod(qh, qi);
+    qh_t[i] = qht;
+    Q_t = (int64_t)((__int128)Q_t * (int64_t)(qi % (uint64_t)t) % t);
+  }
+  std::vector<int64_t> m(N);
+  const int l = c->ell, d = c->dslot;
+  for (int b = 0; b < n; ++b) {
+    for (int k = 0; k < N; ++k) {
+      long double frac = 0.0L;
+      __int128 acc = 0;
+      for (int i = 0; i < lv; ++i) {
+        const uint64_t qi = c->primes[i];
+        const uint64_t y = mulmod(hv[((size_t)b * lv + i) * N + k], qhinv[i], qi);
+        frac += (long double)y / (long double)qi;
+        acc += (__int128)(int64_t)(y % (uint64_t)t) * qh_t[i];
+      }
+      const int64_t kk = (int64_t)llroundl(frac);
+      __int128 val = (acc - (__int128)(kk % t) * Q_t) % t;
+      if (val < 0) val += t;
+      m[k] = (int64_t)val;
+    }
+    // slot j = m(X) mod (X^d - zeta_j): fold with powers of zeta_j
+    for (int j = 0; j < l; ++j) {
+      const int64_t z = (int64_t)powmod((uint64_t)(c->zeta % t), (uint64_t)c->slot_exp[j], (uint64_t)t);
+      bool nc = false;
+      int64_t val0 = 0;
+      for (int bb = 0; bb < d; ++bb) {
+        __int128 acc = 0;
+        int64_t zp = 1;
+        for (int a = 0; a < l; ++a) {
+          acc += (__int128)m[(size_t)a * d + bb] * zp;
+          zp = (int64_t)((__int128)zp * z % t);
+        }
+        const int64_t r = (int64_t)(acc % t);
+        if (bb == 0) val0 = r;
+        else if (r != 0) nc = true;
+        if (!nonconst && bb == 0) break;
+      }
+      slots[(size_t)b * l + j] = (uint64_t)val0;
+      if (nonconst) nonconst[(size_t)b * l + j] = nc ? 1 : 0;
+    }
+  }
+  return BGV_OK;
+}
+
+bgv_status op_keygen(bgv_ctx* c, const int8_t* s, const uint64_t* a, const int32_t* e, const std::vector<int>& gal,
+                     bgv_keys* keys) {
+  const int N = c->N, Lt = c->Ltot, dn = c->dnum;
+  std::vector<int64_t> s64(N);
+  for (int k = 0; k < N; ++k) s64[k] = s[k];
+  Scratch ds(c, (size_t)N), S(c, (size_t)Lt * N), Sp(c, (size_t)Lt * N), A(c, (size_t)dn * Lt * N),
+      E(c, (size_t)dn * Lt * N), de(c, (size_t)dn * N);
+  check_hip(c, hipMemcpyAsync(ds.d, s64.data(), s64.size() * 8, hipMemcpyHostToDevice, c->stream), "upload");
+  lk::from_signed(c, (const int64_t*)ds.d, S.d, 1, Lt, lm_chain(c, Lt));
+  op_ntt(c, S.d, 1, Lt, false);
+  const size_t key_words = (size_t)dn * 2 * Lt * N;
+  std::vector<int64_t> e64((size_t)dn * N);
+  const int n_keys = 1 + (int)gal.size();
+  for (int kidx = 0; kidx < n_keys; ++kidx) {
+    if (kidx == 0) {
+      lk::mul_pointwise(c, S.d, S.d, Sp.d, Lt, lm_chain(c, Lt), 0);
+    } else {
+      lk::automorph(c, S.d, Sp.d, 1, Lt, gal[kidx - 1]);
+    }
+    check_hip(c, hipMemcpyAsync(A.d, a + (size_t)kidx * dn * Lt * N, (size_t)dn * Lt * N * 8, hipMemcpyHostToDevice,
+                                c->stream),
+              "upload");
+    op_ntt(c, A.d, dn, Lt, false);
+    for (size_t i = 0; i < e64.size(); ++i) e64[i] = e[(size_t)kidx * dn * N + i];
+    check_hip(c, hipMemcpyAsync(de.d, e64.data(), e64.size() * 8, hipMemcpyHostToDevice, c->stream), "upload");
+    lk::from_signed(c, (const int64_t*)de.d, E.d, dn, Lt, lm_chain(c, Lt));
+    op_ntt(c, E.d, dn, Lt, false);
+    uint64_t* kd = nullptr;
+    check_hip(c, hipMalloc((void**)&kd, key_words * 8), "key alloc");
+    lk::key_combine(c, A.d, S.d, E.d, Sp.d, kd, dn);
+    keys->bytes += (int64_t)key_words * 8;
+    if (kidx == 0) keys->relin = kd;
+    else keys->galois[gal[kidx - 1]] = kd;
+    check_hip(c, hipStreamSynchronize(c->stream), "sync");  // host staging buffers are reused
+  }
+  return BGV_OK;
+}
+
+// ------------------------------------------------------------------ evaluator
+
+CipherP ev_align(bgv_ctx* c, const CipherP& x, int level) {
+  if (x->v.level == level) return x;
+  if (level > x->v.level || level < 1) throw OpError{BGV_E_LEVEL};
+  CipherP r = new_cipher(c, x->v.n, level, x->v.t_exp);
+  op_mod_switch_to(c, x->v, level, r->v);
+  return r;
+}
+
+static CipherP with_t(const CipherP& x, int t_exp) {
+  auto r = std::make_shared<Cipher>();
+  r->buf = x->buf;
+  r->v = x->v;
+  r->v.t_exp = t_exp;
+  return r;
+}
+
+CipherP ev_mul(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& b) {
+  const int lv = std::min(a->v.level, b->v.level);
+  if (lv < 2) throw OpError{BGV_E_LEVEL};
+  if (a->v.t_exp != b->v.t_exp) throw OpError{BGV_E_PTXT_MOD};
+  CipherP a2 = ev_align(c, a, lv), b2 = ev_align(c, b, lv);
+  const int n = std::max(a->v.n, b->v.n);
+  CipherP m = new_cipher(c, n, lv, a->v.t_exp);
+  if (a2->v.n == 1 && n > 1) op_mul_relin(c, k, b2->v, a2->v, m->v);
+  else op_mul_relin(c, k, a2->v, b2->v, m->v);
+  CipherP r = new_cipher(c, n, lv - 1, a->v.t_exp);
+  op_mod_switch(c, m->v, r->v);
+  return r;
+}
+
+CipherP ev_add(bgv_ctx* c, const CipherP& a, const CipherP& b) {
+  const int lv = std::min(a->v.level, b->v.level);
+  if (a->v.t_exp != b->v.t_exp) throw OpError{BGV_E_PTXT_MOD};
+  CipherP a2 = ev_align(c, a, lv), b2 = ev_align(c, b, lv);
+  const int n = std::max(a->v.n, b->v.n);
+  CipherP r = new_cipher(c, n, lv, a->v.t_exp);
+  if (a2->v.n == 1 && n > 1) op_add_sub(c, b2->v, a2->v, r->v, 0);
+  else op_add_sub(c, a2->v, b2->v, r->v, 0);
+  return r;
+}
+
+static CipherP ev_scalar(bgv_ctx* c, const CipherP& x, int64_t k) {
+  CipherP r = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
+  op_mul_scalar(c, x->v, k, r->v);
+  return r;
+}
+
+static CipherP ev_const(bgv_ctx* c, const CipherP& x, int64_t k) {
+  CipherP r = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
+  op_add_const(c, x->v, k, r->v);
+  return r;
+}
+
+static CipherP ev_neg(bgv_ctx* c, const CipherP& x) {
+  CipherP r = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
+  op_negate(c, x->v, r->v);
+  return r;
+}
+
+// x^i by the power rule: h = 2^floor(log2 i); x^i = x^(i/2) x^(i/2) if i = h, else x^h x^(i-h)
+static const CipherP& power(bgv_ctx* c, const bgv_keys* k, std::map<int, CipherP>& tab, int i) {
+  auto it = tab.find(i);
+  if (it != tab.end()) return it->second;
+  int h = 1;
+  while (2 * h <= i) h *= 2;
+  CipherP r;
+  if (i == h) {
+    const CipherP& half = power(c, k, tab, i / 2);
+    r = ev_mul(c, k, half, half);
+  } else {
+    const CipherP& a = power(c, k, tab, h);
+    const CipherP& b = power(c, k, tab, i - h);
+    r = ev_mul(c, k, a, b);
+  }
+  return tab[i] = r;
+}
+
+int eval_depth(int degree) {
+  int k = 1;
+  while (2 * k * k < degree + 1) k *= 2;
+  int g = (degree + k) / k;
+  int lk2 = 0;
+  while ((1 << lk2) < k) ++lk2;
+  int lg = 0;
+  while ((1 << lg) < g - 1) ++lg;  // depth of y^(g-1) above y
+  return lk2 + (g > 1 ? lg : 0) + 1;
+}
+
+// Baby-step/giant-step evaluation (Paterson-Stockmeyer, Theorem 2) with the
+// schedule: k = smallest power of two with 2k^2 >= D+1, g = ceil((D+1)/k);
+// baby powers x^2..x^k and giant powers y^2..y^(g-1) (y = x^k) by the power
+// rule; inner sums over the nonzero coefficients with every power first brought
+// to the lowest level among those used, scalar terms accumulated in increasing
+// order and the constant added last; outer terms I_j y^j for j = 1..g-1 in
+// increasing order (a scalar multiple of y^j when I_j is a constant), with I_0
+// added at the end.  Each product aligns its operands, relinearises and
+// switches down one prime.
+CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std::vector<int64_t>& coeffs,
+                     std::vector<CipherP>* giant_out, int* giant_k) {
+  const int64_t t = c->tpow[x->v.t_exp];
+  std::vector<int64_t> cf(coeffs.size());
+  for (size_t i = 0; i < coeffs.size(); ++i) cf[i] = ((coeffs[i] % t) + t) % t;
+  int D = (int)cf.size() - 1;
+  while (D > 0 && cf[D] == 0) --D;
+  if (D < 1) throw OpError{BGV_E_ARG};
+  int kk = 1;
+  while (2 * kk * kk < D + 1) kk *= 2;
+  const int g = (D + kk) / kk;
+  auto coef = [&](int n) -> int64_t { return n <= D ? cf[n] : 0; };
+
+  std::map<int, CipherP> baby;
+  baby[1] = x;
+  for (int i = 2; i <= kk; ++i) power(c, k, baby, i);
+  std::map<int, CipherP> giant;
+  giant[1] = baby[kk];
+  for (int j = 2; j < g; ++j) power(c, k, giant, j);
+
+  std::map<std::pair<int, int>, CipherP> aligned;
+  auto aligned_power = [&](int i, int lv) -> CipherP {
+    auto key = std::make_pair(i, lv);
+    auto it = aligned.find(key);
+    if (it != aligned.end()) return it->second;
+    CipherP r = ev_align(c, baby[i], lv);
+    aligned[key] = r;
+    return r;
+  };
+
+  struct Inner {
+    bool is_const;
+    int64_t cst;
+    CipherP ct;
+  };
+  std::vector<Inner> inner(g);
+  for (int j = 0; j < g; ++j) {
+    std::vector<int> used;
+    for (int i = 1; i < kk; ++i)
+      if (coef(j * kk + i) != 0) used.push_back(i);
+    const int64_t cst = coef(j * kk);
+    if (used.empty()) {
+      inner[j] = Inner{true, cst, nullptr};
+      continue;
+    }
+    int lv = 1 << 30;
+    for (int i : used) lv = std::min(lv, baby[i]->v.level);
+    CipherP acc;
+    for (int i : used) {
+      CipherP term = ev_scalar(c, aligned_power(i, lv), coef(j * kk + i));
+      acc = acc ? ev_add(c, acc, term) : term;
+    }
+    if (cst != 0) acc = ev_const(c, acc, cst);
+    inner[j] = Inner{false, 0, acc};
+  }
+  CipherP result;
+  for (int j = 1; j < g; ++j) {
+    CipherP term;
+    if (inner[j].is_const) {
+      if (inner[j].cst == 0) continue;
+      term = ev_scalar(c, giant[j], inner[j].cst);
+    } else {
+      term = ev_mul(c, k, inner[j].ct, giant[j]);
+    }
+    result = result ? ev_add(c, result, term) : term;
+  }
+  if (inner[0].is_const) {
+    if (!result) throw OpError{BGV_E_ARG};
+    if (inner[0].cst != 0) result = ev_const(c, result, inner[0].cst);
+  } else {
+    result = result ? ev_add(c, result, inner[0].ct) : inner[0].ct;
+  }
+  if (giant_out) {
+    giant_out->assign(g, nullptr);
+    for (int j = 1; j < g; ++j) (*giant_out)[j] = giant[j];
+    *giant_k = kk;
+  }
+  return result;
+}
+
+// Algorithm 3 with r = 2: a0 = G_{p,2}(x), a1 = DivideByP(x - a0), both tagged t = p.
+std::vector<CipherP> ev_space_reduce(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
+  if (x->v.t_exp == 1) return {x};
+  if (x->v.t_exp != 2) throw OpError{BGV_E_UNSUPPORTED};
+  CipherP a0 = ev_eval_poly(c, k, x, c->g2);
+  CipherP xb = ev_align(c, x, a0->v.level);
+  CipherP d = new_cipher(c, x->v.n, a0->v.level, 2);
+  op_add_sub(c, xb->v, a0->v, d->v, 1);
+  CipherP a1 = new_cipher(c, x->v.n, a0->v.level, 1);
+  op_divide_by_p(c, d->v, a1->v);
+  return {with_t(a0, 1), a1};
+}
+
+static CipherP eq_from_power(bgv_ctx* c, const CipherP& xp) { return ev_const(c, ev_neg(c, xp), 1); }
+
+// Algorithm 4 (digits least significant first).
+CipherP ev_compare(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& digits, int op) {
+  const int r = (int)digits.size();
+  const int p = c->prm.p;
+  auto eq_digit = [&](const CipherP& x) {
+    std::map<int, CipherP> tab;
+    tab[1] = x;
+    return eq_from_power(c, power(c, k, tab, p - 1));
+  };
+  if (op == BGV_OP_EQ) {
+    CipherP eq = eq_digit(digits[r - 1]);
+    for (int i = r - 2; i >= 0; --i) eq = ev_mul(c, k, eq, eq_digit(digits[i]));
+    return eq;
+  }
+  std::vector<CipherP> lts(r);
+  CipherP eq;
+  for (int i = 0; i < r; ++i) {
+    std::vector<CipherP> giants;
+    int kk = 0;
+    lts[i] = ev_eval_poly(c, k, digits[i], c->flt, &giants, &kk);
+    if (i == r - 1 && r > 1) {
+      // x^(p-1) is the last giant power when (g-1) k = p-1 (same products as the power rule)
+      const int g = (int)giants.size();
+      if (g > 1 && (g - 1) * kk == p - 1) eq = eq_from_power(c, giants[g - 1]);
+      else eq = eq_digit(digits[i]);
+    }
+  }
+  CipherP lt = lts[r - 1];
+  for (int i = r - 2; i >= 0; --i) {
+    lt = ev_add(c, lt, ev_mul(c, k, eq, lts[i]));
+    if (i > 0) eq = ev_mul(c, k, eq, eq_digit(digits[i]));
+  }
+  return lt;
+}
+
+CipherP ev_space_raise(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
+  if (c->prm.r == 1) return with_t(x, 1);
+  if (c->prm.r != 2) throw OpError{BGV_E_UNSUPPORTED};
+  return ev_eval_poly(c, k, with_t(x, c->prm.r), c->g2);
+}
+
+CipherP ev_rotate_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
+  CipherP acc = x;
+  for (int i = 1; i < c->ell / 2; i *= 2) {
+    CipherP r = new_cipher(c, acc->v.n, acc->v.level, acc->v.t_exp);
+    op_rotate(c, k, acc->v, galois_elt(c, i), r->v);
+    acc = ev_add(c, acc, r);
+  }
+  CipherP r = new_cipher(c, acc->v.n, acc->v.level, acc->v.t_exp);
+  op_rotate(c, k, acc->v, galois_elt(c, BGV_ROW_SWAP), r->v);
+  return ev_add(c, acc, r);
+}

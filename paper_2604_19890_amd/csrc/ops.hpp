@@ -1,0 +1,76 @@
+// Internal operation layer: owned temporaries, the operations behind the C-ABI,
+// the polynomial evaluator and the space-switching composites.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "ctx.hpp"
+
+bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream);
+void ctx_free(bgv_ctx* c);
+bool build_encoder(bgv_ctx* c);
+
+// A ciphertext batch view (no ownership).
+struct CtV {
+  uint64_t* d = nullptr;
+  int n = 0, level = 0, t_exp = 0;
+};
+
+// Device scratch from the context pool, returned on destruction.
+struct Scratch {
+  bgv_ctx* c = nullptr;
+  uint64_t* d = nullptr;
+  size_t bytes = 0;
+  Scratch() = default;
+  Scratch(bgv_ctx* cc, size_t words);
+  ~Scratch();
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+};
+
+// An owned ciphertext batch.
+struct Cipher {
+  std::shared_ptr<Scratch> buf;  // shared by views that differ only in the t_exp tag
+  CtV v;
+};
+typedef std::shared_ptr<Cipher> CipherP;
+
+struct OpError {
+  bgv_status st;
+};
+
+CipherP new_cipher(bgv_ctx* c, int n, int level, int t_exp);
+CipherP clone(bgv_ctx* c, const CtV& x);
+inline size_t ct_words(const bgv_ctx* c, int level) { return (size_t)2 * level * c->N; }
+
+// ---- primitive operations (enqueue on the context stream; no argument checks)
+void op_ntt(bgv_ctx* c, uint64_t* d, int n_polys, int level, bool inverse);
+void op_add_sub(bgv_ctx* c, const CtV& a, const CtV& b, const CtV& out, int op);
+void op_negate(bgv_ctx* c, const CtV& a, const CtV& out);
+void op_mul_scalar(bgv_ctx* c, const CtV& a, int64_t k, const CtV& out);
+void op_add_const(bgv_ctx* c, const CtV& a, int64_t k, const CtV& out);
+void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out);
+void op_mul_relin(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out);
+void op_rotate(bgv_ctx* c, const bgv_keys* keys, const CtV& in, int g, const CtV& out);
+void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out);         // one prime
+void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out);  // repeated
+void op_copy(bgv_ctx* c, const CtV& in, const CtV& out);
+int galois_elt(const bgv_ctx* c, int step);
+
+bgv_status op_encrypt(bgv_ctx* c, const int8_t* s, const uint64_t* slots, const uint64_t* c1, const int32_t* e,
+                      const CtV& out);
+bgv_status op_decrypt(bgv_ctx* c, const int8_t* s, const CtV& in, uint64_t* slots, uint8_t* nonconst);
+bgv_status op_keygen(bgv_ctx* c, const int8_t* s, const uint64_t* a, const int32_t* e, const std::vector<int>& gal,
+                     bgv_keys* keys);
+
+// ---- evaluator and composites (owned results)
+CipherP ev_align(bgv_ctx* c, const CipherP& x, int level);
+CipherP ev_mul(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& b);
+CipherP ev_add(bgv_ctx* c, const CipherP& a, const CipherP& b);
+CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std::vector<int64_t>& coeffs,
+                     std::vector<CipherP>* giant_out = nullptr, int* giant_k = nullptr);
+std::vector<CipherP> ev_space_reduce(bgv_ctx* c, const bgv_keys* k, const CipherP& x);
+CipherP ev_compare(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& digits, int op);
+CipherP ev_space_raise(bgv_ctx* c, const bgv_keys* k, const CipherP& x);
+CipherP ev_rotate_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& x);
+int eval_depth(int degree);

@@ -43,6 +43,16 @@ def ternary(n: int, seed: int = 0, workload: int = 0, index: int = 0) -> np.ndar
     return rng(seed, workload, SECRET, index).integers(-1, 2, size=n, dtype=np.int64).astype(np.int8)
 
 
+def ternary_hw(n: int, weight: int, seed: int = 0, workload: int = 0, index: int = 0) -> np.ndarray:
+    """Ternary vector (int8) with exactly `weight` nonzero entries, each +1 or -1 uniformly,
+    at uniformly chosen positions (the sparse secret of the paper's parameter section)."""
+    g = rng(seed, workload, SECRET, index)
+    pos = g.choice(n, size=weight, replace=False)
+    s = np.zeros(n, dtype=np.int8)
+    s[pos] = np.where(g.integers(0, 2, size=weight) == 1, 1, -1).astype(np.int8)
+    return s
+
+
 def gaussian(n: int, seed: int = 0, workload: int = 0, purpose: int = ERROR, index: int = 0) -> np.ndarray:
     """Rounded (half-even) clipped normal deviates, int32, sigma = 3.2."""
     x = rng(seed, workload, purpose, index).normal(0.0, SIGMA, size=n)

@@ -1,0 +1,92 @@
+"""Matched GPU-library / oracle contexts for the parity tests.
+
+Both sides receive the same seeded secret key, key-switching randomness and
+encryption randomness from paper_2604_19890_amd.synth; neither side sees the
+other's outputs.  GPU ciphertexts are brought to coefficient form with the
+library's own inverse NTT before they are compared word by word."""
+import functools
+import sys
+
+import numpy as np
+
+from oracle import bgv as B
+from oracle.params import Params
+from paper_2604_19890_amd import synth
+
+WL = 91  # workload tag of the parity tests
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class Pair:
+    def __init__(self, logN, p, r, L, K, steps=(), conj=False, seed=0, oracle_keys=True):
+        from paper_2604_19890_amd import bgv as G
+        self.G = G
+        log(f"[ctx] N=2^{logN} p={p} r={r} L={L} K={K}")
+        self.lib = G.Context(logN, p, r, L, K)
+        self.P = Params(logN, p, r, L, K)
+        assert self.lib.primes == self.P.primes, "prime chains differ"
+        assert self.lib.slots == self.P.ell
+        self.N = self.P.N
+        self.seed = seed
+        self.s = synth.ternary(self.N, seed, WL)
+        self.steps = list(steps)
+        self.conj = conj
+        n_keys = 1 + len(steps) + (1 if conj else 0)
+        self.key_rand = [synth.key_randomness(self.P.primes, self.N, self.P.dnum, seed, WL, i) for i in range(n_keys)]
+        a = np.stack([kr[0] for kr in self.key_rand])
+        e = np.stack([kr[1] for kr in self.key_rand])
+        self.keys = self.lib.keygen(self.s, a, e, steps=steps, with_conj=conj)
+        self.okeys = B.keygen(self.P, self.s, self.key_rand, steps=steps, with_conj=conj) if oracle_keys else None
+        self._n = 0
+
+    def rand(self, idx):
+        return synth.encryption_randomness(self.P.q, self.N, self.seed, WL, idx)
+
+    def enc_both(self, slot_rows, oracle=True):
+        """Encrypt a batch (one row of slot values per ciphertext) on the GPU and in the oracle."""
+        rows = [list(map(int, r)) for r in slot_rows]
+        c1s, es, octs = [], [], []
+        for r in rows:
+            self._n += 1
+            c1, e = self.rand(5000 + self._n)
+            c1s.append(c1)
+            es.append(e)
+            if oracle:
+                octs.append(B.encrypt(self.P, self.s, r, c1, e))
+        g = self.lib.encrypt(self.s, np.array(rows, dtype=np.uint64), np.stack(c1s), np.stack(es))
+        return g, octs
+
+    def coeff_words(self, ct):
+        """GPU batch -> uint64 [n][2][level][N] in coefficient form (library inverse NTT on a copy)."""
+        t = ct.tensor[: ct.n * 2 * ct.level * self.N].clone()
+        self.lib.ntt(t, ct.n * 2, ct.level, inverse=True)
+        return t.cpu().numpy().view(np.uint64).reshape(ct.n, 2, ct.level, self.N)
+
+    def assert_equal(self, gct, octs, what):
+        w = self.coeff_words(gct)
+        assert gct.n == len(octs)
+        for b, o in enumerate(octs):
+            assert gct.level == o.level, f"{what}: level {gct.level} != {o.level}"
+            assert gct.t_exp == o.t_exp, f"{what}: t_exp {gct.t_exp} != {o.t_exp}"
+            if not np.array_equal(w[b], o.c):
+                bad = np.argwhere(w[b] != o.c)
+                raise AssertionError(f"{what}: ct {b}: {len(bad)} words differ, first at {bad[0].tolist()}")
+
+
+@functools.lru_cache(maxsize=None)
+def pair_tiny17():
+    return Pair(5, 17, 2, 18, 1, steps=(1, 2), conj=True)
+
+
+@functools.lru_cache(maxsize=None)
+def pair_hybrid17():
+    return Pair(6, 17, 2, 7, 2, steps=(1,), conj=True)
+
+
+@functools.lru_cache(maxsize=None)
+def pair_tiny5():
+    return Pair(4, 5, 2, 12, 1, steps=(), conj=True)

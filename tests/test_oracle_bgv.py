@@ -187,3 +187,18 @@ def test_depth_example_ab_cd():
     assert cnt.mul == int(gold["multiplications"])
     assert P.L - r.level == int(gold["depth"])
     assert c.dec(r) == [3 * 5 * 7 * 11 % t] * P.ell
+
+
+@pytest.mark.parametrize("ctx", [tiny17, hybrid17])
+def test_sampled_oracle_matches_full_oracle(ctx):
+    """The sampled-output forms used at large rings agree with the full computations."""
+    from paper_2604_19890_amd import synth
+    c = ctx()
+    P = c.P
+    a, b = c.enc(list(range(P.ell))), c.enc([3] * P.ell)
+    idx = [0, 5, P.N - 1]
+    assert np.array_equal(B.mul_relin(P, c.keys.relin, a, b).c[:, :, idx], B.mul_relin_at(P, c.keys.relin, a, b, idx))
+    assert np.array_equal(B.rotate(P, c.keys.galois, a, 1).c[:, :, idx], B.rotate_at(P, c.keys.galois, a, 1, idx))
+    c1, e = synth.encryption_randomness(P.q, P.N, 0, 5, 3)
+    ct = B.encrypt(P, c.s, list(range(P.ell)), c1, e)
+    assert np.array_equal(ct.c[0][:, idx], B.encrypt_at(P, c.s, list(range(P.ell)), c1, e, idx))
