@@ -194,6 +194,34 @@ bgv_status bgv_less_than(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* x, co
                          bgv_ct* out);
 bgv_status bgv_rotate_sum(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, bgv_ct* out);
 
+/* ---- workload glue ---------------------------------------------------------
+ * bgv_mul: the evaluator's product step: both operands are brought to the lower
+ *   level by single-prime modulus switches, multiplied and relinearised, then
+ *   switched down one prime (output level = min level - 1).  b may be a single
+ *   ciphertext broadcast against a batch.
+ * bgv_batch_sum: out (one ciphertext) = sum of the in->n ciphertexts of a batch.
+ * bgv_filter_sum: the filter-and-aggregate query SUM(b*c WHERE a < thr) over the
+ *   rows packed in the slots of the batches a, b, c (thr: one ciphertext, or a batch
+ *   of the same size): per ciphertext [a < thr] * (b * c) with the product steps
+ *   above, the batch summed, then rotate-and-sum so that every slot of `out` holds
+ *   the total (Figure 1's WHERE -> multiply -> SUM pipeline).  Needs the keys of
+ *   bgv_rotate_sum.
+ * bgv_relu: x * (1 - [x < 0]) slot-wise (the ReLU-style sign/compare workload).   */
+bgv_status bgv_mul(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* a, const bgv_ct* b, bgv_ct* out);
+bgv_status bgv_batch_sum(bgv_ctx* ctx, const bgv_ct* in, bgv_ct* out);
+bgv_status bgv_filter_sum(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* a, const bgv_ct* thr, const bgv_ct* b,
+                          const bgv_ct* c, bgv_ct* out);
+bgv_status bgv_relu(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* x, bgv_ct* out);
+
+/* ---- tuning ---------------------------------------------------------------
+ * bgv_set_ntt_chunk: two-pass NTTs over many limbs run in chunks of `limbs`
+ *   limbs (first and second pass per chunk) so that the first pass's output is
+ *   still cached when the second pass reads it; 0 runs all limbs in one launch
+ *   pair.  Results are identical for every setting.  BGV_E_ARG if limbs < 0.
+ * bgv_get_ntt_chunk: the current setting.                                       */
+bgv_status bgv_set_ntt_chunk(bgv_ctx* ctx, int32_t limbs);
+int32_t bgv_get_ntt_chunk(const bgv_ctx* ctx);
+
 /* ---- raw NTT access (the transform on its own, for tests and bandwidth runs)
  * bgv_ntt: in place on a DEVICE array holding n_polys polynomials of `level` limbs
  *   each ([n_polys][level][N] uint64 residues, limb i under q_i); forward (coefficient

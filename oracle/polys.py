@@ -16,20 +16,32 @@ All coefficient lists are ascending (index i is the coefficient of x^i), values 
 """
 from __future__ import annotations
 
+import functools
 
-def f_eq(p: int) -> list:
+
+@functools.lru_cache(maxsize=None)
+def _f_eq(p: int) -> tuple:
     c = [0] * p
     c[0] = 1
     c[p - 1] = p - 1
-    return c
+    return tuple(c)
 
 
-def f_lt(p: int) -> list:
+def f_eq(p: int) -> list:
+    return list(_f_eq(p))
+
+
+@functools.lru_cache(maxsize=None)
+def _f_lt(p: int) -> tuple:
     c = [0] * p
     c[p - 1] = (p + 1) // 2 % p
     for i in range(1, p - 1, 2):
         c[i] = sum(pow(j, p - 1 - i, p) for j in range(1, (p - 1) // 2 + 1)) % p
-    return c
+    return tuple(c)
+
+
+def f_lt(p: int) -> list:
+    return list(_f_lt(p))
 
 
 def _poly_mul(a, b, m):
@@ -60,15 +72,20 @@ def lagrange(points, values, m):
     return result
 
 
-def g_p2(p: int) -> list:
-    """Coefficients of G_{p,2} mod p^2 (length p + 1)."""
+@functools.lru_cache(maxsize=None)
+def _g_p2(p: int) -> tuple:
     zs = list(range(-(p - 1) // 2, (p - 1) // 2 + 1))
     phi = [((z - z ** p) // p) % p for z in zs]
     H = lagrange([z % p for z in zs], phi, p)
     t = p * p
     G = [(p * h) % t for h in H] + [0]
     G[p] = (G[p] + 1) % t
-    return G
+    return tuple(G)
+
+
+def g_p2(p: int) -> list:
+    """Coefficients of G_{p,2} mod p^2 (length p + 1)."""
+    return list(_g_p2(p))
 
 
 def g_poly(p: int, e: int) -> list:

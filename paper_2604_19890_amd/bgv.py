@@ -83,7 +83,13 @@ _sigs = {
     "bgv_space_raise": [_vp, _vp, _P(_Ct), _P(_Ct)],
     "bgv_less_than": [_vp, _vp, _P(_Ct), _P(_Ct), _P(_Ct)],
     "bgv_rotate_sum": [_vp, _vp, _P(_Ct), _P(_Ct)],
+    "bgv_mul": [_vp, _vp, _P(_Ct), _P(_Ct), _P(_Ct)],
+    "bgv_batch_sum": [_vp, _P(_Ct), _P(_Ct)],
+    "bgv_filter_sum": [_vp, _vp, _P(_Ct), _P(_Ct), _P(_Ct), _P(_Ct), _P(_Ct)],
+    "bgv_relu": [_vp, _vp, _P(_Ct), _P(_Ct)],
     "bgv_ntt": [_vp, _vp, _i64, _i32, _i32, _i32],
+    "bgv_set_ntt_chunk": [_vp, _i32],
+    "bgv_get_ntt_chunk": [_vp],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -130,9 +136,9 @@ class Keys:
     def bytes(self) -> int:
         return int(_lib.bgv_keys_bytes(self.handle))
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.bgv_keys_destroy):
         if getattr(self, "handle", None):
-            _lib.bgv_keys_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 
@@ -159,9 +165,9 @@ class Context:
         _lib.bgv_ctx_primes(h, _ptr(pr))
         self.primes = [int(x) for x in pr]
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.bgv_ctx_destroy):
         if getattr(self, "handle", None):
-            _lib.bgv_ctx_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
     # ------------------------------------------------------------------ helpers
@@ -319,6 +325,36 @@ class Context:
 
     def rotate_sum(self, keys, a, out=None):
         return self._un(_lib.bgv_rotate_sum, a, out=out, keys=keys)
+
+    def mul(self, keys, a, b, out=None):
+        n = max(a.n, b.n)
+        out = self._out(out, n, min(a.level, b.level) - 1, a.t_exp)
+        sa, sb, so = a._struct(), b._struct(), out._struct()
+        self._check(_lib.bgv_mul(self.handle, keys.handle, ctypes.byref(sa), ctypes.byref(sb), ctypes.byref(so)))
+        out._update(so)
+        return out
+
+    def batch_sum(self, a, out=None):
+        return self._un(_lib.bgv_batch_sum, a, out=out) if out is not None else self._un(
+            _lib.bgv_batch_sum, a, out=self.empty(1, a.level, a.t_exp))
+
+    def filter_sum(self, keys, a, thr, b, c, out=None):
+        out = self._out(out, 1, a.level, a.t_exp)
+        s = [x._struct() for x in (a, thr, b, c, out)]
+        self._check(_lib.bgv_filter_sum(self.handle, keys.handle, *[ctypes.byref(x) for x in s]))
+        out._update(s[-1])
+        return out
+
+    def relu(self, keys, x, out=None):
+        return self._un(_lib.bgv_relu, x, out=out, keys=keys)
+
+    @property
+    def ntt_chunk(self) -> int:
+        return int(_lib.bgv_get_ntt_chunk(self.handle))
+
+    @ntt_chunk.setter
+    def ntt_chunk(self, limbs: int):
+        self._check(_lib.bgv_set_ntt_chunk(self.handle, int(limbs)))
 
     def ntt(self, t: torch.Tensor, n_polys: int, level: int, inverse: bool = False):
         self._check(_lib.bgv_ntt(self.handle, ctypes.c_void_p(t.data_ptr()), t.numel(), n_polys, level,

@@ -1,5 +1,6 @@
 // extern "C" entry points: argument validation, then the operation layer.
 // Every check that can fail runs on the host before any work is enqueued.
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -367,17 +368,10 @@ BGV_EXPORT bgv_status bgv_less_than(bgv_ctx* c, const bgv_keys* k, const bgv_ct*
   NEED_CTX(c);
   if (!k) return fail(c, BGV_E_ARG, "no keys");
   CHECK(check_in(c, x, "null x"));
-  if (y) CHECK(binary_check(c, x, y));
+  if (y) CHECK(binary_check(c, x, y));  // y: same batch size or a single broadcast ciphertext
   if (x->t_exp != 2) return fail(c, BGV_E_UNSUPPORTED, "the reduction is built for t = p^2");
   return guarded(c, [&] {
-    CipherP d = borrow(x);
-    if (y) {
-      CipherP t = new_cipher(c, x->n, x->level, x->t_exp);
-      op_add_sub(c, view(x), view(y), t->v, 1);
-      d = t;
-    }
-    std::vector<CipherP> dg = ev_space_reduce(c, k, d);
-    return deliver(c, ev_space_raise(c, k, ev_compare(c, k, dg, BGV_OP_LT)), out);
+    return deliver(c, ev_less_than(c, k, borrow(x), y ? borrow(y) : nullptr), out);
   });
 }
 
@@ -391,6 +385,49 @@ BGV_EXPORT bgv_status bgv_rotate_sum(bgv_ctx* c, const bgv_keys* k, const bgv_ct
   return guarded(c, [&] { return deliver(c, ev_rotate_sum(c, k, borrow(in)), out); });
 }
 
+BGV_EXPORT bgv_status bgv_mul(bgv_ctx* c, const bgv_keys* k, const bgv_ct* a, const bgv_ct* b, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k || !k->relin) return fail(c, BGV_E_NOKEY, "no relinearisation key");
+  CHECK(check_in(c, a, "null a"));
+  CHECK(check_in(c, b, "null b"));
+  if (a->t_exp != b->t_exp) return fail(c, BGV_E_PTXT_MOD, "operands with different plaintext moduli");
+  if (a->n != b->n && a->n != 1 && b->n != 1) return fail(c, BGV_E_ARG, "batch sizes differ");
+  if (std::min(a->level, b->level) < 2) return fail(c, BGV_E_LEVEL, "no level left for a product");
+  return guarded(c, [&] { return deliver(c, ev_mul(c, k, borrow(a), borrow(b)), out); });
+}
+
+BGV_EXPORT bgv_status bgv_batch_sum(bgv_ctx* c, const bgv_ct* in, bgv_ct* out) {
+  NEED_CTX(c);
+  CHECK(check_in(c, in, "null input"));
+  return guarded(c, [&] { return deliver(c, ev_batch_sum(c, borrow(in)), out); });
+}
+
+BGV_EXPORT bgv_status bgv_filter_sum(bgv_ctx* c, const bgv_keys* k, const bgv_ct* a, const bgv_ct* thr,
+                                     const bgv_ct* b, const bgv_ct* cc, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k || !k->relin) return fail(c, BGV_E_NOKEY, "no keys");
+  CHECK(check_in(c, a, "null a"));
+  CHECK(check_in(c, thr, "null thr"));
+  CHECK(check_in(c, b, "null b"));
+  CHECK(check_in(c, cc, "null c"));
+  if (a->t_exp != 2 || thr->t_exp != 2 || b->t_exp != 2 || cc->t_exp != 2)
+    return fail(c, BGV_E_PTXT_MOD, "the query runs on t = p^2 inputs");
+  if (b->n != a->n || cc->n != a->n || (thr->n != 1 && thr->n != a->n)) return fail(c, BGV_E_ARG, "batch sizes differ");
+  if (a->level != thr->level) return fail(c, BGV_E_LEVEL, "a and thr at different levels");
+  for (int i = 1; i < c->ell / 2; i *= 2)
+    if (!k->galois.count(galois_elt(c, i))) return fail(c, BGV_E_NOKEY, "missing a power-of-two rotation key");
+  if (!k->galois.count(galois_elt(c, BGV_ROW_SWAP))) return fail(c, BGV_E_NOKEY, "missing the row-swap key");
+  return guarded(c, [&] { return deliver(c, ev_filter_sum(c, k, borrow(a), borrow(thr), borrow(b), borrow(cc)), out); });
+}
+
+BGV_EXPORT bgv_status bgv_relu(bgv_ctx* c, const bgv_keys* k, const bgv_ct* x, bgv_ct* out) {
+  NEED_CTX(c);
+  if (!k || !k->relin) return fail(c, BGV_E_NOKEY, "no keys");
+  CHECK(check_in(c, x, "null x"));
+  if (x->t_exp != 2) return fail(c, BGV_E_UNSUPPORTED, "the reduction is built for t = p^2");
+  return guarded(c, [&] { return deliver(c, ev_relu(c, k, borrow(x)), out); });
+}
+
 BGV_EXPORT bgv_status bgv_ntt(bgv_ctx* c, uint64_t* d, int64_t cap_words, int32_t n_polys, int32_t level,
                               int32_t inverse) {
   NEED_CTX(c);
@@ -401,3 +438,12 @@ BGV_EXPORT bgv_status bgv_ntt(bgv_ctx* c, uint64_t* d, int64_t cap_words, int32_
     return BGV_OK;
   });
 }
+
+BGV_EXPORT bgv_status bgv_set_ntt_chunk(bgv_ctx* c, int32_t limbs) {
+  NEED_CTX(c);
+  if (limbs < 0) return fail(c, BGV_E_ARG, "chunk must be >= 0");
+  c->ntt_chunk = limbs;
+  return BGV_OK;
+}
+
+BGV_EXPORT int32_t bgv_get_ntt_chunk(const bgv_ctx* c) { return c ? c->ntt_chunk : 0; }

@@ -35,15 +35,18 @@ struct LimbMap {
   int skip_alpha;
   int dnum_p;
   int first;
+  int offset;  // added to the launch's limb index before the map is applied
 };
 
 __device__ __forceinline__ int limb_prime(const LimbMap& lm, int l) {
+  l += lm.offset;
   int m = l % lm.period;
   return m < lm.ell_q ? lm.first + m : lm.Lfull + (m - lm.ell_q);
 }
 
 __device__ __forceinline__ bool limb_skipped(const LimbMap& lm, int l) {
   if (lm.skip_alpha <= 0) return false;
+  l += lm.offset;
   int m = l % lm.period;
   int j = (l / lm.period) % lm.dnum_p;
   return m < lm.ell_q && m / lm.skip_alpha == j;

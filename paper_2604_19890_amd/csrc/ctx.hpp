@@ -31,6 +31,7 @@ struct bgv_ctx {
   std::vector<int64_t> tpow;     // p^e for e = 0..r
   hipStream_t stream = nullptr;
   std::string err;
+  int ntt_chunk = 0;  // limbs per chunk of a two-pass NTT (0: one launch pair for all limbs)
   DevPool pool;
 
   // device tables
@@ -110,6 +111,8 @@ void msw_final(bgv_ctx* c, const uint64_t* a, const uint64_t* w, uint64_t* out, 
 void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int to, int t_exp);
 // copy limb rows: y[b][c][i] = x[b][c][i] for i < to_level (x has from_level rows)
 void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from_level, int to_level, int comps);
+// out (one ciphertext) = sum of the n ciphertexts of x
+void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level);
 // automorphism in evaluation form on n*2 polys of `level` limbs
 void automorph(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n_polys, int level, int g);
 // signed small integers (int64 [N] per poly) -> residues [n_polys][rows][N] under primes given by lm

@@ -308,6 +308,22 @@ __global__ void k_copy_rows(const uint64_t* __restrict__ x, uint64_t* __restrict
   y[((size_t)cc * to + i) * N + n0] = x[((size_t)cc * from + i) * N + n0];
 }
 
+// out[c][i] = sum over the batch of in[b][c][i]  (one block row per limb of one ciphertext)
+__global__ void k_batch_sum(const uint64_t* __restrict__ x, uint64_t* __restrict__ out, int n, int level, int N,
+                            const PrimeD* __restrict__ pc) {
+  const int limb = blockIdx.y;  // comp * level + i
+  const int i = limb % level;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)2 * level * N;
+  double acc = 0.0;
+  for (int b = 0; b < n; ++b) {
+    acc += u2d(x[(size_t)b * stride + (size_t)limb * N + n0]);
+    if ((b & 3) == 3) acc = red(acc, q, qinv);
+  }
+  out[(size_t)limb * N + n0] = to_u(acc, q, qinv);
+}
+
 __device__ __forceinline__ uint32_t brv32(uint32_t v, int bits) { return __brev(v) >> (32 - bits); }
 
 // X -> X^g in evaluation form: slot j holds a(psi^(2 brv(j)+1)); the image holds
@@ -493,6 +509,11 @@ void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int
 void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from, int to, int comps) {
   hipLaunchKernelGGL(k_copy_rows, grid_for(c->N, n * comps * to), dim3(block_for(c->N)), 0, c->stream, x, y, from, to,
                      c->N);
+}
+
+void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level) {
+  hipLaunchKernelGGL(k_batch_sum, grid_for(c->N, 2 * level), dim3(block_for(c->N)), 0, c->stream, x, out, n, level,
+                     c->N, c->d_prime);
 }
 
 void automorph(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n_polys, int level, int g) {

@@ -17,6 +17,16 @@
 // the coalesced order for the store.  Global loads and stores are coalesced:
 // in the column pass neighbouring threads handle neighbouring columns, in the
 // contiguous pass neighbouring threads handle neighbouring points.
+//
+// Reduction is lazy.  A Cooley-Tukey step of four register stages starts with
+// |v| <= q and keeps every value below 7.1 q without reducing: at the four
+// stages the multiplicand is below 1, 1.9, 3.1 and 4.8 q; the quotient estimate
+// of a product is off by at most 3 * 2^-53 |y w / q| + 1/2, so the product's
+// representative stays below 0.9, 1.2, 1.7 and 2.3 q, and every intermediate
+// (including |h - k q| <= 2.3 q + ulp(h)/2 < 2^53) is exact.  A Gentleman-Sande
+// step reduces the sums after its second and fourth stage, which keeps every
+// value below 4 q and every multiplicand below 8 q.  Each step ends with one
+// reduction of its 16 values.
 #include "ctx.hpp"
 
 namespace {
@@ -25,12 +35,59 @@ constexpr int NT_MAX = 256;
 
 __device__ __forceinline__ int lds_idx(int sl, int k, int S) { return sl * (S + (S >> 4) + 1) + k + (k >> 4); }
 
+// Cooley-Tukey stages at register distances DMAX, DMAX/2, .., 1 on 16 registers
+// holding global indices g0 + i * 2^gs_log.  The butterflies of group g at
+// distance dd share twiddle number ((N + g0) >> log2(2 dd 2^gs_log)) + g.
+template <int DMAX>
+__device__ __forceinline__ void ct_stages(double* v, const double* __restrict__ w, int N, int g0, int gs_log,
+                                          double q, double qinv) {
+#pragma unroll
+  for (int dd = DMAX; dd >= 1; dd >>= 1) {
+    const double* wp = w + ((N + g0) >> (__builtin_ctz(2 * dd) + gs_log));
+#pragma unroll
+    for (int g = 0; g < 16 / (2 * dd); ++g) {
+      const double wt = wp[g];
+#pragma unroll
+      for (int i = g * 2 * dd; i < g * 2 * dd + dd; ++i) {
+        const double r = mul_lazy(v[i + dd], wt, q, qinv);
+        const double a = v[i];
+        v[i] = a + r;
+        v[i + dd] = a - r;
+      }
+    }
+  }
+}
+
+// Gentleman-Sande stages at register distances 1, 2, .., DMAX.
+template <int DMAX>
+__device__ __forceinline__ void gs_stages(double* v, const double* __restrict__ w, int N, int g0, int gs_log,
+                                          double q, double qinv) {
+  int stage = 0;
+#pragma unroll
+  for (int dd = 1; dd <= DMAX; dd <<= 1) {
+    ++stage;
+    const double* wp = w + ((N + g0) >> (__builtin_ctz(2 * dd) + gs_log));
+#pragma unroll
+    for (int g = 0; g < 16 / (2 * dd); ++g) {
+      const double wt = wp[g];
+#pragma unroll
+      for (int i = g * 2 * dd; i < g * 2 * dd + dd; ++i) {
+        const double a = v[i], b = v[i + dd];
+        const double s = a + b;
+        v[i] = (stage & 1) ? s : red(s, q, qinv);
+        v[i + dd] = mul_lazy(a - b, wt, q, qinv);
+      }
+    }
+  }
+}
+
 template <int LOGS, bool INV>
 __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data, int logN, int s0, LimbMap lm,
                                                      const PrimeD* __restrict__ pc,
-                                                     const double* __restrict__ tw, int first, int last) {
+                                                     const double* __restrict__ tw, int last) {
   constexpr int S = 1 << LOGS;
   constexpr int T = S / 16;
+  constexpr int T_LOG = LOGS - 4;
   __shared__ double lds[NT_MAX * 16 + NT_MAX + NT_MAX];
   const int N = 1 << logN;
   const int NT = blockDim.x;
@@ -56,52 +113,28 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
   const int lo = st & (tmin - 1);
   const int hi = st >> tmin_log;
   const int base = (hi << (tmax_log + 1)) + lo;
+  // coalesced layout: register i holds global index g1 + i * 2^gs1_log
+  const int g1 = base + (tau << tmin_log);
+  const int gs1_log = T_LOG + tmin_log;
+  // consecutive layout: register i holds global index g2 + i * tmin
+  const int g2 = base + ((16 * tau) << tmin_log);
+  uint64_t* __restrict__ xp = x + g1;
   double v[16];
 
-  // load in the coalesced order: k = tau + T*i
 #pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = u2d(x[base + (tau + T * i) * tmin]);
+  for (int i = 0; i < 16; ++i) v[i] = u2d(xp[(size_t)i << gs1_log]);
 
   if (!INV) {
-    // stages with local half-distance 8T, 4T, 2T, T (register distance 8, 4, 2, 1)
-#pragma unroll
-    for (int dd = 8; dd >= 1; dd >>= 1) {
-      const int tg_log = tmin_log + __builtin_ctz(dd * T);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (i & dd) continue;
-        const int jup = base + (tau + T * i) * tmin;
-        const double wt = w[(N + jup) >> (tg_log + 1)];
-        const double r = mul_lazy(v[i + dd], wt, q, qinv);
-        const double a = v[i];
-        v[i] = red(a + r, q, qinv);
-        v[i + dd] = red(a - r, q, qinv);
-      }
-    }
+    ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
     if (T > 1) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = v[i];
+      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
-      // remaining stages: local half-distance T/2 .. 1 on consecutive points
+      ct_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, tmin_log, q, qinv);
 #pragma unroll
-      for (int dd = 8; dd >= 1; dd >>= 1) {
-        if (dd >= T) continue;
-        const int tg_log = tmin_log + __builtin_ctz(dd);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          if (i & dd) continue;
-          const int jup = base + (16 * tau + i) * tmin;
-          const double wt = w[(N + jup) >> (tg_log + 1)];
-          const double r = mul_lazy(v[i + dd], wt, q, qinv);
-          const double a = v[i];
-          v[i] = red(a + r, q, qinv);
-          v[i + dd] = red(a - r, q, qinv);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = v[i];
+      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
@@ -113,52 +146,26 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+      gs_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, tmin_log, q, qinv);
 #pragma unroll
-      for (int dd = 1; dd <= 8; dd <<= 1) {
-        if (dd >= T) continue;
-        const int tg_log = tmin_log + __builtin_ctz(dd);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          if (i & dd) continue;
-          const int jup = base + (16 * tau + i) * tmin;
-          const double wt = w[(N + jup) >> (tg_log + 1)];
-          const double a = v[i], b = v[i + dd];
-          v[i] = red(a + b, q, qinv);
-          v[i + dd] = mul_lazy(red(a - b, q, qinv), wt, q, qinv);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = v[i];
+      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
     }
-#pragma unroll
-    for (int dd = 1; dd <= 8; dd <<= 1) {
-      const int tg_log = tmin_log + __builtin_ctz(dd * T);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (i & dd) continue;
-        const int jup = base + (tau + T * i) * tmin;
-        const double wt = w[(N + jup) >> (tg_log + 1)];
-        const double a = v[i], b = v[i + dd];
-        v[i] = red(a + b, q, qinv);
-        v[i + dd] = mul_lazy(red(a - b, q, qinv), wt, q, qinv);
-      }
-    }
+    gs_stages<8>(v, w, N, g1, gs1_log, q, qinv);
     if (last) {
       const double ninv = pc[pi].ninv;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = mul_lazy(v[i], ninv, q, qinv);
+      for (int i = 0; i < 16; ++i) v[i] = mul_lazy(red(v[i], q, qinv), ninv, q, qinv);
     }
   }
 #pragma unroll
-  for (int i = 0; i < 16; ++i) x[base + (tau + T * i) * tmin] = d2u(canon(red(v[i], q, qinv), q));
-  (void)first;
+  for (int i = 0; i < 16; ++i) xp[(size_t)i << gs1_log] = d2u(canon(red(v[i], q, qinv), q));
 }
 
 template <bool INV>
-void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int s0, int first, int last) {
+void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int s0, int last) {
   const int N = c->N;
   const int S = 1 << logS;
   const int T = S / 16;
@@ -170,7 +177,7 @@ void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int
 #define CASE(LS)                                                                                           \
   case LS:                                                                                                 \
     hipLaunchKernelGGL((k_ntt_pass<LS, INV>), grid, dim3(NT), 0, c->stream, d, c->logN, s0, lm, c->d_prime, \
-                       tw, first, last);                                                                   \
+                       tw, last);                                                                          \
     break;
     CASE(4)
     CASE(5)
@@ -198,15 +205,25 @@ void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse) {
     p1 = (logN + 1) / 2;
     p2 = logN - p1;
   }
-  if (!inverse) {
-    launch_pass<false>(c, d, n_limbs, lm, p1, 0, 1, p2 == 0);
-    if (p2) launch_pass<false>(c, d, n_limbs, lm, p2, p1, 0, 1);
-  } else {
-    if (p2) {
-      launch_pass<true>(c, d, n_limbs, lm, p2, p1, 1, 0);
-      launch_pass<true>(c, d, n_limbs, lm, p1, 0, 0, 1);
+  // Two-pass transforms run chunk by chunk so that a chunk's first-pass output is
+  // still in L2 / Infinity Cache when the second pass reads it.  The limb map is
+  // shifted with the chunk: limb l of the chunk is limb off + l of the launch.
+  const int chunk = (p2 && c->ntt_chunk > 0) ? c->ntt_chunk : n_limbs;
+  for (int off = 0; off < n_limbs; off += chunk) {
+    const int cnt = n_limbs - off < chunk ? n_limbs - off : chunk;
+    uint64_t* dc = d + (size_t)off * c->N;
+    LimbMap lc = lm;
+    lc.offset = lm.offset + off;
+    if (!inverse) {
+      launch_pass<false>(c, dc, cnt, lc, p1, 0, p2 == 0);
+      if (p2) launch_pass<false>(c, dc, cnt, lc, p2, p1, 1);
     } else {
-      launch_pass<true>(c, d, n_limbs, lm, p1, 0, 1, 1);
+      if (p2) {
+        launch_pass<true>(c, dc, cnt, lc, p2, p1, 0);
+        launch_pass<true>(c, dc, cnt, lc, p1, 0, 1);
+      } else {
+        launch_pass<true>(c, dc, cnt, lc, p1, 0, 1);
+      }
     }
   }
 }

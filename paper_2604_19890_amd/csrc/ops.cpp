@@ -55,7 +55,7 @@ CipherP clone(bgv_ctx* c, const CtV& x) {
   return r;
 }
 
-static LimbMap lm_chain(const bgv_ctx* c, int level) { return LimbMap{level, level, c->prm.L, 0, 1, 0}; }
+static LimbMap lm_chain(const bgv_ctx* c, int level) { return LimbMap{level, level, c->prm.L, 0, 1, 0, 0}; }
 
 void op_ntt(bgv_ctx* c, uint64_t* d, int n_polys, int level, bool inverse) {
   lk::ntt(c, d, n_polys * level, lm_chain(c, level), inverse);
@@ -108,7 +108,7 @@ static void key_switch(bgv_ctx* c, const uint64_t* key, const uint64_t* x_eval, 
   op_ntt(c, X.d, n, level, true);
   Scratch Y(c, (size_t)n * dn * rows * N);
   lk::mod_up(c, X.d, Y.d, n, level);
-  lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0}, false);
+  lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0}, false);
   lk::mod_up_copy_own(c, x_eval, x_stride, Y.d, n, level);
   Scratch U(c, (size_t)n * 2 * rows * N);
   lk::key_inner(c, Y.d, key, U.d, n, level);
@@ -117,7 +117,7 @@ static void key_switch(bgv_ctx* c, const uint64_t* key, const uint64_t* x_eval, 
             hipMemcpy2DAsync(Up.d, (size_t)K * N * 8, U.d + (size_t)level * N, (size_t)rows * N * 8, (size_t)K * N * 8,
                              (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
             "gather special");
-  lk::ntt(c, Up.d, n * 2 * K, LimbMap{K, 0, L, 0, 1, 0}, true);
+  lk::ntt(c, Up.d, n * 2 * K, LimbMap{K, 0, L, 0, 1, 0, 0}, true);
   Scratch DL(c, (size_t)n * 2 * level * N);
   lk::mod_down_delta(c, Up.d, DL.d, n, level, t_exp);
   op_ntt(c, DL.d, n * 2, level, false);
@@ -158,7 +158,7 @@ void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out) {
             hipMemcpy2DAsync(T.d, (size_t)N * 8, in.d + (size_t)(lv - 1) * N, (size_t)lv * N * 8, (size_t)N * 8,
                              (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
             "gather top");
-  lk::ntt(c, T.d, n * 2, LimbMap{1, 1, c->prm.L, 0, 1, lv - 1}, true);
+  lk::ntt(c, T.d, n * 2, LimbMap{1, 1, c->prm.L, 0, 1, lv - 1, 0}, true);
   Scratch W(c, (size_t)n * 2 * (lv - 1) * N);
   lk::msw_w(c, T.d, W.d, n, lv, in.t_exp);
   op_ntt(c, W.d, n * 2, lv - 1, false);
@@ -625,4 +625,38 @@ CipherP ev_rotate_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
   CipherP r = new_cipher(c, acc->v.n, acc->v.level, acc->v.t_exp);
   op_rotate(c, k, acc->v, galois_elt(c, BGV_ROW_SWAP), r->v);
   return ev_add(c, acc, r);
+}
+
+// [x < y] in the number space: reduce -> compare -> raise of x - y (of x alone if y is null)
+CipherP ev_less_than(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const CipherP& y) {
+  CipherP d = x;
+  if (y) {
+    // y is a batch of the same size or one ciphertext broadcast over x
+    if (y->v.n != x->v.n && y->v.n != 1) throw OpError{BGV_E_ARG};
+    d = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
+    op_add_sub(c, x->v, y->v, d->v, 1);
+  }
+  std::vector<CipherP> dg = ev_space_reduce(c, k, d);
+  return ev_space_raise(c, k, ev_compare(c, k, dg, BGV_OP_LT));
+}
+
+CipherP ev_batch_sum(bgv_ctx* c, const CipherP& x) {
+  CipherP r = new_cipher(c, 1, x->v.level, x->v.t_exp);
+  lk::batch_sum(c, x->v.d, r->v.d, x->v.n, x->v.level);
+  return r;
+}
+
+// SUM(b*c WHERE a < thr): [a < thr] * (b * c) per ciphertext, summed over the batch,
+// then rotate-and-sum over the slots.
+CipherP ev_filter_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& thr, const CipherP& b,
+                      const CipherP& cc) {
+  CipherP bc = ev_mul(c, k, b, cc);
+  CipherP lt = ev_less_than(c, k, a, thr);
+  CipherP prod = ev_mul(c, k, lt, bc);
+  return ev_rotate_sum(c, k, ev_batch_sum(c, prod));
+}
+
+CipherP ev_relu(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
+  CipherP lt = ev_less_than(c, k, x, nullptr);
+  return ev_mul(c, k, x, ev_const(c, ev_neg(c, lt), 1));
 }

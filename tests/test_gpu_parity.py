@@ -172,3 +172,31 @@ def test_rotate_sum_and_batch_equals_singles():
         single.level = ga.level
         ws = c.coeff_words(c.lib.mul_relin(c.keys, single, single))
         assert np.array_equal(ws[0], wb[b])
+
+
+def test_workload_glue_matches():
+    """bgv_mul, bgv_batch_sum, bgv_filter_sum and bgv_relu against the oracle's pipelines."""
+    c = pair_tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(12)
+    a_rows = g.integers(0, t, size=(2, P.ell))
+    b_rows = g.integers(0, 40, size=(2, P.ell))
+    c_rows = g.integers(0, 40, size=(2, P.ell))
+    ga, oa = c.enc_both(a_rows)
+    gb, ob = c.enc_both(b_rows)
+    gc, oc = c.enc_both(c_rows)
+    gt, ot = c.enc_both([[100] * P.ell])
+    m = c.lib.mul(c.keys, gb, gc)
+    c.assert_equal(m, [S._mul(P, c.okeys, x, y) for x, y in zip(ob, oc)], "mul")
+    bs = c.lib.batch_sum(gb)
+    c.assert_equal(bs, [B.add(P, ob[0], ob[1])], "batch_sum")
+    fs = c.lib.filter_sum(c.keys, ga, gt, gb, gc)
+    prods = [S.filter_product(P, c.okeys, x, ot[0], y, z) for x, y, z in zip(oa, ob, oc)]
+    ref = S.rotate_and_sum(P, c.okeys, B.add(P, prods[0], prods[1]))
+    c.assert_equal(fs, [ref], "filter_sum")
+    cen = lambda v: v - t if v > (t - 1) // 2 else v
+    expect = sum(int(y) * int(z) for ra, rb, rc in zip(a_rows, b_rows, c_rows)
+                 for x, y, z in zip(ra, rb, rc) if cen((int(x) - 100) % t) < 0) % t
+    assert np.array_equal(c.lib.decrypt(c.s, fs), np.array([[expect] * P.ell]))
+    r = c.lib.relu(c.keys, ga)
+    c.assert_equal(r, [S.relu(P, c.okeys, x) for x in oa], "relu")
