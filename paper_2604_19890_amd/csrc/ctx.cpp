@@ -296,6 +296,8 @@ void ctx_free(bgv_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   c->pool.release();
+  for (auto& kv : c->coeff_tabs) (void)hipFree(kv.second);
+  c->coeff_tabs.clear();
   void* ptrs[] = {c->d_prime, c->d_tw, c->d_itw, c->d_modup, c->d_moddown, c->d_msw, c->d_tconst};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

@@ -58,6 +58,9 @@ struct bgv_ctx {
   std::vector<int64_t> slot_exp;  // exponent e_j of slot j (root zeta^e_j)
   int64_t zeta = 0;
   std::vector<int64_t> encoder;   // [ell][ell] inverse Vandermonde of the slot roots mod p^r
+  // device tables of polynomial coefficients reduced mod every q_i ([D+1][L] doubles),
+  // keyed by (t_exp, coefficients)
+  std::map<std::pair<int, std::vector<int64_t>>, double*> coeff_tabs;
 
   size_t modup_inv_off(int level, int j) const {
     return ((size_t)(level * dnum + j)) * (size_t)alpha * (1 + Ltot);
@@ -111,6 +114,12 @@ void msw_final(bgv_ctx* c, const uint64_t* a, const uint64_t* w, uint64_t* out, 
 void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int to, int t_exp);
 // copy limb rows: y[b][c][i] = x[b][c][i] for i < to_level (x has from_level rows)
 void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from_level, int to_level, int comps);
+// out = sum_t sc[rows[t]][i] * xs[t] (+ sc[cst_row][i] on component 0); nt <= 16 terms, all at `level`
+void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, const double* sc, int sc_stride,
+             int cst_row, uint64_t* out, int n, int level);
+// product step with the modulus switch merged into ModDown (see kernels.hip)
+void ms_corr(bgv_ctx* c, const uint64_t* up, const uint64_t* tops, uint64_t* e, int n, int level, int t_exp);
+void ms_final(bgv_ctx* c, const uint64_t* d, const uint64_t* u, const uint64_t* e, uint64_t* out, int n, int level);
 // out (one ciphertext) = sum of the n ciphertexts of x
 void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level);
 // automorphism in evaluation form on n*2 polys of `level` limbs

@@ -324,6 +324,106 @@ __global__ void k_batch_sum(const uint64_t* __restrict__ x, uint64_t* __restrict
   out[(size_t)limb * N + n0] = to_u(acc, q, qinv);
 }
 
+// out[ct][c][i] = sum_t sc[row_t][i] * x_t[ct][c][i] (+ sc[cst_row][i] on component 0): the inner
+// sums of the polynomial evaluator in one pass (every term at the same level).
+struct LinTerms {
+  const uint64_t* x[16];
+  int row[16];
+};
+
+__global__ void k_lincomb(LinTerms terms, int nt, const double* __restrict__ sc, int sc_stride, int cst_row,
+                          uint64_t* __restrict__ out, int level, int N, const PrimeD* __restrict__ pc) {
+  const int limb = blockIdx.y;
+  const int i = limb % level;
+  const int comp = (limb / level) & 1;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t off = (size_t)limb * N + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    acc += mul_lazy(u2d(terms.x[t][off]), sc[(size_t)terms.row[t] * sc_stride + i], q, qinv);
+    if ((t & 3) == 3) acc = red(acc, q, qinv);
+  }
+  if (comp == 0 && cst_row >= 0) acc += sc[(size_t)cst_row * sc_stride + i];
+  out[off] = to_u(acc, q, qinv);
+}
+
+// Product step with the modulus switch merged into ModDown, part 1 (coefficient form).
+// For ciphertext ct and component c: from the special rows up [ct*2+c][K][N] the
+// ModDown correction wt_i = FBC_{P->Q}([u_P t^-1]_P) is formed for every q_i; the top
+// limb of the relinearised product in coefficient form is
+//   o_top = d_top + (u_top - t wt_top) P^-1,
+// its switch correction w = centered([o_top t^-1]_{q_top}), and the combined
+// correction e_i = t P^-1 wt_i + t w (mod q_i) for i < level-1 is written to e.
+// tops [2][n*2][N] holds u_top (first half) and d_top (second half).
+__global__ void k_ms_corr(const uint64_t* __restrict__ up, const uint64_t* __restrict__ tops,
+                          uint64_t* __restrict__ e, int n, int level, int N, int K, int Lfull,
+                          const double* __restrict__ md, const double* __restrict__ tinv,
+                          const double* __restrict__ tmod, const PrimeD* __restrict__ pc) {
+  const int cc = blockIdx.y;  // ct * 2 + comp
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double* phat_inv = md;
+  const double* phat_mod = md + K;
+  const double* pinv = md + K + (size_t)K * Lfull;
+  const uint64_t* U = up + (size_t)cc * K * N + n0;
+  double v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < K) {
+      const int pk = Lfull + k;
+      const double q = pc[pk].q, qinv = pc[pk].qinv;
+      const double w = canon(mul_lazy(u2d(U[(size_t)k * N]), tinv[pk], q, qinv), q);
+      v[k] = canon(mul_lazy(w, phat_inv[k], q, qinv), q);
+    } else {
+      v[k] = 0.0;
+    }
+  }
+  auto fbc = [&](int i, double q, double qinv) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < K) acc += mul_lazy(v[k], phat_mod[(size_t)k * Lfull + i], q, qinv);
+    return canon(red(acc, q, qinv), q);
+  };
+  const int it = level - 1;
+  double wms;
+  {
+    const double q = pc[it].q, qinv = pc[it].qinv;
+    const double wt = fbc(it, q, qinv);
+    const double ut = u2d(tops[(size_t)cc * N + n0]);
+    const double dt = u2d(tops[((size_t)n * 2 + cc) * N + n0]);
+    const double diff = red(ut - mul_lazy(wt, tmod[it], q, qinv), q, qinv);
+    const double o = canon(red(dt + mul_lazy(diff, pinv[it], q, qinv), q, qinv), q);
+    const double w = canon(mul_lazy(o, tinv[it], q, qinv), q);
+    wms = w > (q - 1.0) * 0.5 ? w - q : w;  // centered
+  }
+  uint64_t* E = e + (size_t)cc * (level - 1) * N + n0;
+  for (int i = 0; i < level - 1; ++i) {
+    const double q = pc[i].q, qinv = pc[i].qinv;
+    const double tp = mul_lazy(tmod[i], pinv[i], q, qinv);
+    const double a = mul_lazy(fbc(i, q, qinv), tp, q, qinv);
+    const double b = mul_lazy(wms < 0.0 ? wms + q : wms, tmod[i], q, qinv);
+    E[(size_t)i * N] = to_u(a + b, q, qinv);
+  }
+}
+
+// part 2 (evaluation form): out_i = (d_i + u_i P^-1 - e_i) q_top^-1 for i < level-1
+__global__ void k_ms_final(const uint64_t* __restrict__ d, const uint64_t* __restrict__ u,
+                           const uint64_t* __restrict__ e, uint64_t* __restrict__ out, int level, int N, int K,
+                           const double* __restrict__ pinv, const double* __restrict__ qinv_top,
+                           const PrimeD* __restrict__ pc) {
+  const int lv = level - 1;
+  const int i = blockIdx.y % lv;
+  const int cc = blockIdx.y / lv;
+  const int ct = cc >> 1, comp = cc & 1;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double dd = u2d(d[((size_t)ct * 3 * level + (size_t)comp * level + i) * N + n0]);
+  const double uu = u2d(u[((size_t)cc * (level + K) + i) * N + n0]);
+  const double ee = u2d(e[((size_t)cc * lv + i) * N + n0]);
+  const double s = red(dd - ee + mul_lazy(uu, pinv[i], q, qinv), q, qinv);
+  out[((size_t)cc * lv + i) * N + n0] = to_u(mul_lazy(s, qinv_top[i], q, qinv), q, qinv);
+}
+
 __device__ __forceinline__ uint32_t brv32(uint32_t v, int bits) { return __brev(v) >> (32 - bits); }
 
 // X -> X^g in evaluation form: slot j holds a(psi^(2 brv(j)+1)); the image holds
@@ -509,6 +609,29 @@ void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int
 void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from, int to, int comps) {
   hipLaunchKernelGGL(k_copy_rows, grid_for(c->N, n * comps * to), dim3(block_for(c->N)), 0, c->stream, x, y, from, to,
                      c->N);
+}
+
+void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, const double* sc, int sc_stride,
+             int cst_row, uint64_t* out, int n, int level) {
+  LinTerms t;
+  for (int i = 0; i < 16; ++i) {
+    t.x[i] = i < nt ? xs[i] : nullptr;
+    t.row[i] = i < nt ? rows[i] : 0;
+  }
+  hipLaunchKernelGGL(k_lincomb, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, t, nt, sc,
+                     sc_stride, cst_row, out, level, c->N, c->d_prime);
+}
+
+void ms_corr(bgv_ctx* c, const uint64_t* up, const uint64_t* tops, uint64_t* e, int n, int level, int t_exp) {
+  hipLaunchKernelGGL(k_ms_corr, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, up, tops, e, n, level,
+                     c->N, c->prm.K, c->prm.L, c->d_moddown, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
+                     c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
+}
+
+void ms_final(bgv_ctx* c, const uint64_t* d, const uint64_t* u, const uint64_t* e, uint64_t* out, int n, int level) {
+  const double* pinv = c->d_moddown + c->prm.K + (size_t)c->prm.K * c->prm.L;
+  hipLaunchKernelGGL(k_ms_final, grid_for(c->N, n * 2 * (level - 1)), dim3(block_for(c->N)), 0, c->stream, d, u, e,
+                     out, level, c->N, c->prm.K, pinv, c->d_msw + (size_t)(level - 1) * c->prm.L, c->d_prime);
 }
 
 void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level) {

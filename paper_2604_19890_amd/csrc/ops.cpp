@@ -94,10 +94,11 @@ void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out) {
   lk::mul_scalar(c, a.d, out.d, a.n, a.level, s);
 }
 
-// Hybrid key switching of the polynomial x (ciphertext b at x_eval + b * x_stride, [level][N]
-// evaluation form) under `key`; out[b][comp] = add[b][comp] (comp < add_comps) + switched[comp].
-static void key_switch(bgv_ctx* c, const uint64_t* key, const uint64_t* x_eval, int64_t x_stride, int n, int level,
-                       int t_exp, const uint64_t* add, int64_t add_stride, int add_comps, uint64_t* out) {
+// Hybrid key switching, first half: ModUp of each digit of the polynomial x
+// (ciphertext b at x_eval + b * x_stride, [level][N] evaluation form), NTT, and the
+// inner product with the key.  Returns u [n][2][level+K][N] in evaluation form.
+static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const uint64_t* x_eval, int64_t x_stride,
+                                         int n, int level) {
   const int N = c->N, K = c->prm.K, L = c->prm.L, A = c->alpha;
   const int dn = (level + A - 1) / A, rows = level + K;
   Scratch X(c, (size_t)n * level * N);
@@ -110,18 +111,65 @@ static void key_switch(bgv_ctx* c, const uint64_t* key, const uint64_t* x_eval, 
   lk::mod_up(c, X.d, Y.d, n, level);
   lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0}, false);
   lk::mod_up_copy_own(c, x_eval, x_stride, Y.d, n, level);
-  Scratch U(c, (size_t)n * 2 * rows * N);
-  lk::key_inner(c, Y.d, key, U.d, n, level);
-  Scratch Up(c, (size_t)n * 2 * K * N);
+  std::unique_ptr<Scratch> U(new Scratch(c, (size_t)n * 2 * rows * N));
+  lk::key_inner(c, Y.d, key, U->d, n, level);
+  return U;
+}
+
+// special rows of u -> coefficient form [n*2][K][N]
+static std::unique_ptr<Scratch> special_rows_coeff(bgv_ctx* c, const Scratch& U, int n, int level) {
+  const int N = c->N, K = c->prm.K, rows = level + K;
+  std::unique_ptr<Scratch> Up(new Scratch(c, (size_t)n * 2 * K * N));
   check_hip(c,
-            hipMemcpy2DAsync(Up.d, (size_t)K * N * 8, U.d + (size_t)level * N, (size_t)rows * N * 8, (size_t)K * N * 8,
+            hipMemcpy2DAsync(Up->d, (size_t)K * N * 8, U.d + (size_t)level * N, (size_t)rows * N * 8, (size_t)K * N * 8,
                              (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
             "gather special");
-  lk::ntt(c, Up.d, n * 2 * K, LimbMap{K, 0, L, 0, 1, 0, 0}, true);
+  lk::ntt(c, Up->d, n * 2 * K, LimbMap{K, 0, c->prm.L, 0, 1, 0, 0}, true);
+  return Up;
+}
+
+// Hybrid key switching of x under `key`; out[b][comp] = add[b][comp] (comp < add_comps) + switched[comp].
+static void key_switch(bgv_ctx* c, const uint64_t* key, const uint64_t* x_eval, int64_t x_stride, int n, int level,
+                       int t_exp, const uint64_t* add, int64_t add_stride, int add_comps, uint64_t* out) {
+  const int N = c->N;
+  auto U = ks_inner(c, key, x_eval, x_stride, n, level);
+  auto Up = special_rows_coeff(c, *U, n, level);
   Scratch DL(c, (size_t)n * 2 * level * N);
-  lk::mod_down_delta(c, Up.d, DL.d, n, level, t_exp);
+  lk::mod_down_delta(c, Up->d, DL.d, n, level, t_exp);
   op_ntt(c, DL.d, n * 2, level, false);
-  lk::mod_down_final(c, U.d, DL.d, add, add_comps == 2 ? add_stride : -add_stride, out, n, level, t_exp);
+  lk::mod_down_final(c, U->d, DL.d, add, add_comps == 2 ? add_stride : -add_stride, out, n, level, t_exp);
+}
+
+// Relinearised product followed by one modulus switch, with the switch merged into
+// ModDown: both corrections are formed in coefficient form and go through one NTT
+// (the transform is linear over every Z_q_i, so the words equal those of the
+// relinearised product followed by the separate switch).
+void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
+  const int n = a.n, lv = a.level, N = c->N, K = c->prm.K;
+  if (lv < 2) throw OpError{BGV_E_LEVEL};
+  const int rows = lv + K;
+  Scratch D(c, (size_t)n * 3 * lv * N);
+  lk::tensor(c, a.d, b.d, D.d, n, lv, b.n == 1 && n > 1);
+  const int64_t st = (int64_t)3 * lv * N;
+  auto U = ks_inner(c, keys->relin, D.d + (size_t)2 * lv * N, st, n, lv);
+  auto Up = special_rows_coeff(c, *U, n, lv);
+  // top limbs in coefficient form: u tops [n*2][N], then d tops [n*2][N]
+  Scratch Tp(c, (size_t)4 * n * N);
+  check_hip(c,
+            hipMemcpy2DAsync(Tp.d, (size_t)N * 8, U->d + (size_t)(lv - 1) * N, (size_t)rows * N * 8, (size_t)N * 8,
+                             (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
+            "gather u top");
+  for (int comp = 0; comp < 2; ++comp)
+    check_hip(c,
+              hipMemcpy2DAsync(Tp.d + ((size_t)2 * n + comp) * N, (size_t)2 * N * 8,
+                               D.d + ((size_t)comp * lv + (lv - 1)) * N, (size_t)3 * lv * N * 8, (size_t)N * 8,
+                               (size_t)n, hipMemcpyDeviceToDevice, c->stream),
+              "gather d top");
+  lk::ntt(c, Tp.d, 4 * n, LimbMap{1, 1, c->prm.L, 0, 1, lv - 1, 0}, true);
+  Scratch E(c, (size_t)n * 2 * (lv - 1) * N);
+  lk::ms_corr(c, Up->d, Tp.d, E.d, n, lv, a.t_exp);
+  op_ntt(c, E.d, n * 2, lv - 1, false);
+  lk::ms_final(c, D.d, U->d, E.d, out.d, n, lv);
 }
 
 void op_mul_relin(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
@@ -404,11 +452,9 @@ CipherP ev_mul(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& b
   if (a->v.t_exp != b->v.t_exp) throw OpError{BGV_E_PTXT_MOD};
   CipherP a2 = ev_align(c, a, lv), b2 = ev_align(c, b, lv);
   const int n = std::max(a->v.n, b->v.n);
-  CipherP m = new_cipher(c, n, lv, a->v.t_exp);
-  if (a2->v.n == 1 && n > 1) op_mul_relin(c, k, b2->v, a2->v, m->v);
-  else op_mul_relin(c, k, a2->v, b2->v, m->v);
   CipherP r = new_cipher(c, n, lv - 1, a->v.t_exp);
-  op_mod_switch(c, m->v, r->v);
+  if (a2->v.n == 1 && n > 1) op_mul_ms(c, k, b2->v, a2->v, r->v);
+  else op_mul_ms(c, k, a2->v, b2->v, r->v);
   return r;
 }
 
@@ -470,6 +516,23 @@ int eval_depth(int degree) {
   return lk2 + (g > 1 ? lg : 0) + 1;
 }
 
+// Device table [D+1][L] of the coefficients, each lifted to the centered range mod
+// t and reduced mod every q_i; built once per (t_exp, coefficients) and kept.
+static const double* coeff_table(bgv_ctx* c, int t_exp, const std::vector<int64_t>& cf) {
+  auto key = std::make_pair(t_exp, cf);
+  auto it = c->coeff_tabs.find(key);
+  if (it != c->coeff_tabs.end()) return it->second;
+  const int L = c->prm.L;
+  const int64_t t = c->tpow[t_exp];
+  std::vector<double> h(cf.size() * (size_t)L);
+  for (size_t r = 0; r < cf.size(); ++r) scalar_table(c, centered(cf[r], t), L, &h[r * L]);
+  double* d = nullptr;
+  check_hip(c, hipMalloc((void**)&d, h.size() * sizeof(double)), "coefficient table");
+  check_hip(c, hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice), "coefficient table");
+  c->coeff_tabs[key] = d;
+  return d;
+}
+
 // Baby-step/giant-step evaluation (Paterson-Stockmeyer, Theorem 2) with the
 // schedule: k = smallest power of two with 2k^2 >= D+1, g = ceil((D+1)/k);
 // baby powers x^2..x^k and giant powers y^2..y^(g-1) (y = x^k) by the power
@@ -492,6 +555,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   const int g = (D + kk) / kk;
   auto coef = [&](int n) -> int64_t { return n <= D ? cf[n] : 0; };
 
+  const double* tab = coeff_table(c, x->v.t_exp, cf);
   std::map<int, CipherP> baby;
   baby[1] = x;
   for (int i = 2; i <= kk; ++i) power(c, k, baby, i);
@@ -526,12 +590,25 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
     }
     int lv = 1 << 30;
     for (int i : used) lv = std::min(lv, baby[i]->v.level);
-    CipherP acc;
+    // sum_i c_{jk+i} x^i (+ c_{jk}) in one pass: the scalar products and additions
+    // are exact in every Z_q_i, so one linear combination gives the same words as
+    // the term-by-term accumulation
+    std::vector<CipherP> keep;
+    std::vector<const uint64_t*> xs;
+    std::vector<int> rws;
     for (int i : used) {
-      CipherP term = ev_scalar(c, aligned_power(i, lv), coef(j * kk + i));
-      acc = acc ? ev_add(c, acc, term) : term;
+      keep.push_back(aligned_power(i, lv));
+      xs.push_back(keep.back()->v.d);
+      rws.push_back(j * kk + i);
     }
-    if (cst != 0) acc = ev_const(c, acc, cst);
+    CipherP acc = new_cipher(c, x->v.n, lv, x->v.t_exp);
+    for (size_t s = 0; s < xs.size(); s += 16) {
+      const int nt = (int)std::min<size_t>(16, xs.size() - s);
+      CipherP part = s == 0 ? acc : new_cipher(c, x->v.n, lv, x->v.t_exp);
+      lk::lincomb(c, xs.data() + s, rws.data() + s, nt, tab, c->prm.L, (s == 0 && cst != 0) ? j * kk : -1,
+                  part->v.d, x->v.n, lv);
+      if (s > 0) op_add_sub(c, acc->v, part->v, acc->v, 0);
+    }
     inner[j] = Inner{false, 0, acc};
   }
   CipherP result;

@@ -52,6 +52,7 @@ void op_add_const(bgv_ctx* c, const CtV& a, int64_t k, const CtV& out);
 void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out);
 void op_mul_relin(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out);
 void op_rotate(bgv_ctx* c, const bgv_keys* keys, const CtV& in, int g, const CtV& out);
+void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out);  // product + one switch
 void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out);         // one prime
 void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out);  // repeated
 void op_copy(bgv_ctx* c, const CtV& in, const CtV& out);
