@@ -534,3 +534,14 @@ def encrypt_at(P: Params, s, slots, c1, e, idx) -> np.ndarray:
         c1s = R.negacyclic_dot_at(np.asarray(c1[i], dtype=np.uint64), s_res, q, idx)
         out[i] = (np.mod(me[idx], np.int64(q)).astype(np.uint64) + np.uint64(q) - c1s) % np.uint64(q)
     return out
+
+
+def sampled(P: Params, ct: Ct, idx) -> Ct:
+    """The columns idx of a ciphertext, as a ciphertext over a ring of len(idx) coefficients
+    (valid input for the coefficient-wise steps: add, mod_switch, mul_scalar)."""
+    return Ct(np.ascontiguousarray(ct.c[:, :, idx]), ct.level, ct.t_exp)
+
+
+def mod_switch_cols(P: Params, ct: Ct) -> Ct:
+    """mod_switch on a column-sampled ciphertext (coefficient-wise)."""
+    return mod_switch(_SubP(P, ct.c.shape[2]), ct)

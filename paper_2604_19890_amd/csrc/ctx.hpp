@@ -78,6 +78,11 @@ struct bgv_keys {
 
 // ------------------------------------------------------------------ launchers
 namespace lk {
+// true when the forward NTT has two passes (log N > 8), so the second can be fused
+bool ntt_fused_inner_ok(const bgv_ctx* c);
+// ModUp output y [n][dn][level+K][N] (coefficient form except the own-digit rows):
+// first NTT pass in place, then the second pass fused with the inner product -> u [n][2][level+K][N]
+void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* key, uint64_t* u, int n, int level);
 // NTT over n_limbs limbs of length N at d (limb l uses the prime given by lm).
 void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse);
 
@@ -89,8 +94,9 @@ void negate(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level);
 void mul_scalar(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);
 // add s_i to every word of component 0
 void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);
-// tensor: d [n][3][level][N] from a, b [n][2][level][N]
-void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, int n, int level, bool b_bcast);
+// tensor: d01 [n][2][level][N] (d0, d1) and d2 [n][level][N] from a, b [n][2][level][N]
+void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d01, uint64_t* d2, int n, int level,
+            bool b_bcast);
 // ModUp of the coefficient-form limbs x [n][level][N] -> y [n][dnum'][level+K][N] (coefficient form,
 // own-digit rows left untouched)
 void mod_up(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level);
@@ -122,8 +128,8 @@ void ms_corr(bgv_ctx* c, const uint64_t* up, const uint64_t* tops, uint64_t* e, 
 void ms_final(bgv_ctx* c, const uint64_t* d, const uint64_t* u, const uint64_t* e, uint64_t* out, int n, int level);
 // out (one ciphertext) = sum of the n ciphertexts of x
 void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level);
-// automorphism in evaluation form on n*2 polys of `level` limbs
-void automorph(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n_polys, int level, int g);
+// automorphism in evaluation form: for each of n ciphertexts, `rows` limbs at x + ct*xs -> y + ct*ys
+void automorph(bgv_ctx* c, const uint64_t* x, int64_t xs, uint64_t* y, int64_t ys, int n, int rows, int g);
 // signed small integers (int64 [N] per poly) -> residues [n_polys][rows][N] under primes given by lm
 void from_signed(bgv_ctx* c, const int64_t* v, uint64_t* y, int n_polys, int rows, LimbMap lm);
 // elementwise: out = a*b (+ sign * c*d) style helpers for encryption / keys

@@ -65,9 +65,9 @@ __global__ void k_add_const(const uint64_t* __restrict__ a, uint64_t* __restrict
   out[i] = d2u(x);
 }
 
-// d[b][0] = a0 b0, d[b][1] = a0 b1 + a1 b0, d[b][2] = a1 b1
+// d01[b][0] = a0 b0, d01[b][1] = a0 b1 + a1 b0, d2[b] = a1 b1
 __global__ void k_tensor(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b, uint64_t* __restrict__ d,
-                         int level, int N, int b_bcast, const PrimeD* __restrict__ pc) {
+                         uint64_t* __restrict__ d2, int level, int N, int b_bcast, const PrimeD* __restrict__ pc) {
   const int ct = blockIdx.y / level;
   const int i = blockIdx.y % level;
   const double q = pc[i].q, qinv = pc[i].qinv;
@@ -75,12 +75,12 @@ __global__ void k_tensor(const uint64_t* __restrict__ a, const uint64_t* __restr
   const size_t L2 = (size_t)level * N;
   const uint64_t* A = a + (size_t)ct * 2 * L2 + (size_t)i * N + n0;
   const uint64_t* B = b + (size_t)(b_bcast ? 0 : ct) * 2 * L2 + (size_t)i * N + n0;
-  uint64_t* D = d + (size_t)ct * 3 * L2 + (size_t)i * N + n0;
+  uint64_t* D = d + (size_t)ct * 2 * L2 + (size_t)i * N + n0;
   const double a0 = u2d(A[0]), a1 = u2d(A[L2]), b0 = u2d(B[0]), b1 = u2d(B[L2]);
   D[0] = d2u(canon(mul_lazy(a0, b0, q, qinv), q));
   const double m = mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv);
   D[L2] = d2u(canon(red(m, q, qinv), q));
-  D[2 * L2] = d2u(canon(mul_lazy(a1, b1, q, qinv), q));
+  d2[(size_t)ct * L2 + (size_t)i * N + n0] = d2u(canon(mul_lazy(a1, b1, q, qinv), q));
 }
 
 // ModUp: x [n][level][N] coefficient form -> y [n][dn][level+K][N].  For digit j
@@ -417,7 +417,7 @@ __global__ void k_ms_final(const uint64_t* __restrict__ d, const uint64_t* __res
   const int ct = cc >> 1, comp = cc & 1;
   const double q = pc[i].q, qinv = pc[i].qinv;
   const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double dd = u2d(d[((size_t)ct * 3 * level + (size_t)comp * level + i) * N + n0]);
+  const double dd = u2d(d[((size_t)ct * 2 * level + (size_t)comp * level + i) * N + n0]);
   const double uu = u2d(u[((size_t)cc * (level + K) + i) * N + n0]);
   const double ee = u2d(e[((size_t)cc * lv + i) * N + n0]);
   const double s = red(dd - ee + mul_lazy(uu, pinv[i], q, qinv), q, qinv);
@@ -428,14 +428,16 @@ __device__ __forceinline__ uint32_t brv32(uint32_t v, int bits) { return __brev(
 
 // X -> X^g in evaluation form: slot j holds a(psi^(2 brv(j)+1)); the image holds
 // a(psi^((2 brv(j)+1) g)), i.e. the input slot j' with 2 brv(j')+1 = (2 brv(j)+1) g mod 2N.
-__global__ void k_automorph(const uint64_t* __restrict__ x, uint64_t* __restrict__ y, int logN, int g) {
+__global__ void k_automorph(const uint64_t* __restrict__ x, int64_t xs, uint64_t* __restrict__ y, int64_t ys, int rows,
+                            int logN, int g) {
   const int N = 1 << logN;
-  const size_t limb = blockIdx.y;
+  const int ct = blockIdx.y / rows;
+  const int r = blockIdx.y % rows;
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t e = 2 * brv32(j, logN) + 1;
   const uint32_t e2 = (uint32_t)(((uint64_t)e * (uint32_t)g) & (uint32_t)(2 * N - 1));
   const uint32_t jp = brv32((e2 - 1) >> 1, logN);
-  y[limb * N + j] = x[limb * N + jp];
+  y[(size_t)ct * ys + (size_t)r * N + j] = x[(size_t)ct * xs + (size_t)r * N + jp];
 }
 
 __global__ void k_from_signed(const int64_t* __restrict__ v, uint64_t* __restrict__ y, int rows, int N, LimbMap lm,
@@ -536,9 +538,9 @@ void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, c
                      c->N, t, c->d_prime);
 }
 
-void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, int n, int level, bool bb) {
-  hipLaunchKernelGGL(k_tensor, grid_for(c->N, n * level), dim3(block_for(c->N)), 0, c->stream, a, b, d, level, c->N,
-                     bb ? 1 : 0, c->d_prime);
+void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, uint64_t* d2, int n, int level, bool bb) {
+  hipLaunchKernelGGL(k_tensor, grid_for(c->N, n * level), dim3(block_for(c->N)), 0, c->stream, a, b, d, d2, level,
+                     c->N, bb ? 1 : 0, c->d_prime);
 }
 
 void mod_up(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level) {
@@ -639,9 +641,9 @@ void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level) {
                      c->N, c->d_prime);
 }
 
-void automorph(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n_polys, int level, int g) {
-  hipLaunchKernelGGL(k_automorph, grid_for(c->N, n_polys * level), dim3(block_for(c->N)), 0, c->stream, x, y, c->logN,
-                     g);
+void automorph(bgv_ctx* c, const uint64_t* x, int64_t xs, uint64_t* y, int64_t ys, int n, int rows, int g) {
+  hipLaunchKernelGGL(k_automorph, grid_for(c->N, n * rows), dim3(block_for(c->N)), 0, c->stream, x, xs, y, ys, rows,
+                     c->logN, g);
 }
 
 void from_signed(bgv_ctx* c, const int64_t* v, uint64_t* y, int n_polys, int rows, LimbMap lm) {

@@ -164,6 +164,88 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
   for (int i = 0; i < 16; ++i) xp[(size_t)i << gs1_log] = d2u(canon(red(v[i], q, qinv), q));
 }
 
+// Second forward pass fused with the key-switching inner product.  Launch over
+// (row block, ciphertext) x target row m of the ModUp output y [n][dn][rows][N],
+// whose first pass is done (rows of a digit's own primes are already in
+// evaluation form and are used as they are).  For every digit j the block
+// finishes the transform of y[ct][j][m] in registers and LDS, multiplies it by
+// key[j][comp][prime(m)] and accumulates; u[ct][comp][m] receives the sums.
+template <int LOGS>
+__global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __restrict__ y,
+                                                           const uint64_t* __restrict__ key,
+                                                           uint64_t* __restrict__ u, int logN, int s0, int level,
+                                                           int dn, int K, int alpha, int Lfull, int Ltot, int n_ct,
+                                                           const PrimeD* __restrict__ pc,
+                                                           const double* __restrict__ tw) {
+  constexpr int S = 1 << LOGS;
+  constexpr int T = S / 16;
+  constexpr int T_LOG = LOGS - 4;
+  __shared__ double lds[NT_MAX * 16 + NT_MAX + NT_MAX];
+  const int N = 1 << logN;
+  const int NT = blockDim.x;
+  const int SUBS = NT / T;
+  const int m = blockIdx.y;
+  const int rows = level + K;
+  const int ct = blockIdx.x % n_ct;
+  const int rb = blockIdx.x / n_ct;
+  const int pm = m < level ? m : Lfull + (m - level);
+  const double q = pc[pm].q, qinv = pc[pm].qinv;
+  const double* __restrict__ w = tw + (size_t)pm * N;
+  const int tmax_log = logN - s0 - 1;  // tmin = 1 in the second pass
+  const int tau = threadIdx.x % T;
+  const int sl = threadIdx.x / T;
+  const int st = rb * SUBS + sl;
+  const int base = st << (tmax_log + 1);
+  const int g1 = base + tau;
+  const int gs1_log = T_LOG;
+  const int g2 = base + 16 * tau;
+  double acc0[16], acc1[16], v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = 0.0;
+  for (int j = 0; j < dn; ++j) {
+    const uint64_t* __restrict__ yp = y + (((size_t)ct * dn + j) * rows + m) * N + g1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = u2d(yp[(size_t)i << gs1_log]);
+    const bool own = m < level && m / alpha == j;
+    if (!own) {
+      ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+      ct_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, 0, q, qinv);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
+      __syncthreads();  // the next digit writes the same LDS rows
+    }
+    const uint64_t* __restrict__ kb = key + (((size_t)j * 2 + 0) * Ltot + pm) * N + g1;
+    const uint64_t* __restrict__ ka = key + (((size_t)j * 2 + 1) * Ltot + pm) * N + g1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      acc0[i] += mul_lazy(v[i], u2d(kb[(size_t)i << gs1_log]), q, qinv);
+      acc1[i] += mul_lazy(v[i], u2d(ka[(size_t)i << gs1_log]), q, qinv);
+    }
+    if ((j & 3) == 3) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        acc0[i] = red(acc0[i], q, qinv);
+        acc1[i] = red(acc1[i], q, qinv);
+      }
+    }
+  }
+  uint64_t* __restrict__ u0 = u + ((size_t)ct * 2 * rows + m) * N + g1;
+  uint64_t* __restrict__ u1 = u0 + (size_t)rows * N;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    u0[(size_t)i << gs1_log] = to_u(acc0[i], q, qinv);
+    u1[(size_t)i << gs1_log] = to_u(acc1[i], q, qinv);
+  }
+}
+
 template <bool INV>
 void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int s0, int last) {
   const int N = c->N;
@@ -193,6 +275,36 @@ void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int
 }  // namespace
 
 namespace lk {
+
+bool ntt_fused_inner_ok(const bgv_ctx* c) { return c->logN > 8; }
+
+void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* key, uint64_t* u, int n, int level) {
+  const int logN = c->logN;
+  const int p1 = (logN + 1) / 2, p2 = logN - p1;
+  const int A = c->alpha, K = c->prm.K, L = c->prm.L;
+  const int dn = (level + A - 1) / A, rows = level + K;
+  // first pass over the non-own rows
+  launch_pass<false>(c, y, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0}, p1, 0, 0);
+  const int N = c->N, S = 1 << p2, T = S / 16;
+  const int NT = N / 16 < NT_MAX ? N / 16 : NT_MAX;
+  const int SUBS = NT / T;
+  dim3 grid(((N / S) / SUBS) * n, rows);
+  switch (p2) {
+#define CASE2(LS)                                                                                              \
+  case LS:                                                                                                     \
+    hipLaunchKernelGGL((k_ntt2_key_inner<LS>), grid, dim3(NT), 0, c->stream, y, key, u, logN, p1, level, dn, K, A, \
+                       L, c->Ltot, n, c->d_prime, c->d_tw);                                                    \
+    break;
+    CASE2(4)
+    CASE2(5)
+    CASE2(6)
+    CASE2(7)
+    CASE2(8)
+#undef CASE2
+    default:
+      break;
+  }
+}
 
 void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse) {
   if (n_limbs <= 0) return;

@@ -95,24 +95,22 @@ void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out) {
 }
 
 // Hybrid key switching, first half: ModUp of each digit of the polynomial x
-// (ciphertext b at x_eval + b * x_stride, [level][N] evaluation form), NTT, and the
-// inner product with the key.  Returns u [n][2][level+K][N] in evaluation form.
-static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const uint64_t* x_eval, int64_t x_stride,
-                                         int n, int level) {
+// (X = [n][level][N] in evaluation form; overwritten), NTT, and the inner product
+// with the key.  Returns u [n][2][level+K][N] in evaluation form.
+static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, Scratch& X, int n, int level) {
   const int N = c->N, K = c->prm.K, L = c->prm.L, A = c->alpha;
   const int dn = (level + A - 1) / A, rows = level + K;
-  Scratch X(c, (size_t)n * level * N);
-  check_hip(c,
-            hipMemcpy2DAsync(X.d, (size_t)level * N * 8, x_eval, (size_t)x_stride * 8, (size_t)level * N * 8, n,
-                             hipMemcpyDeviceToDevice, c->stream),
-            "gather");
-  op_ntt(c, X.d, n, level, true);
   Scratch Y(c, (size_t)n * dn * rows * N);
+  lk::mod_up_copy_own(c, X.d, (int64_t)level * N, Y.d, n, level);  // the digit's own rows stay as they are
+  op_ntt(c, X.d, n, level, true);
   lk::mod_up(c, X.d, Y.d, n, level);
-  lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0}, false);
-  lk::mod_up_copy_own(c, x_eval, x_stride, Y.d, n, level);
   std::unique_ptr<Scratch> U(new Scratch(c, (size_t)n * 2 * rows * N));
-  lk::key_inner(c, Y.d, key, U->d, n, level);
+  if (lk::ntt_fused_inner_ok(c)) {
+    lk::ntt_pass1_key_inner(c, Y.d, key, U->d, n, level);
+  } else {
+    lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0}, false);
+    lk::key_inner(c, Y.d, key, U->d, n, level);
+  }
   return U;
 }
 
@@ -128,11 +126,11 @@ static std::unique_ptr<Scratch> special_rows_coeff(bgv_ctx* c, const Scratch& U,
   return Up;
 }
 
-// Hybrid key switching of x under `key`; out[b][comp] = add[b][comp] (comp < add_comps) + switched[comp].
-static void key_switch(bgv_ctx* c, const uint64_t* key, const uint64_t* x_eval, int64_t x_stride, int n, int level,
-                       int t_exp, const uint64_t* add, int64_t add_stride, int add_comps, uint64_t* out) {
+// Hybrid key switching of X under `key`; out[b][comp] = add[b][comp] (comp < add_comps) + switched[comp].
+static void key_switch(bgv_ctx* c, const uint64_t* key, Scratch& X, int n, int level, int t_exp, const uint64_t* add,
+                       int64_t add_stride, int add_comps, uint64_t* out) {
   const int N = c->N;
-  auto U = ks_inner(c, key, x_eval, x_stride, n, level);
+  auto U = ks_inner(c, key, X, n, level);
   auto Up = special_rows_coeff(c, *U, n, level);
   Scratch DL(c, (size_t)n * 2 * level * N);
   lk::mod_down_delta(c, Up->d, DL.d, n, level, t_exp);
@@ -148,10 +146,9 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   const int n = a.n, lv = a.level, N = c->N, K = c->prm.K;
   if (lv < 2) throw OpError{BGV_E_LEVEL};
   const int rows = lv + K;
-  Scratch D(c, (size_t)n * 3 * lv * N);
-  lk::tensor(c, a.d, b.d, D.d, n, lv, b.n == 1 && n > 1);
-  const int64_t st = (int64_t)3 * lv * N;
-  auto U = ks_inner(c, keys->relin, D.d + (size_t)2 * lv * N, st, n, lv);
+  Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
+  lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1);
+  auto U = ks_inner(c, keys->relin, X, n, lv);
   auto Up = special_rows_coeff(c, *U, n, lv);
   // top limbs in coefficient form: u tops [n*2][N], then d tops [n*2][N]
   Scratch Tp(c, (size_t)4 * n * N);
@@ -162,7 +159,7 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   for (int comp = 0; comp < 2; ++comp)
     check_hip(c,
               hipMemcpy2DAsync(Tp.d + ((size_t)2 * n + comp) * N, (size_t)2 * N * 8,
-                               D.d + ((size_t)comp * lv + (lv - 1)) * N, (size_t)3 * lv * N * 8, (size_t)N * 8,
+                               D.d + ((size_t)comp * lv + (lv - 1)) * N, (size_t)2 * lv * N * 8, (size_t)N * 8,
                                (size_t)n, hipMemcpyDeviceToDevice, c->stream),
               "gather d top");
   lk::ntt(c, Tp.d, 4 * n, LimbMap{1, 1, c->prm.L, 0, 1, lv - 1, 0}, true);
@@ -174,10 +171,9 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
 
 void op_mul_relin(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
   const int n = a.n, lv = a.level, N = c->N;
-  Scratch D(c, (size_t)n * 3 * lv * N);
-  lk::tensor(c, a.d, b.d, D.d, n, lv, b.n == 1 && n > 1);
-  const int64_t st = (int64_t)3 * lv * N;
-  key_switch(c, keys->relin, D.d + (size_t)2 * lv * N, st, n, lv, a.t_exp, D.d, st, 2, out.d);
+  Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
+  lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1);
+  key_switch(c, keys->relin, X, n, lv, a.t_exp, D.d, (int64_t)2 * lv * N, 2, out.d);
 }
 
 int galois_elt(const bgv_ctx* c, int step) {
@@ -192,10 +188,11 @@ void op_rotate(bgv_ctx* c, const bgv_keys* keys, const CtV& in, int g, const CtV
   const int n = in.n, lv = in.level, N = c->N;
   auto it = keys->galois.find(g);
   if (it == keys->galois.end()) throw OpError{BGV_E_NOKEY};
-  Scratch R(c, (size_t)n * 2 * lv * N);
-  lk::automorph(c, in.d, R.d, n * 2, lv, g);
+  Scratch R(c, (size_t)n * lv * N), X(c, (size_t)n * lv * N);
   const int64_t st = (int64_t)2 * lv * N;
-  key_switch(c, it->second, R.d + (size_t)lv * N, st, n, lv, in.t_exp, R.d, st, 1, out.d);
+  lk::automorph(c, in.d, st, R.d, (int64_t)lv * N, n, lv, g);              // X -> X^g on c0
+  lk::automorph(c, in.d + (size_t)lv * N, st, X.d, (int64_t)lv * N, n, lv, g);  // and on c1
+  key_switch(c, it->second, X, n, lv, in.t_exp, R.d, (int64_t)lv * N, 1, out.d);
 }
 
 void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out) {
@@ -407,7 +404,7 @@ bgv_status op_keygen(bgv_ctx* c, const int8_t* s, const uint64_t* a, const int32
     if (kidx == 0) {
       lk::mul_pointwise(c, S.d, S.d, Sp.d, Lt, lm_chain(c, Lt), 0);
     } else {
-      lk::automorph(c, S.d, Sp.d, 1, Lt, gal[kidx - 1]);
+      lk::automorph(c, S.d, 0, Sp.d, 0, 1, Lt, gal[kidx - 1]);
     }
     check_hip(c, hipMemcpyAsync(A.d, a + (size_t)kidx * dn * Lt * N, (size_t)dn * Lt * N * 8, hipMemcpyHostToDevice,
                                 c->stream),
@@ -556,12 +553,39 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   auto coef = [&](int n) -> int64_t { return n <= D ? cf[n] : 0; };
 
   const double* tab = coeff_table(c, x->v.t_exp, cf);
+  // Only the powers some term uses (and the factors the power rule builds them
+  // from) are computed; each of them is the same product chain as in the full
+  // table, so skipping the unused ones leaves every output word unchanged.
+  std::vector<char> need_b(kk + 1, 0), need_g(std::max(g, 2), 0);
+  need_b[kk] = 1;
+  for (int j = 0; j < g; ++j) {
+    bool any = false;
+    for (int i = 1; i < kk; ++i)
+      if (coef(j * kk + i) != 0) {
+        need_b[i] = 1;
+        any = true;
+      }
+    if (j >= 1 && (any || coef(j * kk) != 0)) need_g[j] = 1;
+  }
+  auto close = [](std::vector<char>& need) {
+    for (int i = (int)need.size() - 1; i >= 2; --i) {
+      if (!need[i]) continue;
+      int h = 1;
+      while (2 * h <= i) h *= 2;
+      if (i == h) need[i / 2] = 1;
+      else need[h] = need[i - h] = 1;
+    }
+  };
+  close(need_b);
+  close(need_g);
   std::map<int, CipherP> baby;
   baby[1] = x;
-  for (int i = 2; i <= kk; ++i) power(c, k, baby, i);
+  for (int i = 2; i <= kk; ++i)
+    if (need_b[i]) power(c, k, baby, i);
   std::map<int, CipherP> giant;
   giant[1] = baby[kk];
-  for (int j = 2; j < g; ++j) power(c, k, giant, j);
+  for (int j = 2; j < g; ++j)
+    if (need_g[j]) power(c, k, giant, j);
 
   std::map<std::pair<int, int>, CipherP> aligned;
   auto aligned_power = [&](int i, int lv) -> CipherP {
@@ -630,7 +654,8 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   }
   if (giant_out) {
     giant_out->assign(g, nullptr);
-    for (int j = 1; j < g; ++j) (*giant_out)[j] = giant[j];
+    for (int j = 1; j < g; ++j)
+      if (giant.count(j)) (*giant_out)[j] = giant[j];
     *giant_k = kk;
   }
   return result;
@@ -674,7 +699,7 @@ CipherP ev_compare(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& di
     if (i == r - 1 && r > 1) {
       // x^(p-1) is the last giant power when (g-1) k = p-1 (same products as the power rule)
       const int g = (int)giants.size();
-      if (g > 1 && (g - 1) * kk == p - 1) eq = eq_from_power(c, giants[g - 1]);
+      if (g > 1 && (g - 1) * kk == p - 1 && giants[g - 1]) eq = eq_from_power(c, giants[g - 1]);
       else eq = eq_digit(digits[i]);
     }
   }

@@ -22,7 +22,7 @@ def log(*a):
 
 
 class Pair:
-    def __init__(self, logN, p, r, L, K, steps=(), conj=False, seed=0, oracle_keys=True):
+    def __init__(self, logN, p, r, L, K, steps=(), conj=False, seed=0, oracle_keys=True, hw=None):
         from paper_2604_19890_amd import bgv as G
         self.G = G
         log(f"[ctx] N=2^{logN} p={p} r={r} L={L} K={K}")
@@ -32,7 +32,8 @@ class Pair:
         assert self.lib.slots == self.P.ell
         self.N = self.P.N
         self.seed = seed
-        self.s = synth.ternary(self.N, seed, WL)
+        # uniform ternary secret, or the sparse one (Hamming weight hw) of the paper's parameter section
+        self.s = synth.ternary(self.N, seed, WL) if hw is None else synth.ternary_hw(self.N, hw, seed, WL)
         self.steps = list(steps)
         self.conj = conj
         n_keys = 1 + len(steps) + (1 if conj else 0)
@@ -90,3 +91,9 @@ def pair_hybrid17():
 @functools.lru_cache(maxsize=None)
 def pair_tiny5():
     return Pair(4, 5, 2, 12, 1, steps=(), conj=True)
+
+
+@functools.lru_cache(maxsize=None)
+def pair_two_pass():
+    """A ring large enough for the two-pass NTT (and its fused key-switching pass), with 2-prime digits."""
+    return Pair(10, 17, 2, 6, 2, steps=(1,), conj=True)

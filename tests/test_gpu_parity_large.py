@@ -1,0 +1,86 @@
+"""GPU parity on rings with the two-pass NTT (and the fused key-switching pass), the tiny
+workload end to end at N = 4096, and sampled checks at the real sizes N = 2^15 and 2^16."""
+import numpy as np
+import pytest
+
+from oracle import bgv as B
+from oracle import space as S
+from tests.gpu_ctx import Pair, log, pair_two_pass
+
+pytestmark = pytest.mark.gpu
+
+
+def test_two_pass_ring_operations_match():
+    c = pair_two_pass()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(21)
+    ga, oa = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    c.assert_equal(c.lib.mul_relin(c.keys, ga, gb), [B.mul_relin(P, c.okeys.relin, x, y) for x, y in zip(oa, ob)],
+                   "mul_relin N=1024")
+    c.assert_equal(c.lib.mul(c.keys, ga, gb), [S._mul(P, c.okeys, x, y) for x, y in zip(oa, ob)], "mul N=1024")
+    c.assert_equal(c.lib.rotate(c.keys, ga, 1), [B.rotate(P, c.okeys.galois, x, 1) for x in oa], "rotate N=1024")
+    c.assert_equal(c.lib.rotate(c.keys, ga, c.G.ROW_SWAP), [B.rotate(P, c.okeys.galois, x, "conj") for x in oa],
+                   "conj N=1024")
+    c.assert_equal(c.lib.mod_switch_to(ga, 2), [B.align(P, x, 2) for x in oa], "mod_switch_to N=1024")
+    coeffs = [int(v) for v in g.integers(0, t, size=6)]
+    c.assert_equal(c.lib.eval_poly(c.keys, ga, coeffs), [S.eval_poly(P, c.okeys, x, coeffs) for x in oa],
+                   "eval_poly N=1024")
+
+
+def test_tiny_workload_end_to_end_n4096():
+    """v * [x < y] with N = 4096, p = 17, 18 primes + 1 special prime: every word of the result."""
+    c = Pair(12, 17, 2, 18, 1)
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(0)
+    xs, ys, vs = (g.integers(0, 17, size=(1, P.ell)) for _ in range(3))
+    gx, ox = c.enc_both(xs)
+    gy, oy = c.enc_both(ys)
+    gv, ov = c.enc_both(vs)
+    lt = c.lib.less_than(c.keys, gx, gy)
+    out = c.lib.mul(c.keys, lt, gv)
+    log("[e2e] oracle pipeline at N=4096 ...")
+    ref = S.masked_product(P, c.okeys, ox[0], oy[0], ov[0])
+    c.assert_equal(out, [ref], "masked product N=4096")
+    expect = [int(v) if a < b else 0 for v, a, b in zip(vs[0], xs[0], ys[0])]
+    assert list(c.lib.decrypt(c.s, out)[0]) == expect
+    assert out.level >= 1
+
+
+def _sampled_words(c, gct, idx):
+    w = c.coeff_words(gct)
+    return w[:, :, :, idx]
+
+
+@pytest.mark.parametrize("shape", [(15, 257, 2, 16, 4, 16), (16, 257, 2, 30, 6, 8)])
+def test_full_size_products_sampled(shape):
+    """mul_relin, the product step and a rotation at N = 2^15 (L = 16, K = 4) and N = 2^16
+    (L = 30, K = 6, taken at a lower level), compared on sampled coefficients.  The secret has
+    Hamming weight 120 (the paper's parameter) so that the oracle's key generation stays fast."""
+    logN, p, r, L, K, lv = shape
+    log(f"[full] logN={logN} L={L} K={K} level={lv}")
+    c = Pair(logN, p, r, L, K, steps=(1,), conj=False, hw=120)
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(logN)
+    ga, oa = c.enc_both(g.integers(0, t, size=(1, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(1, P.ell)))
+    idx = np.array([0, 1, 4097, P.N // 2 + 3, P.N - 1])
+    # encryption on sampled columns
+    assert np.array_equal(_sampled_words(c, ga, idx)[0], B.sampled(P, oa[0], idx).c)
+    if lv < L:
+        ga, gb = c.lib.mod_switch_to(ga, lv), c.lib.mod_switch_to(gb, lv)
+        oa = [B.align(P, oa[0], lv)]
+        ob = [B.align(P, ob[0], lv)]
+        assert np.array_equal(_sampled_words(c, ga, idx)[0], B.sampled(P, oa[0], idx).c)
+    log("[full] oracle mul_relin at sampled columns ...")
+    ref = B.mul_relin_at(P, c.okeys.relin, oa[0], ob[0], idx)
+    got = c.lib.mul_relin(c.keys, ga, gb)
+    assert np.array_equal(_sampled_words(c, got, idx)[0], ref), "mul_relin"
+    prod = c.lib.mul(c.keys, ga, gb)
+    ref_ms = B.mod_switch_cols(P, B.Ct(ref, lv, oa[0].t_exp))
+    assert np.array_equal(_sampled_words(c, prod, idx)[0], ref_ms.c), "product step (merged switch)"
+    rot = c.lib.rotate(c.keys, ga, 1)
+    assert np.array_equal(_sampled_words(c, rot, idx)[0], B.rotate_at(P, c.okeys.galois, oa[0], 1, idx)), "rotate"
+    # and the semantics at full size
+    ta, tb = c.lib.decrypt(c.s, ga)[0], c.lib.decrypt(c.s, gb)[0]
+    assert np.array_equal(c.lib.decrypt(c.s, prod)[0], (ta.astype(object) * tb.astype(object)) % t)
