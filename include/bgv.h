@@ -105,6 +105,10 @@ bgv_status bgv_ctx_primes(const bgv_ctx* ctx, uint64_t* out);
 int64_t bgv_ct_words(const bgv_ctx* ctx, int32_t level);
 bgv_status bgv_sync(bgv_ctx* ctx);
 const char* bgv_last_error(const bgv_ctx* ctx);
+/* bgv_trim: synchronise the stream and free the context's cached scratch buffers
+ * (device memory the library keeps for reuse between operations); `held_bytes`, if not
+ * NULL, receives the bytes still held (buffers in use) afterwards.                  */
+bgv_status bgv_trim(bgv_ctx* ctx, int64_t* held_bytes);
 
 /* ---- keys ----------------------------------------------------------------
  * Hybrid key-switching keys (digit j = primes j*alpha .. min((j+1)*alpha, L)-1):
@@ -212,6 +216,12 @@ bgv_status bgv_batch_sum(bgv_ctx* ctx, const bgv_ct* in, bgv_ct* out);
 bgv_status bgv_filter_sum(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* a, const bgv_ct* thr, const bgv_ct* b,
                           const bgv_ct* c, bgv_ct* out);
 bgv_status bgv_relu(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* x, bgv_ct* out);
+/* bgv_filter_products: the per-ciphertext part of bgv_filter_sum, [a < thr] * (b * c) for
+ *   each ciphertext of the batch (no sum, no rotation); thr is one ciphertext or a batch of
+ *   the same size.  A serving loop sums the products of each query itself, so ciphertexts of
+ *   several queries can share one batch.                                                   */
+bgv_status bgv_filter_products(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* a, const bgv_ct* thr,
+                               const bgv_ct* b, const bgv_ct* c, bgv_ct* out);
 
 /* ---- tuning ---------------------------------------------------------------
  * bgv_set_ntt_chunk: two-pass NTTs over many limbs run in chunks of `limbs`

@@ -87,8 +87,10 @@ _sigs = {
     "bgv_batch_sum": [_vp, _P(_Ct), _P(_Ct)],
     "bgv_filter_sum": [_vp, _vp, _P(_Ct), _P(_Ct), _P(_Ct), _P(_Ct), _P(_Ct)],
     "bgv_relu": [_vp, _vp, _P(_Ct), _P(_Ct)],
+    "bgv_filter_products": [_vp, _vp, _P(_Ct), _P(_Ct), _P(_Ct), _P(_Ct), _P(_Ct)],
     "bgv_ntt": [_vp, _vp, _i64, _i32, _i32, _i32],
     "bgv_set_ntt_chunk": [_vp, _i32],
+    "bgv_trim": [_vp, _vp],
     "bgv_get_ntt_chunk": [_vp],
 }
 for _name, _args in _sigs.items():
@@ -189,8 +191,33 @@ class Context:
         t = torch.from_numpy(w.reshape(-1).view(np.int64)).to(self.device)
         return Ct(t, n, level, t_exp)
 
+    def view(self, ct: Ct, start: int, count: int) -> Ct:
+        """Ciphertexts start .. start+count-1 of a batch, sharing its memory."""
+        per = self.words(ct.level)
+        return Ct(ct.tensor[start * per:(start + count) * per], count, ct.level, ct.t_exp)
+
+    def concat(self, parts, out: Ct = None) -> Ct:
+        """Copy batches of equal level and t_exp into one contiguous batch."""
+        n = sum(p.n for p in parts)
+        lv, te = parts[0].level, parts[0].t_exp
+        out = out or self.empty(n, lv, te)
+        per = self.words(lv)
+        pos = 0
+        for p in parts:
+            assert p.level == lv and p.t_exp == te
+            out.tensor[pos * per:(pos + p.n) * per].copy_(p.tensor[:p.n * per])
+            pos += p.n
+        out.n, out.level, out.t_exp = n, lv, te
+        return out
+
     def sync(self):
         self._check(_lib.bgv_sync(self.handle))
+
+    def trim(self) -> int:
+        """Free the library's cached scratch; returns the bytes still in use."""
+        held = ctypes.c_int64()
+        self._check(_lib.bgv_trim(self.handle, ctypes.byref(held)))
+        return held.value
 
     # ------------------------------------------------------------------ keys and encryption
     def keygen(self, s, a, e, steps=(), with_conj=False) -> Keys:
@@ -342,6 +369,13 @@ class Context:
         out = self._out(out, 1, a.level, a.t_exp)
         s = [x._struct() for x in (a, thr, b, c, out)]
         self._check(_lib.bgv_filter_sum(self.handle, keys.handle, *[ctypes.byref(x) for x in s]))
+        out._update(s[-1])
+        return out
+
+    def filter_products(self, keys, a, thr, b, c, out=None):
+        out = self._out(out, a.n, a.level, a.t_exp)
+        s = [x._struct() for x in (a, thr, b, c, out)]
+        self._check(_lib.bgv_filter_products(self.handle, keys.handle, *[ctypes.byref(x) for x in s]))
         out._update(s[-1])
         return out
 

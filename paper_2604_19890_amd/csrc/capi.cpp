@@ -402,9 +402,8 @@ BGV_EXPORT bgv_status bgv_batch_sum(bgv_ctx* c, const bgv_ct* in, bgv_ct* out) {
   return guarded(c, [&] { return deliver(c, ev_batch_sum(c, borrow(in)), out); });
 }
 
-BGV_EXPORT bgv_status bgv_filter_sum(bgv_ctx* c, const bgv_keys* k, const bgv_ct* a, const bgv_ct* thr,
-                                     const bgv_ct* b, const bgv_ct* cc, bgv_ct* out) {
-  NEED_CTX(c);
+static bgv_status filter_check(bgv_ctx* c, const bgv_keys* k, const bgv_ct* a, const bgv_ct* thr, const bgv_ct* b,
+                               const bgv_ct* cc) {
   if (!k || !k->relin) return fail(c, BGV_E_NOKEY, "no keys");
   CHECK(check_in(c, a, "null a"));
   CHECK(check_in(c, thr, "null thr"));
@@ -414,10 +413,26 @@ BGV_EXPORT bgv_status bgv_filter_sum(bgv_ctx* c, const bgv_keys* k, const bgv_ct
     return fail(c, BGV_E_PTXT_MOD, "the query runs on t = p^2 inputs");
   if (b->n != a->n || cc->n != a->n || (thr->n != 1 && thr->n != a->n)) return fail(c, BGV_E_ARG, "batch sizes differ");
   if (a->level != thr->level) return fail(c, BGV_E_LEVEL, "a and thr at different levels");
+  return BGV_OK;
+}
+
+BGV_EXPORT bgv_status bgv_filter_sum(bgv_ctx* c, const bgv_keys* k, const bgv_ct* a, const bgv_ct* thr,
+                                     const bgv_ct* b, const bgv_ct* cc, bgv_ct* out) {
+  NEED_CTX(c);
+  CHECK(filter_check(c, k, a, thr, b, cc));
   for (int i = 1; i < c->ell / 2; i *= 2)
     if (!k->galois.count(galois_elt(c, i))) return fail(c, BGV_E_NOKEY, "missing a power-of-two rotation key");
   if (!k->galois.count(galois_elt(c, BGV_ROW_SWAP))) return fail(c, BGV_E_NOKEY, "missing the row-swap key");
   return guarded(c, [&] { return deliver(c, ev_filter_sum(c, k, borrow(a), borrow(thr), borrow(b), borrow(cc)), out); });
+}
+
+BGV_EXPORT bgv_status bgv_filter_products(bgv_ctx* c, const bgv_keys* k, const bgv_ct* a, const bgv_ct* thr,
+                                          const bgv_ct* b, const bgv_ct* cc, bgv_ct* out) {
+  NEED_CTX(c);
+  CHECK(filter_check(c, k, a, thr, b, cc));
+  return guarded(c, [&] {
+    return deliver(c, ev_filter_products(c, k, borrow(a), borrow(thr), borrow(b), borrow(cc)), out);
+  });
 }
 
 BGV_EXPORT bgv_status bgv_relu(bgv_ctx* c, const bgv_keys* k, const bgv_ct* x, bgv_ct* out) {
@@ -447,3 +462,15 @@ BGV_EXPORT bgv_status bgv_set_ntt_chunk(bgv_ctx* c, int32_t limbs) {
 }
 
 BGV_EXPORT int32_t bgv_get_ntt_chunk(const bgv_ctx* c) { return c ? c->ntt_chunk : 0; }
+
+BGV_EXPORT bgv_status bgv_trim(bgv_ctx* c, int64_t* held_bytes) {
+  NEED_CTX(c);
+  hipError_t e = c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    c->err = std::string("device error: ") + hipGetErrorString(e);
+    return BGV_E_DEVICE;
+  }
+  c->pool.trim();
+  if (held_bytes) *held_bytes = (int64_t)c->pool.held;
+  return BGV_OK;
+}

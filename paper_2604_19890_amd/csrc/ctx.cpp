@@ -16,44 +16,56 @@ bool hip_ok(bgv_ctx* c, hipError_t e, const char* what) {
   return false;
 }
 
+// Size classes: 1 MiB, then steps of 1/8 of a power of two (at most 12.5% slack),
+// so buffers of neighbouring levels share a class and the cache does not fragment.
+static size_t size_class(size_t bytes) {
+  const size_t mib = (size_t)1 << 20;
+  if (bytes <= mib) return mib;
+  size_t p = mib;
+  while (p * 2 < bytes) p *= 2;
+  const size_t step = p / 8;
+  return (bytes + step - 1) / step * step;
+}
+
 void* DevPool::get(size_t bytes) {
-  const size_t gran = (size_t)1 << 20;
-  bytes = (bytes + gran - 1) / gran * gran;
-  auto it = free_.lower_bound(bytes);
-  // reuse a cached block of the same size class (up to 2x larger)
-  if (it != free_.end() && it->first <= 2 * bytes) {
+  bytes = size_class(bytes);
+  auto it = free_.find(bytes);
+  if (it != free_.end()) {
     void* p = it->second;
     free_.erase(it);
     return p;
   }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
-    // give back the cache and retry once
-    for (auto& kv : free_) {
-      (void)hipFree(kv.second);
-      for (auto a = all_.begin(); a != all_.end(); ++a)
-        if (a->first == kv.second) {
-          held -= a->second;
-          all_.erase(a);
-          break;
-        }
+    (void)hipGetLastError();  // clear the sticky allocation error
+    trim();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
     }
-    free_.clear();
-    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
   }
-  all_.push_back({p, bytes});
+  all_[p] = bytes;
   held += bytes;
   return p;
 }
 
-void DevPool::put(void* p, size_t bytes) {
+void DevPool::put(void* p, size_t) {
   if (!p) return;
-  for (auto& a : all_)
-    if (a.first == p) {
-      free_.insert({a.second, p});
-      return;
+  auto a = all_.find(p);
+  if (a != all_.end()) free_.insert({a->second, p});
+}
+
+// Free every cached block that is not in use (after the stream has drained them).
+void DevPool::trim() {
+  for (auto& kv : free_) {
+    (void)hipFree(kv.second);
+    auto a = all_.find(kv.second);
+    if (a != all_.end()) {
+      held -= a->second;
+      all_.erase(a);
     }
-  (void)bytes;
+  }
+  free_.clear();
 }
 
 void DevPool::release() {

@@ -15,10 +15,11 @@
 // runs after every earlier use of it.
 struct DevPool {
   std::multimap<size_t, void*> free_;
-  std::vector<std::pair<void*, size_t>> all_;
+  std::map<void*, size_t> all_;
   size_t held = 0;
   void* get(size_t bytes);
   void put(void* p, size_t bytes);
+  void trim();
   void release();
 };
 

@@ -264,38 +264,50 @@ __global__ void k_msw_final(const uint64_t* __restrict__ a, const uint64_t* __re
   out[((size_t)cc * lv + i) * N + n0] = to_u(mul_lazy(red(diff, q, qinv), qinv_top[i], q, qinv), q, qinv);
 }
 
-// repeated modulus switch in coefficient form: x [n*2][level][N] -> y [n*2][to][N]
+// repeated modulus switch in coefficient form: x [n*2][level][N] -> y [n*2][to][N],
+// at most MAXD = 16 drops per launch (longer drops are chained launches).  The
+// loops over drops are unrolled so that the per-drop corrections stay in registers.
+constexpr int MSW_MAXD = 16;
+
 __global__ void k_msw_multi(const uint64_t* __restrict__ x, uint64_t* __restrict__ y, int level, int to, int N,
                             const double* __restrict__ msw, int L, const double* __restrict__ tinv,
                             const double* __restrict__ tmod, const PrimeD* __restrict__ pc) {
   const int cc = blockIdx.y;
   const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t* X = x + (size_t)cc * level * N + n0;
-  double wv[64];
   const int nd = level - to;
+  double wv[MSW_MAXD];
   // w for each dropped prime, from the top down; the current value of limb `top`
   // is its input transformed by every drop above it
-  for (int d = 0; d < nd; ++d) {
-    const int top = level - 1 - d;
-    const double q = pc[top].q, qinv = pc[top].qinv;
-    double cur = u2d(X[(size_t)top * N]);
-    for (int e = 0; e < d; ++e) {
-      const int up = level - 1 - e;
-      const double diff = cur - mul_lazy(wv[e] < 0.0 ? wv[e] + q : wv[e], tmod[top], q, qinv);
-      cur = mul_lazy(red(diff, q, qinv), msw[(size_t)up * L + top], q, qinv);
+#pragma unroll
+  for (int d = 0; d < MSW_MAXD; ++d) {
+    wv[d] = 0.0;
+    if (d < nd) {
+      const int top = level - 1 - d;
+      const double q = pc[top].q, qinv = pc[top].qinv;
+      double cur = u2d(X[(size_t)top * N]);
+#pragma unroll
+      for (int e = 0; e < d; ++e) {
+        const int up = level - 1 - e;
+        const double diff = cur - mul_lazy(wv[e] < 0.0 ? wv[e] + q : wv[e], tmod[top], q, qinv);
+        cur = mul_lazy(red(diff, q, qinv), msw[(size_t)up * L + top], q, qinv);
+      }
+      double wt = canon(mul_lazy(canon(red(cur, q, qinv), q), tinv[top], q, qinv), q);
+      const double half = (q - 1.0) * 0.5;
+      wv[d] = wt > half ? wt - q : wt;
     }
-    double wt = canon(mul_lazy(canon(red(cur, q, qinv), q), tinv[top], q, qinv), q);
-    const double half = (q - 1.0) * 0.5;
-    wv[d] = wt > half ? wt - q : wt;
   }
   uint64_t* Y = y + (size_t)cc * to * N + n0;
   for (int i = 0; i < to; ++i) {
     const double q = pc[i].q, qinv = pc[i].qinv;
     double cur = u2d(X[(size_t)i * N]);
-    for (int e = 0; e < nd; ++e) {
-      const int up = level - 1 - e;
-      const double diff = cur - mul_lazy(wv[e] < 0.0 ? wv[e] + q : wv[e], tmod[i], q, qinv);
-      cur = mul_lazy(red(diff, q, qinv), msw[(size_t)up * L + i], q, qinv);
+#pragma unroll
+    for (int e = 0; e < MSW_MAXD; ++e) {
+      if (e < nd) {
+        const int up = level - 1 - e;
+        const double diff = cur - mul_lazy(wv[e] < 0.0 ? wv[e] + q : wv[e], tmod[i], q, qinv);
+        cur = mul_lazy(red(diff, q, qinv), msw[(size_t)up * L + i], q, qinv);
+      }
     }
     Y[(size_t)i * N] = to_u(cur, q, qinv);
   }

@@ -228,10 +228,21 @@ void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out) {
     op_mod_switch(c, in, out);
     return;
   }
-  Scratch X(c, (size_t)n * 2 * lv * N);
-  check_hip(c, hipMemcpyAsync(X.d, in.d, (size_t)n * 2 * lv * N * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
-  op_ntt(c, X.d, n * 2, lv, true);
-  lk::msw_multi(c, X.d, out.d, n, lv, to, in.t_exp);
+  // coefficient form, then at most 16 drops per launch; chained launches are the
+  // same sequence of single-prime drops
+  std::unique_ptr<Scratch> A(new Scratch(c, (size_t)n * 2 * lv * N));
+  check_hip(c, hipMemcpyAsync(A->d, in.d, (size_t)n * 2 * lv * N * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+  op_ntt(c, A->d, n * 2, lv, true);
+  const int maxd = 16;
+  int cur = lv;
+  while (cur - to > maxd) {
+    const int nxt = cur - maxd;
+    std::unique_ptr<Scratch> B(new Scratch(c, (size_t)n * 2 * nxt * N));
+    lk::msw_multi(c, A->d, B->d, n, cur, nxt, in.t_exp);
+    A = std::move(B);  // the old buffer goes back to the pool; later users run after this launch
+    cur = nxt;
+  }
+  lk::msw_multi(c, A->d, out.d, n, cur, to, in.t_exp);
   op_ntt(c, out.d, n * 2, to, false);
 }
 
@@ -635,6 +646,9 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
     }
     inner[j] = Inner{false, 0, acc};
   }
+  // the inner sums hold everything the outer sum needs from the baby steps
+  aligned.clear();
+  for (auto it = baby.begin(); it != baby.end();) it = (it->first != 1 && it->first != kk) ? baby.erase(it) : std::next(it);
   CipherP result;
   for (int j = 1; j < g; ++j) {
     CipherP term;
@@ -750,12 +764,16 @@ CipherP ev_batch_sum(bgv_ctx* c, const CipherP& x) {
 
 // SUM(b*c WHERE a < thr): [a < thr] * (b * c) per ciphertext, summed over the batch,
 // then rotate-and-sum over the slots.
-CipherP ev_filter_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& thr, const CipherP& b,
-                      const CipherP& cc) {
+CipherP ev_filter_products(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& thr, const CipherP& b,
+                           const CipherP& cc) {
   CipherP bc = ev_mul(c, k, b, cc);
   CipherP lt = ev_less_than(c, k, a, thr);
-  CipherP prod = ev_mul(c, k, lt, bc);
-  return ev_rotate_sum(c, k, ev_batch_sum(c, prod));
+  return ev_mul(c, k, lt, bc);
+}
+
+CipherP ev_filter_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& thr, const CipherP& b,
+                      const CipherP& cc) {
+  return ev_rotate_sum(c, k, ev_batch_sum(c, ev_filter_products(c, k, a, thr, b, cc)));
 }
 
 CipherP ev_relu(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {

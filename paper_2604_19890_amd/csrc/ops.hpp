@@ -76,6 +76,8 @@ CipherP ev_space_raise(bgv_ctx* c, const bgv_keys* k, const CipherP& x);
 CipherP ev_rotate_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& x);
 CipherP ev_less_than(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const CipherP& y);
 CipherP ev_batch_sum(bgv_ctx* c, const CipherP& x);
+CipherP ev_filter_products(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& thr, const CipherP& b,
+                           const CipherP& cc);
 CipherP ev_filter_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& thr, const CipherP& b,
                       const CipherP& cc);
 CipherP ev_relu(bgv_ctx* c, const bgv_keys* k, const CipherP& x);
