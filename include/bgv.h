@@ -85,8 +85,12 @@ typedef struct bgv_ctx bgv_ctx;
 typedef struct bgv_keys bgv_keys;
 
 #define BGV_ROW_SWAP (-1) /* rotation step that swaps the two slot rows (X -> X^(2N-1)) */
-#define BGV_OP_LT 0
-#define BGV_OP_EQ 1
+#define BGV_OP_LT 0  /* [value < 0] on the centered range of Z_{p^r}          */
+#define BGV_OP_EQ 1  /* [value = 0]                                          */
+#define BGV_OP_GT 2  /* [value > 0]: digit polynomial F_GT(x) = F_LT(-x)      */
+#define BGV_OP_LE 3  /* 1 - GT                                               */
+#define BGV_OP_GE 4  /* 1 - LT                                               */
+#define BGV_OP_NEQ 5 /* 1 - EQ                                               */
 
 /* ---- context -------------------------------------------------------------
  * bgv_ctx_create: derives the prime chain, NTT roots and twiddles, slot roots,
@@ -181,8 +185,10 @@ bgv_status bgv_mod_switch_to(bgv_ctx* ctx, const bgv_ct* in, int32_t level, bgv_
  * bgv_space_reduce: Algorithm 3 for r = 2: digits[0] = G_{p,2}(in) and
  *   digits[1] = DivideByP(in - digits[0]), both tagged t = p (ChangeModToP); the
  *   digits are the balanced base-p digits of each slot.  `digits` has r entries.
- * bgv_compare: Algorithm 4 on r digit batches (least significant first), op
- *   BGV_OP_LT ([value < 0] on the centered range of Z_{p^r}) or BGV_OP_EQ.
+ * bgv_compare: Algorithm 4 on r digit batches (least significant first), op one of
+ *   BGV_OP_LT / GT (digit polynomial and the aggregation LT = LT + EQ * LT_i),
+ *   BGV_OP_EQ (product of the digit equalities) or the complements LE = 1 - GT,
+ *   GE = 1 - LT, NEQ = 1 - EQ (the comparison subsection's predicate family).
  * bgv_space_raise: RaiseModToP2R -- tag t = p^r, then G_{p,r}; a slot holding k
  *   mod p becomes centered_p(k) mod p^r.
  * bgv_less_than: reduce -> compare(LT) -> raise of (x - y), or of x if y is NULL.
@@ -222,6 +228,22 @@ bgv_status bgv_relu(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* x, bgv_ct*
  *   several queries can share one batch.                                                   */
 bgv_status bgv_filter_products(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* a, const bgv_ct* thr,
                                const bgv_ct* b, const bgv_ct* c, bgv_ct* out);
+
+/* ---- graph capture ---------------------------------------------------------
+ * bgv_capture_begin / bgv_capture_end record every device operation the context
+ * enqueues in between into an executable graph (capture in relaxed mode on a
+ * stream of the library's own, after the context stream has drained; work that
+ * is not the library's is not recorded); bgv_graph_launch replays it on the context's
+ * stream with the same buffers (inputs, outputs, and the library's scratch, which
+ * stays reserved while any graph of the context exists).  Only asynchronous
+ * operations can be captured (not keygen, encrypt, decrypt, trim); run the sequence
+ * once before capturing it so that its tables are built.  BGV_E_DEVICE if the
+ * runtime rejects the capture.                                                   */
+typedef struct bgv_graph bgv_graph;
+bgv_status bgv_capture_begin(bgv_ctx* ctx);
+bgv_status bgv_capture_end(bgv_ctx* ctx, bgv_graph** out);
+bgv_status bgv_graph_launch(bgv_ctx* ctx, const bgv_graph* graph);
+void bgv_graph_destroy(bgv_graph* graph);
 
 /* ---- tuning ---------------------------------------------------------------
  * bgv_set_ntt_chunk: two-pass NTTs over many limbs run in chunks of `limbs`

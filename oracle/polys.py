@@ -6,6 +6,7 @@ Test infrastructure only (see the package docstring).
   restated for comparison with zero in the Method's comparison subsection).
 * F_LT(x, 0) = (p+1)/2 x^(p-1) + sum_{i odd, 1 <= i <= p-2} c_i x^i with
   c_i = sum_{j=1}^{(p-1)/2} j^(p-1-i)  (Method, comparison subsection).
+* F_GT(x, 0) = F_LT(-x, 0): GT is obtained the same way as LT.
 * G_{p,2}: a polynomial with G(z0 + p z1) = z0 mod p^2 for balanced z0 (Lemma 3).
   The paper defers the construction; the reading used here is the monic form
   G(x) = x^p + p H(x) mod p^2, where H in F_p[x] (degree <= p-1) interpolates
@@ -81,6 +82,12 @@ def _g_p2(p: int) -> tuple:
     G = [(p * h) % t for h in H] + [0]
     G[p] = (G[p] + 1) % t
     return tuple(G)
+
+
+def f_gt(p: int) -> list:
+    """F_GT(x, 0) = [x > 0] on the balanced representatives: F_LT(-x) (the comparison
+    subsection derives GT the same way as LT)."""
+    return [(c if i % 2 == 0 else -c) % p for i, c in enumerate(f_lt(p))]
 
 
 def g_p2(p: int) -> list:

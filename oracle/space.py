@@ -154,15 +154,26 @@ def _eq_digit(P, keys, x, cnt):
     return B.add_const(P, B.neg(P, y), 1)
 
 
+def _one_minus(P, ct):
+    return B.add_const(P, B.neg(P, ct), 1)
+
+
 def compare(P, keys, digits, op="lt", cnt=None):
-    """Algorithm 4 over the digits (least significant first); op 'lt' or 'eq'."""
+    """Algorithm 4 over the digits (least significant first).
+
+    op: 'lt' and 'gt' (digit polynomial F_LT or F_GT, aggregated LT = LT + EQ * LT_i),
+    'eq' (product of the digit equalities), and the complements of the comparison
+    subsection: 'ge' = 1 - LT, 'le' = 1 - GT, 'neq' = 1 - EQ."""
     r = len(digits)
+    if op in ("ge", "le", "neq"):
+        base = {"ge": "lt", "le": "gt", "neq": "eq"}[op]
+        return _one_minus(P, compare(P, keys, digits, base, cnt))
     if op == "eq":
         eq = _eq_digit(P, keys, digits[r - 1], cnt)
         for i in range(r - 2, -1, -1):
             eq = _mul(P, keys, eq, _eq_digit(P, keys, digits[i], cnt), cnt)
         return eq
-    flt = polys.f_lt(P.p)
+    flt = polys.f_lt(P.p) if op == "lt" else polys.f_gt(P.p)
     lts = [eval_poly(P, keys, dg, flt, cnt) for dg in digits]
     lt = lts[r - 1]
     eq = _eq_digit(P, keys, digits[r - 1], cnt) if r > 1 else None

@@ -22,6 +22,10 @@ _lib = ctypes.CDLL(LIB_PATH)
 ROW_SWAP = -1
 OP_LT = 0
 OP_EQ = 1
+OP_GT = 2
+OP_LE = 3
+OP_GE = 4
+OP_NEQ = 5
 
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_PARAM", 3: "E_LEVEL", 4: "E_PTXT_MOD", 5: "E_NOKEY", 6: "E_OOM",
           7: "E_DEVICE", 8: "E_UNSUPPORTED"}
@@ -91,6 +95,10 @@ _sigs = {
     "bgv_ntt": [_vp, _vp, _i64, _i32, _i32, _i32],
     "bgv_set_ntt_chunk": [_vp, _i32],
     "bgv_trim": [_vp, _vp],
+    "bgv_capture_begin": [_vp],
+    "bgv_capture_end": [_vp, _P(_vp)],
+    "bgv_graph_launch": [_vp, _vp],
+    "bgv_graph_destroy": [_vp],
     "bgv_get_ntt_chunk": [_vp],
 }
 for _name, _args in _sigs.items():
@@ -99,6 +107,7 @@ for _name, _args in _sigs.items():
     _f.restype = ctypes.c_int
 _lib.bgv_ctx_destroy.restype = None
 _lib.bgv_keys_destroy.restype = None
+_lib.bgv_graph_destroy.restype = None
 _lib.bgv_last_error.restype = ctypes.c_char_p
 _lib.bgv_ct_words.restype = ctypes.c_int64
 _lib.bgv_keys_bytes.restype = ctypes.c_int64
@@ -139,6 +148,22 @@ class Keys:
         return int(_lib.bgv_keys_bytes(self.handle))
 
     def __del__(self, _destroy=_lib.bgv_keys_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
+
+
+class Graph:
+    """A captured sequence of library operations, replayed with the same buffers."""
+
+    def __init__(self, ctx: "Context", handle: ctypes.c_void_p):
+        self._ctx = ctx
+        self.handle = handle
+
+    def launch(self):
+        self._ctx._check(_lib.bgv_graph_launch(self._ctx.handle, self.handle))
+
+    def __del__(self, _destroy=_lib.bgv_graph_destroy):
         if getattr(self, "handle", None):
             _destroy(self.handle)
             self.handle = None
@@ -212,6 +237,14 @@ class Context:
 
     def sync(self):
         self._check(_lib.bgv_sync(self.handle))
+
+    def capture_begin(self):
+        self._check(_lib.bgv_capture_begin(self.handle))
+
+    def capture_end(self) -> Graph:
+        h = ctypes.c_void_p()
+        self._check(_lib.bgv_capture_end(self.handle, ctypes.byref(h)))
+        return Graph(self, h)
 
     def trim(self) -> int:
         """Free the library's cached scratch; returns the bytes still in use."""

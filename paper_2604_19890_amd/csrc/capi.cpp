@@ -344,7 +344,7 @@ BGV_EXPORT bgv_status bgv_space_reduce(bgv_ctx* c, const bgv_keys* k, const bgv_
 BGV_EXPORT bgv_status bgv_compare(bgv_ctx* c, const bgv_keys* k, const bgv_ct* digits, int32_t r, int32_t op,
                                   bgv_ct* out) {
   NEED_CTX(c);
-  if (!k || !digits || r < 1 || r > c->prm.r || (op != BGV_OP_LT && op != BGV_OP_EQ))
+  if (!k || !digits || r < 1 || r > c->prm.r || op < BGV_OP_LT || op > BGV_OP_NEQ)
     return fail(c, BGV_E_ARG, "bad compare arguments");
   std::vector<CipherP> d;
   for (int i = 0; i < r; ++i) {
@@ -473,4 +473,77 @@ BGV_EXPORT bgv_status bgv_trim(bgv_ctx* c, int64_t* held_bytes) {
   c->pool.trim();
   if (held_bytes) *held_bytes = (int64_t)c->pool.held;
   return BGV_OK;
+}
+
+struct bgv_graph {
+  bgv_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+BGV_EXPORT bgv_status bgv_capture_begin(bgv_ctx* c) {
+  NEED_CTX(c);
+  if (c->capturing) return fail(c, BGV_E_ARG, "already capturing");
+  // capture on a stream of the library's own (the context stream may be the null
+  // stream, which cannot be captured); the graph is launched on the context stream
+  hipError_t e = c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize();
+  if (e == hipSuccess && !c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    c->err = std::string("capture begin: ") + hipGetErrorString(e);
+    return BGV_E_DEVICE;
+  }
+  c->saved_stream = c->stream;
+  c->stream = c->cap_stream;
+  c->capturing = true;
+  c->graphs_alive += 1;  // keep scratch reserved from the start of the capture
+  return BGV_OK;
+}
+
+BGV_EXPORT bgv_status bgv_capture_end(bgv_ctx* c, bgv_graph** out) {
+  NEED_CTX(c);
+  if (!c->capturing || !out) return fail(c, BGV_E_ARG, "not capturing");
+  c->capturing = false;
+  bgv_graph* g = new (std::nothrow) bgv_graph();
+  if (!g) {
+    hipGraph_t tmp = nullptr;
+    (void)hipStreamEndCapture(c->cap_stream, &tmp);
+    if (tmp) (void)hipGraphDestroy(tmp);
+    c->stream = c->saved_stream;
+    c->graphs_alive -= 1;
+    return BGV_E_OOM;
+  }
+  g->ctx = c;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &g->graph);
+  c->stream = c->saved_stream;
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    c->err = std::string("graph capture: ") + hipGetErrorString(e);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    c->graphs_alive -= 1;
+    return BGV_E_DEVICE;
+  }
+  *out = g;
+  return BGV_OK;
+}
+
+BGV_EXPORT bgv_status bgv_graph_launch(bgv_ctx* c, const bgv_graph* g) {
+  NEED_CTX(c);
+  if (!g || g->ctx != c) return fail(c, BGV_E_ARG, "graph of another context");
+  hipError_t e = hipGraphLaunch(g->exec, c->stream);
+  if (e != hipSuccess) {
+    c->err = std::string("hipGraphLaunch: ") + hipGetErrorString(e);
+    return BGV_E_DEVICE;
+  }
+  return BGV_OK;
+}
+
+BGV_EXPORT void bgv_graph_destroy(bgv_graph* g) {
+  if (!g) return;
+  if (g->ctx && g->ctx->stream) (void)hipStreamSynchronize(g->ctx->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->ctx) g->ctx->graphs_alive -= 1;
+  delete g;
 }

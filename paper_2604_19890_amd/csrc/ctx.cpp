@@ -57,6 +57,7 @@ void DevPool::put(void* p, size_t) {
 
 // Free every cached block that is not in use (after the stream has drained them).
 void DevPool::trim() {
+  if (pinned && *pinned > 0) return;  // graphs may replay into cached blocks
   for (auto& kv : free_) {
     (void)hipFree(kv.second);
     auto a = all_.find(kv.second);
@@ -124,16 +125,17 @@ bool interpolate_fp(int64_t p, const std::vector<int64_t>& zs, const std::vector
 
 }  // namespace
 
-// F_LT: the interpolant over Z_p of [z < 0] on the balanced representatives.
+// F_LT, F_GT: the interpolants over Z_p of [z < 0] and [z > 0] on the balanced representatives.
 // G_{p,2} = x^p + p H(x) with H the interpolant of (z - z^p)/p on balanced z:
 // then G(z) = z mod p^2 and G'(z) = 0 mod p for every balanced z, so
 // G(z0 + p z1) = z0 mod p^2 (Lemma 3 with e = 2, degree p = (e-1)(p-1)+1).
 static bool build_poly_tables(bgv_ctx* c) {
   const int64_t p = c->prm.p;
-  std::vector<int64_t> zs, lt, phi;
+  std::vector<int64_t> zs, lt, gt, phi;
   for (int64_t z = -(p - 1) / 2; z <= (p - 1) / 2; ++z) {
     zs.push_back(z);
     lt.push_back(z < 0 ? 1 : 0);
+    gt.push_back(z > 0 ? 1 : 0);
     // (z - z^p)/p mod p computed with exact 128-bit arithmetic on z^p mod p^2
     const int64_t t2 = p * p;
     int64_t zz = ((z % t2) + t2) % t2, pw = 1;
@@ -142,6 +144,7 @@ static bool build_poly_tables(bgv_ctx* c) {
     phi.push_back((diff / p) % p);
   }
   if (!interpolate_fp(p, zs, lt, c->flt)) return false;
+  if (!interpolate_fp(p, zs, gt, c->fgt)) return false;
   std::vector<int64_t> H;
   if (!interpolate_fp(p, zs, phi, H)) return false;
   const int64_t t2 = p * p;
@@ -187,6 +190,7 @@ static bool upload(bgv_ctx* c, T** dst, const std::vector<T>& v) {
 bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream) {
   c->prm = *prm;
   c->stream = stream;
+  c->pool.pinned = &c->graphs_alive;
   if (prm->log_n < 4 || prm->log_n > 16) { c->err = "log_n must be in [4, 16]"; return BGV_E_PARAM; }
   if (prm->p < 5 || prm->p % 4 != 1 || prm->p > 65521) { c->err = "p must be a prime = 1 mod 4 below 2^16"; return BGV_E_PARAM; }
   if (!is_prime((uint64_t)prm->p)) { c->err = "p is not prime"; return BGV_E_PARAM; }
@@ -313,4 +317,5 @@ void ctx_free(bgv_ctx* c) {
   void* ptrs[] = {c->d_prime, c->d_tw, c->d_itw, c->d_modup, c->d_moddown, c->d_msw, c->d_tconst};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
 }

@@ -17,6 +17,7 @@ struct DevPool {
   std::multimap<size_t, void*> free_;
   std::map<void*, size_t> all_;
   size_t held = 0;
+  const int* pinned = nullptr;  // while *pinned > 0 no cached block is freed
   void* get(size_t bytes);
   void put(void* p, size_t bytes);
   void trim();
@@ -33,6 +34,10 @@ struct bgv_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   int ntt_chunk = 0;  // limbs per chunk of a two-pass NTT (0: one launch pair for all limbs)
+  int graphs_alive = 0;  // executable graphs referring to pool buffers (trim keeps them then)
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;    // capture happens here (default priority, non-blocking)
+  hipStream_t saved_stream = nullptr;  // the context stream while capturing
   DevPool pool;
 
   // device tables
@@ -55,6 +60,7 @@ struct bgv_ctx {
   // polynomial tables (ascending coefficients)
   std::vector<int64_t> g2;    // G_{p,2} mod p^2
   std::vector<int64_t> flt;   // F_LT mod p
+  std::vector<int64_t> fgt;   // F_GT mod p
   // slot structure
   std::vector<int64_t> slot_exp;  // exponent e_j of slot j (root zeta^e_j)
   int64_t zeta = 0;

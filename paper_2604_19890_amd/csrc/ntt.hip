@@ -164,12 +164,16 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
   for (int i = 0; i < 16; ++i) xp[(size_t)i << gs1_log] = d2u(canon(red(v[i], q, qinv), q));
 }
 
-// Second forward pass fused with the key-switching inner product.  Launch over
-// (row block, ciphertext) x target row m of the ModUp output y [n][dn][rows][N],
-// whose first pass is done (rows of a digit's own primes are already in
-// evaluation form and are used as they are).  For every digit j the block
+// Second forward pass fused with the key-switching inner product, over the
+// ModUp output y [n][dn][rows][N] whose first pass is done (rows of a digit's own
+// primes are already in evaluation form and are used as they are).  A block
+// handles one (row block, target row m, ciphertext): for every digit j it
 // finishes the transform of y[ct][j][m] in registers and LDS, multiplies it by
 // key[j][comp][prime(m)] and accumulates; u[ct][comp][m] receives the sums.
+// Block order: workgroups are dispatched round-robin over the eight XCDs, so the
+// blocks of one (row block, m) group -- which read the same key rows -- are given
+// ids with the same residue mod 8 and consecutive positions on that XCD; the key
+// rows are then read once into that XCD's L2 and shared by all ciphertexts.
 template <int LOGS>
 __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __restrict__ y,
                                                            const uint64_t* __restrict__ key,
@@ -184,10 +188,21 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
   const int N = 1 << logN;
   const int NT = blockDim.x;
   const int SUBS = NT / T;
-  const int m = blockIdx.y;
   const int rows = level + K;
-  const int ct = blockIdx.x % n_ct;
-  const int rb = blockIdx.x / n_ct;
+  const int RB = (N / S) / SUBS;  // row blocks per limb
+  const int G = RB * rows;         // (row block, m) groups
+  const int wid = blockIdx.x;
+  int g, ct;
+  if ((G & 7) == 0) {
+    const int k = wid >> 3;
+    g = (wid & 7) + 8 * (k / n_ct);
+    ct = k % n_ct;
+  } else {
+    g = wid / n_ct;
+    ct = wid % n_ct;
+  }
+  const int rb = g % RB;
+  const int m = g / RB;
   const int pm = m < level ? m : Lfull + (m - level);
   const double q = pc[pm].q, qinv = pc[pm].qinv;
   const double* __restrict__ w = tw + (size_t)pm * N;
@@ -288,7 +303,7 @@ void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* key, uint64_t*
   const int N = c->N, S = 1 << p2, T = S / 16;
   const int NT = N / 16 < NT_MAX ? N / 16 : NT_MAX;
   const int SUBS = NT / T;
-  dim3 grid(((N / S) / SUBS) * n, rows);
+  dim3 grid(((N / S) / SUBS) * n * rows);
   switch (p2) {
 #define CASE2(LS)                                                                                              \
   case LS:                                                                                                     \

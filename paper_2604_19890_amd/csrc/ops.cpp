@@ -688,7 +688,7 @@ std::vector<CipherP> ev_space_reduce(bgv_ctx* c, const bgv_keys* k, const Cipher
   return {with_t(a0, 1), a1};
 }
 
-static CipherP eq_from_power(bgv_ctx* c, const CipherP& xp) { return ev_const(c, ev_neg(c, xp), 1); }
+static CipherP one_minus(bgv_ctx* c, const CipherP& x) { return ev_const(c, ev_neg(c, x), 1); }
 
 // Algorithm 4 (digits least significant first).
 CipherP ev_compare(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& digits, int op) {
@@ -697,23 +697,28 @@ CipherP ev_compare(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& di
   auto eq_digit = [&](const CipherP& x) {
     std::map<int, CipherP> tab;
     tab[1] = x;
-    return eq_from_power(c, power(c, k, tab, p - 1));
+    return one_minus(c, power(c, k, tab, p - 1));
   };
+  if (op == BGV_OP_LE || op == BGV_OP_GE || op == BGV_OP_NEQ) {
+    const int base = op == BGV_OP_LE ? BGV_OP_GT : (op == BGV_OP_GE ? BGV_OP_LT : BGV_OP_EQ);
+    return one_minus(c, ev_compare(c, k, digits, base));  // 1 - base
+  }
   if (op == BGV_OP_EQ) {
     CipherP eq = eq_digit(digits[r - 1]);
     for (int i = r - 2; i >= 0; --i) eq = ev_mul(c, k, eq, eq_digit(digits[i]));
     return eq;
   }
+  const std::vector<int64_t>& fdig = op == BGV_OP_GT ? c->fgt : c->flt;
   std::vector<CipherP> lts(r);
   CipherP eq;
   for (int i = 0; i < r; ++i) {
     std::vector<CipherP> giants;
     int kk = 0;
-    lts[i] = ev_eval_poly(c, k, digits[i], c->flt, &giants, &kk);
+    lts[i] = ev_eval_poly(c, k, digits[i], fdig, &giants, &kk);
     if (i == r - 1 && r > 1) {
       // x^(p-1) is the last giant power when (g-1) k = p-1 (same products as the power rule)
       const int g = (int)giants.size();
-      if (g > 1 && (g - 1) * kk == p - 1 && giants[g - 1]) eq = eq_from_power(c, giants[g - 1]);
+      if (g > 1 && (g - 1) * kk == p - 1 && giants[g - 1]) eq = one_minus(c, giants[g - 1]);
       else eq = eq_digit(digits[i]);
     }
   }

@@ -97,3 +97,9 @@ def pair_tiny5():
 def pair_two_pass():
     """A ring large enough for the two-pass NTT (and its fused key-switching pass), with 2-prime digits."""
     return Pair(10, 17, 2, 6, 2, steps=(1,), conj=True)
+
+
+@functools.lru_cache(maxsize=None)
+def pair_two_pass_deep():
+    """Two-pass ring with the full depth of the p = 17 pipeline (18 primes, 2-prime digits)."""
+    return Pair(10, 17, 2, 18, 2, steps=(1, 2), conj=True)

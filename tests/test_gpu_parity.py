@@ -151,6 +151,8 @@ def test_space_switching_composites_match(pf):
     c.assert_equal(glt, olt, "compare lt")
     geq = c.lib.compare(c.keys, gd, c.G.OP_EQ)
     c.assert_equal(geq, [S.compare(P, c.okeys, d, "eq") for d in od], "compare eq")
+    for op, name in ((c.G.OP_GT, "gt"), (c.G.OP_LE, "le"), (c.G.OP_GE, "ge"), (c.G.OP_NEQ, "neq")):
+        c.assert_equal(c.lib.compare(c.keys, gd, op), [S.compare(P, c.okeys, d, name) for d in od], f"compare {name}")
     graise = c.lib.space_raise(c.keys, glt)
     oraise = [S.space_raise(P, c.okeys, x) for x in olt]
     c.assert_equal(graise, oraise, "raise")

@@ -70,6 +70,27 @@ def test_compare_brute_force(ctx):
 
 
 @pytest.mark.parametrize("ctx", [tiny5, tiny17])
+def test_predicate_family_brute_force(ctx):
+    """GT, GE, LE and NEQ (the comparison subsection's family) for every d in Z_{p^2}."""
+    c = ctx()
+    P, p, t = c.P, c.P.p, c.P.t_full
+    ref = {"gt": lambda v: _centered(v, t) > 0, "ge": lambda v: _centered(v, t) >= 0,
+           "le": lambda v: _centered(v, t) <= 0, "neq": lambda v: v % t != 0}
+    step = P.ell if P.ell > 2 else 2
+    for start in range(0, t, step * (3 if t > 100 else 1)):
+        vals = [(start + i) % t for i in range(P.ell)]
+        dg = S.space_reduce(P, c.keys, c.enc(vals))
+        for op, f in ref.items():
+            assert c.dec(S.compare(P, c.keys, dg, op)) == [1 if f(v) else 0 for v in vals], op
+
+
+def test_fgt_truth_table():
+    for p in (5, 17, 257):
+        for x in range(-(p - 1) // 2, (p - 1) // 2 + 1):
+            assert polys.eval_mod(polys.f_gt(p), x % p, p) == (1 if x > 0 else 0)
+
+
+@pytest.mark.parametrize("ctx", [tiny5, tiny17])
 def test_space_raise_clears_high_digits(ctx):
     """Raise of k + p*junk (tagged p) returns centered_p(k) mod p^2."""
     c = ctx()
