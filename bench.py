@@ -126,6 +126,27 @@ def time_plain(ctx, keys, cts, n_plain):
     return time.perf_counter() - t0
 
 
+def time_graph(ctx, keys, cts, steps):
+    """The batched step captured once as a hipGraph and replayed."""
+    import torch
+    out = ctx.empty(1, 1)
+    ctx.filter_sum(keys, cts["a"], cts["t"], cts["b"], cts["c"], out=out)  # eager run: tables, scratch
+    torch.cuda.synchronize()
+    ctx.capture_begin()
+    ctx.filter_sum(keys, cts["a"], cts["t"], cts["b"], cts["c"], out=out)
+    graph = ctx.capture_end()
+    graph.launch()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        graph.launch()
+    stop.record()
+    torch.cuda.synchronize()
+    del graph
+    return start.elapsed_time(stop) / 1e3 / steps
+
+
 def time_ntt(ctx, n_cts, reps=20):
     """Forward NTT over n_cts ciphertexts at the top level: per-NTT time with HIP events."""
     import torch
@@ -243,6 +264,7 @@ def main():
     ap.add_argument("--plain", type=int, default=2, help="ciphertexts timed in the plain form")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="also time the step replayed from a hipGraph")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -264,6 +286,9 @@ def main():
         assert all(int(v) == exp for v in got), (got[:4], exp)
         log(f"[bench] decrypted SUM = {exp} in every slot (matches the plaintext query)")
 
+    t_graph = time_graph(ctx, keys, cts, args.steps) if args.graph else None
+    if t_graph:
+        log(f"[bench] graph replay: {t_graph * 1e3:.1f} ms/step, {rows / t_graph:.1f} rows/s")
     t_plain = time_plain(ctx, keys, cts, args.plain) if args.plain > 0 else None
     plain_rows = (args.plain * ctx.slots / t_plain) if t_plain else None
     if t_plain:
@@ -290,6 +315,7 @@ def main():
         "config": {"workload": f"filter_sum N=2^16 p=257 r=2 L=30 K=6, {args.cts} ciphertexts x 128 rows per column",
                    "rows_per_step": rows, "parallelism": "batch"},
         "plain_rows_per_s": plain_rows,
+        "graph_rows_per_s": (rows / t_graph) if t_graph else None,
         "batched_over_plain": (value / plain_rows) if plain_rows else None,
         "ntt_gb_per_s": ntt_gbs,
         "roofline": {"bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -253,6 +253,14 @@ void bgv_graph_destroy(bgv_graph* graph);
  * bgv_get_ntt_chunk: the current setting.                                       */
 bgv_status bgv_set_ntt_chunk(bgv_ctx* ctx, int32_t limbs);
 int32_t bgv_get_ntt_chunk(const bgv_ctx* ctx);
+/* bgv_set_ntt_split: stages in the first of the two NTT passes (each pass does 4..8
+ *   stages; 0 restores the default ceil(log N / 2)).  BGV_E_ARG if out of range.
+ * bgv_autotune_ntt: times every valid split on a scratch array of `limbs` limbs
+ *   (`reps` forward transforms each, HIP events on the context stream), keeps the
+ *   fastest in the context and reports it with its time per transform.  Results
+ *   are identical for every split.                                                 */
+bgv_status bgv_set_ntt_split(bgv_ctx* ctx, int32_t first_pass_stages);
+bgv_status bgv_autotune_ntt(bgv_ctx* ctx, int32_t limbs, int32_t reps, int32_t* best_split, float* best_us);
 
 /* ---- raw NTT access (the transform on its own, for tests and bandwidth runs)
  * bgv_ntt: in place on a DEVICE array holding n_polys polynomials of `level` limbs

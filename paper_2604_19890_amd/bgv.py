@@ -95,6 +95,8 @@ _sigs = {
     "bgv_ntt": [_vp, _vp, _i64, _i32, _i32, _i32],
     "bgv_set_ntt_chunk": [_vp, _i32],
     "bgv_trim": [_vp, _vp],
+    "bgv_set_ntt_split": [_vp, _i32],
+    "bgv_autotune_ntt": [_vp, _i32, _i32, _vp, _vp],
     "bgv_capture_begin": [_vp],
     "bgv_capture_end": [_vp, _P(_vp)],
     "bgv_graph_launch": [_vp, _vp],
@@ -414,6 +416,16 @@ class Context:
 
     def relu(self, keys, x, out=None):
         return self._un(_lib.bgv_relu, x, out=out, keys=keys)
+
+    def set_ntt_split(self, first_pass_stages: int):
+        self._check(_lib.bgv_set_ntt_split(self.handle, int(first_pass_stages)))
+
+    def autotune_ntt(self, limbs: int, reps: int = 10):
+        """Pick the fastest NTT pass split for `limbs` limbs; returns (split, microseconds)."""
+        s = ctypes.c_int32()
+        us = ctypes.c_float()
+        self._check(_lib.bgv_autotune_ntt(self.handle, int(limbs), int(reps), ctypes.byref(s), ctypes.byref(us)))
+        return s.value, us.value
 
     @property
     def ntt_chunk(self) -> int:

@@ -547,3 +547,53 @@ BGV_EXPORT void bgv_graph_destroy(bgv_graph* g) {
   if (g->ctx) g->ctx->graphs_alive -= 1;
   delete g;
 }
+
+BGV_EXPORT bgv_status bgv_set_ntt_split(bgv_ctx* c, int32_t s) {
+  NEED_CTX(c);
+  if (s != 0 && (s < 4 || s > 8 || c->logN - s < 4 || c->logN - s > 8 || c->logN <= 8))
+    return fail(c, BGV_E_ARG, "split out of range");
+  c->ntt_split = s;
+  return BGV_OK;
+}
+
+BGV_EXPORT bgv_status bgv_autotune_ntt(bgv_ctx* c, int32_t limbs, int32_t reps, int32_t* best_split, float* best_us) {
+  NEED_CTX(c);
+  if (limbs < 1 || reps < 1) return fail(c, BGV_E_ARG, "limbs and reps must be positive");
+  if (c->capturing) return fail(c, BGV_E_ARG, "cannot tune while capturing");
+  return guarded(c, [&] {
+    std::vector<int> cands;
+    if (c->logN <= 8) cands.push_back(0);
+    for (int s = 4; s <= 8 && c->logN > 8; ++s)
+      if (c->logN - s >= 4 && c->logN - s <= 8) cands.push_back(s);
+    // zero residues are valid input; the transform's time does not depend on the values
+    Scratch buf(c, (size_t)limbs * c->N);
+    if (hipMemsetAsync(buf.d, 0, buf.bytes, c->stream) != hipSuccess) throw OpError{BGV_E_DEVICE};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) throw OpError{BGV_E_DEVICE};
+    const int saved = c->ntt_split;
+    int best = saved;
+    float best_t = 1e30f;
+    const int L = c->prm.L;
+    for (int s : cands) {
+      c->ntt_split = s;
+      lk::ntt(c, buf.d, limbs, LimbMap{L, L, L, 0, 1, 0, 0}, false);  // warm-up
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < reps; ++r) lk::ntt(c, buf.d, limbs, LimbMap{L, L, L, 0, 1, 0, 0}, false);
+      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const float us = ms * 1000.f / reps;
+      if (us < best_t) {
+        best_t = us;
+        best = s;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->ntt_split = best >= 0 ? best : saved;
+    if (best_split) *best_split = c->ntt_split;
+    if (best_us) *best_us = best_t;
+    return BGV_OK;
+  });
+}

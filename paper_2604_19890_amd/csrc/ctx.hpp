@@ -34,6 +34,7 @@ struct bgv_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   int ntt_chunk = 0;  // limbs per chunk of a two-pass NTT (0: one launch pair for all limbs)
+  int ntt_split = 0;  // stages in the first of two NTT passes (0: ceil(log N / 2))
   int graphs_alive = 0;  // executable graphs referring to pool buffers (trim keeps them then)
   bool capturing = false;
   hipStream_t cap_stream = nullptr;    // capture happens here (default priority, non-blocking)
@@ -85,6 +86,8 @@ struct bgv_keys {
 
 // ------------------------------------------------------------------ launchers
 namespace lk {
+// stages of the first and second NTT pass (second = 0 for a single pass)
+void ntt_split(const bgv_ctx* c, int* p1, int* p2);
 // true when the forward NTT has two passes (log N > 8), so the second can be fused
 bool ntt_fused_inner_ok(const bgv_ctx* c);
 // ModUp output y [n][dn][level+K][N] (coefficient form except the own-digit rows):

@@ -224,18 +224,22 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
     const bool own = m < level && m / alpha == j;
     if (!own) {
       ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
+      if (T > 1) {  // with T = 1 the four register stages were all of the pass
 #pragma unroll
-      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
-      __syncthreads();
+        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
+        __syncthreads();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
-      ct_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, 0, q, qinv);
+        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+        ct_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, 0, q, qinv);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
-      __syncthreads();
+        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
+        __syncthreads();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
-      __syncthreads();  // the next digit writes the same LDS rows
+        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
+        __syncthreads();  // the next digit writes the same LDS rows
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = red(v[i], q, qinv);
     }
     const uint64_t* __restrict__ kb = key + (((size_t)j * 2 + 0) * Ltot + pm) * N + g1;
     const uint64_t* __restrict__ ka = key + (((size_t)j * 2 + 1) * Ltot + pm) * N + g1;
@@ -291,11 +295,25 @@ void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int
 
 namespace lk {
 
+void ntt_split(const bgv_ctx* c, int* p1, int* p2) {
+  const int logN = c->logN;
+  if (logN <= 8) {
+    *p1 = logN;
+    *p2 = 0;
+    return;
+  }
+  int a = (logN + 1) / 2;
+  if (c->ntt_split >= 4 && c->ntt_split <= 8 && logN - c->ntt_split >= 4 && logN - c->ntt_split <= 8) a = c->ntt_split;
+  *p1 = a;
+  *p2 = logN - a;
+}
+
 bool ntt_fused_inner_ok(const bgv_ctx* c) { return c->logN > 8; }
 
 void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* key, uint64_t* u, int n, int level) {
   const int logN = c->logN;
-  const int p1 = (logN + 1) / 2, p2 = logN - p1;
+  int p1, p2;
+  ntt_split(c, &p1, &p2);
   const int A = c->alpha, K = c->prm.K, L = c->prm.L;
   const int dn = (level + A - 1) / A, rows = level + K;
   // first pass over the non-own rows
@@ -323,15 +341,8 @@ void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* key, uint64_t*
 
 void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse) {
   if (n_limbs <= 0) return;
-  const int logN = c->logN;
   int p1, p2;
-  if (logN <= 8) {
-    p1 = logN;
-    p2 = 0;
-  } else {
-    p1 = (logN + 1) / 2;
-    p2 = logN - p1;
-  }
+  ntt_split(c, &p1, &p2);
   // Two-pass transforms run chunk by chunk so that a chunk's first-pass output is
   // still in L2 / Infinity Cache when the second pass reads it.  The limb map is
   // shifted with the chunk: limb l of the chunk is limb off + l of the launch.

@@ -204,3 +204,26 @@ def test_workload_glue_matches():
     assert np.array_equal(c.lib.decrypt(c.s, fs), np.array([[expect] * P.ell]))
     r = c.lib.relu(c.keys, ga)
     c.assert_equal(r, [S.relu(P, c.okeys, x) for x in oa], "relu")
+
+
+
+@pytest.mark.parametrize("logN", [10, 12, 14])
+def test_every_ntt_split_matches_the_definition_and_autotune_picks_one(logN):
+    import torch
+    from paper_2604_19890_amd import bgv as G
+    lib = G.Context(logN, 17, 2, 3, 1)
+    P = Params(logN, 17, 2, 3, 1)
+    x = _rand_limbs(P, 3, 1, logN + 100)
+    idx = np.array([0, 1, 5, P.N // 2, P.N - 1])
+    ref = [R.ntt_def_at(x[0, i], q, P.psi(q), idx) for i, q in enumerate(P.primes[:3])]
+    for split in [s for s in range(4, 9) if 4 <= logN - s <= 8]:
+        lib.set_ntt_split(split)
+        t = torch.from_numpy(x.reshape(-1).view(np.int64).copy()).cuda()
+        lib.ntt(t, 1, 3)
+        got = t.cpu().numpy().view(np.uint64).reshape(x.shape)
+        for i in range(3):
+            assert np.array_equal(got[0, i, idx], ref[i]), (split, i)
+        lib.ntt(t, 1, 3, inverse=True)
+        assert np.array_equal(t.cpu().numpy().view(np.uint64).reshape(x.shape), x), split
+    split, us = lib.autotune_ntt(64, reps=3)
+    assert 4 <= split <= 8 and 4 <= logN - split <= 8 and us > 0

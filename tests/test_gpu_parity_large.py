@@ -18,7 +18,10 @@ def test_two_pass_ring_operations_match():
     gb, ob = c.enc_both(g.integers(0, t, size=(2, P.ell)))
     c.assert_equal(c.lib.mul_relin(c.keys, ga, gb), [B.mul_relin(P, c.okeys.relin, x, y) for x, y in zip(oa, ob)],
                    "mul_relin N=1024")
-    c.assert_equal(c.lib.mul(c.keys, ga, gb), [S._mul(P, c.okeys, x, y) for x, y in zip(oa, ob)], "mul N=1024")
+    om = [S._mul(P, c.okeys, x, y) for x, y in zip(oa, ob)]
+    for split in (4, 6, 0):  # the fused key-switching pass under every pass split
+        c.lib.set_ntt_split(split)
+        c.assert_equal(c.lib.mul(c.keys, ga, gb), om, f"mul N=1024 split {split}")
     c.assert_equal(c.lib.rotate(c.keys, ga, 1), [B.rotate(P, c.okeys.galois, x, 1) for x in oa], "rotate N=1024")
     c.assert_equal(c.lib.rotate(c.keys, ga, c.G.ROW_SWAP), [B.rotate(P, c.okeys.galois, x, "conj") for x in oa],
                    "conj N=1024")
@@ -26,6 +29,18 @@ def test_two_pass_ring_operations_match():
     coeffs = [int(v) for v in g.integers(0, t, size=6)]
     c.assert_equal(c.lib.eval_poly(c.keys, ga, coeffs), [S.eval_poly(P, c.okeys, x, coeffs) for x in oa],
                    "eval_poly N=1024")
+
+
+def test_products_on_a_ring_with_a_four_stage_second_pass():
+    """N = 2^9: the default pass split is 5 + 4, so the fused pass has a single register step."""
+    c = Pair(9, 17, 2, 5, 2)
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(23)
+    ga, oa = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    c.assert_equal(c.lib.mul_relin(c.keys, ga, gb), [B.mul_relin(P, c.okeys.relin, x, y) for x, y in zip(oa, ob)],
+                   "mul_relin N=512")
+    c.assert_equal(c.lib.mul(c.keys, ga, gb), [S._mul(P, c.okeys, x, y) for x, y in zip(oa, ob)], "mul N=512")
 
 
 def test_tiny_workload_end_to_end_n4096():
