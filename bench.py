@@ -165,6 +165,24 @@ def time_ntt(ctx, n_cts, reps=20):
     return per, algo_bytes, limbs
 
 
+def ntt_only(args):
+    """Forward NTT over --cts ciphertexts (2 x 30 limbs each) and a device copy of the same
+    number of bytes, reps times each: the run the hardware counters are read on."""
+    import torch
+    from paper_2604_19890_amd import bgv as G
+    ctx = G.Context(LOG_N, P_, R_, L_, K_)
+    limbs = args.cts * 2 * ctx.L
+    x = torch.randint(0, 1 << 49, (limbs * ctx.N,), dtype=torch.int64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.steps):
+        ctx.ntt(x, args.cts * 2, ctx.L)
+        y.copy_(x)
+    torch.cuda.synchronize()
+    per, algo_bytes, limbs = time_ntt(ctx, args.cts, reps=args.steps)
+    log(f"[bench] ntt-only: {limbs} limbs, {algo_bytes / 2**30:.3f} GiB algorithmic per transform, "
+        f"copy of {x.numel() * 8 / 2**30:.3f} GiB; {per * 1e6:.1f} us per transform")
+
+
 # ----------------------------------------------------------------------------- CPU oracle baseline
 
 def limb_products_per_query_ct():
@@ -265,6 +283,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="also time the step replayed from a hipGraph")
+    ap.add_argument("--ntt-only", action="store_true",
+                    help="only the forward NTT at the query shape and a copy of the same bytes (for counters)")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -273,6 +293,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.ntt_only:
+        ntt_only(args)
+        return
     ctx, keys, s, cols, thr, cts = setup(args)
     rows = args.cts * ctx.slots
 

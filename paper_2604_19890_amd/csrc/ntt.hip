@@ -92,7 +92,14 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
   const int N = 1 << logN;
   const int NT = blockDim.x;
   const int SUBS = NT / T;
-  const int limb = blockIdx.y;
+  // Prime-major block order: consecutive block rows take the same limb position
+  // of consecutive polynomials, so the prime's twiddle table is read once into
+  // each XCD's L2 and reused instead of cycling through every prime's table.
+  int limb = blockIdx.y;
+  if (gridDim.y % lm.period == 0) {
+    const int polys = gridDim.y / lm.period;
+    limb = (blockIdx.y % polys) * lm.period + blockIdx.y / polys;
+  }
   if (limb_skipped(lm, limb)) return;
   const int pi = limb_prime(lm, limb);
   const double q = pc[pi].q, qinv = pc[pi].qinv;
