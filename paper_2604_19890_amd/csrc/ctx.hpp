@@ -130,6 +130,17 @@ void msw_final(bgv_ctx* c, const uint64_t* a, const uint64_t* w, uint64_t* out, 
 void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int to, int t_exp);
 // copy limb rows: y[b][c][i] = x[b][c][i] for i < to_level (x has from_level rows)
 void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from_level, int to_level, int comps);
+// Terms and sums of one multi-output linear combination (at most LC_MAXT terms,
+// LC_MAXO sums per launch).
+constexpr int LC_MAXT = 16;
+constexpr int LC_MAXO = 24;
+struct LinMulti {
+  const uint64_t* x[LC_MAXT];
+  uint64_t* out[LC_MAXO];
+  int row[LC_MAXO][LC_MAXT];  // coefficient row of term t in sum o; -1: absent
+  int cst_row[LC_MAXO];       // row of the constant of sum o; -1: none
+};
+void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* sc, int sc_stride, int n, int level);
 // out = sum_t sc[rows[t]][i] * xs[t] (+ sc[cst_row][i] on component 0); nt <= 16 terms, all at `level`
 void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, const double* sc, int sc_stride,
              int cst_row, uint64_t* out, int n, int level);

@@ -359,6 +359,35 @@ __global__ void k_lincomb(LinTerms terms, int nt, const double* __restrict__ sc,
   out[off] = to_u(acc, q, qinv);
 }
 
+// Several inner sums over one set of terms in one pass: out_o[ct][c][i] =
+// sum_t sc[row[o][t]][i] * x_t[ct][c][i] (+ sc[cst_row[o]][i] on component 0), a term
+// with row -1 being absent from sum o.  Each term is read once for all sums.
+__global__ void k_lincomb_multi(lk::LinMulti m, int nt, int no, const double* __restrict__ sc, int sc_stride,
+                                int level, int N, const PrimeD* __restrict__ pc) {
+  const int limb = blockIdx.y;
+  const int i = limb % level;
+  const int comp = (limb / level) & 1;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t off = (size_t)limb * N + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double x[lk::LC_MAXT];
+#pragma unroll
+  for (int t = 0; t < lk::LC_MAXT; ++t) x[t] = t < nt ? u2d(m.x[t][off]) : 0.0;
+  for (int o = 0; o < no; ++o) {
+    double acc = 0.0;
+    int cnt = 0;
+#pragma unroll
+    for (int t = 0; t < lk::LC_MAXT; ++t) {
+      const int row = m.row[o][t];
+      if (t < nt && row >= 0) {
+        acc += mul_lazy(x[t], sc[(size_t)row * sc_stride + i], q, qinv);
+        if ((++cnt & 3) == 0) acc = red(acc, q, qinv);
+      }
+    }
+    if (comp == 0 && m.cst_row[o] >= 0) acc += sc[(size_t)m.cst_row[o] * sc_stride + i];
+    m.out[o][off] = to_u(acc, q, qinv);
+  }
+}
+
 // Product step with the modulus switch merged into ModDown, part 1 (coefficient form).
 // For ciphertext ct and component c: from the special rows up [ct*2+c][K][N] the
 // ModDown correction wt_i = FBC_{P->Q}([u_P t^-1]_P) is formed for every q_i; the top
@@ -634,6 +663,12 @@ void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, con
   }
   hipLaunchKernelGGL(k_lincomb, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, t, nt, sc,
                      sc_stride, cst_row, out, level, c->N, c->d_prime);
+}
+
+void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* sc, int sc_stride, int n,
+                   int level) {
+  hipLaunchKernelGGL(k_lincomb_multi, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, m, nt, no,
+                     sc, sc_stride, level, c->N, c->d_prime);
 }
 
 void ms_corr(bgv_ctx* c, const uint64_t* up, const uint64_t* tops, uint64_t* e, int n, int level, int t_exp) {

@@ -35,6 +35,27 @@ constexpr int NT_MAX = 256;
 
 __device__ __forceinline__ int lds_idx(int sl, int k, int S) { return sl * (S + (S >> 4) + 1) + k + (k >> 4); }
 
+// Ordering point for an LDS exchange among the lanes of one wavefront.  The LDS
+// instructions of a wave are performed in issue order, so it suffices to keep
+// the compiler from moving LDS accesses across this point; no s_barrier is
+// issued and the other waves of the block run on.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS exchange point of a pass.  In a contiguous pass (tmin = 1) the T <= 16
+// threads of a sub-transform are consecutive lanes of one wave (T divides 64)
+// and each sub-transform has LDS rows of its own, so the exchange stays inside
+// the wave; a column pass spreads a sub-transform over the block's waves.
+__device__ __forceinline__ void pass_sync(bool wave_local) {
+  if (wave_local)
+    wave_lds_sync();
+  else
+    __syncthreads();
+}
+
 // Cooley-Tukey stages at register distances DMAX, DMAX/2, .., 1 on 16 registers
 // holding global indices g0 + i * 2^gs_log.  The butterflies of group g at
 // distance dd share twiddle number ((N + g0) >> log2(2 dd 2^gs_log)) + g.
@@ -126,6 +147,7 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
   // consecutive layout: register i holds global index g2 + i * tmin
   const int g2 = base + ((16 * tau) << tmin_log);
   uint64_t* __restrict__ xp = x + g1;
+  const bool wave_local = tmin == 1;
   double v[16];
 
 #pragma unroll
@@ -136,13 +158,13 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
     if (T > 1) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
-      __syncthreads();
+      pass_sync(wave_local);
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
       ct_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, tmin_log, q, qinv);
 #pragma unroll
       for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
-      __syncthreads();
+      pass_sync(wave_local);
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
     }
@@ -150,13 +172,13 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
     if (T > 1) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = v[i];
-      __syncthreads();
+      pass_sync(wave_local);
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
       gs_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, tmin_log, q, qinv);
 #pragma unroll
       for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
-      __syncthreads();
+      pass_sync(wave_local);
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
     }
@@ -224,26 +246,39 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
   double acc0[16], acc1[16], v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = 0.0;
-  for (int j = 0; j < dn; ++j) {
-    const uint64_t* __restrict__ yp = y + (((size_t)ct * dn + j) * rows + m) * N + g1;
+  // Digit j + 1's y row is requested at the start of digit j, in the same batch
+  // as digit j's twiddle loads: loads complete in issue order, so the transform
+  // waits for both, and each digit costs one round trip to memory for its data
+  // and twiddles instead of two.
+  const uint64_t* __restrict__ yrow = y + ((size_t)ct * dn * rows + m) * N + g1;
+  const size_t ystep = (size_t)rows * N;
+  uint64_t yn[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = u2d(yp[(size_t)i << gs1_log]);
+  for (int i = 0; i < 16; ++i) yn[i] = yrow[(size_t)i << gs1_log];
+  for (int j = 0; j < dn; ++j) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = u2d(yn[i]);
+    if (j + 1 < dn) {
+      const uint64_t* __restrict__ yp = yrow + (size_t)(j + 1) * ystep;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) yn[i] = yp[(size_t)i << gs1_log];
+    }
     const bool own = m < level && m / alpha == j;
     if (!own) {
       ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
       if (T > 1) {  // with T = 1 the four register stages were all of the pass
 #pragma unroll
         for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
-        __syncthreads();
+        wave_lds_sync();
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
         ct_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, 0, q, qinv);
 #pragma unroll
         for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
-        __syncthreads();
+        wave_lds_sync();
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
-        __syncthreads();  // the next digit writes the same LDS rows
+        wave_lds_sync();  // the next digit writes the same LDS rows
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = red(v[i], q, qinv);

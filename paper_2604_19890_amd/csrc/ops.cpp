@@ -614,37 +614,74 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
     CipherP ct;
   };
   std::vector<Inner> inner(g);
+  // Sums at the same level read the same aligned baby powers: one multi-output
+  // pass per level reads each power once for all of them (a power absent from
+  // a sum has no term there, so every sum gets the words of its own pass).
+  std::map<int, std::vector<int>> by_level;
+  std::vector<std::vector<int>> used(g);
   for (int j = 0; j < g; ++j) {
-    std::vector<int> used;
     for (int i = 1; i < kk; ++i)
-      if (coef(j * kk + i) != 0) used.push_back(i);
-    const int64_t cst = coef(j * kk);
-    if (used.empty()) {
-      inner[j] = Inner{true, cst, nullptr};
+      if (coef(j * kk + i) != 0) used[j].push_back(i);
+    if (used[j].empty()) {
+      inner[j] = Inner{true, coef(j * kk), nullptr};
       continue;
     }
     int lv = 1 << 30;
-    for (int i : used) lv = std::min(lv, baby[i]->v.level);
-    // sum_i c_{jk+i} x^i (+ c_{jk}) in one pass: the scalar products and additions
-    // are exact in every Z_q_i, so one linear combination gives the same words as
-    // the term-by-term accumulation
-    std::vector<CipherP> keep;
-    std::vector<const uint64_t*> xs;
-    std::vector<int> rws;
-    for (int i : used) {
-      keep.push_back(aligned_power(i, lv));
-      xs.push_back(keep.back()->v.d);
-      rws.push_back(j * kk + i);
+    for (int i : used[j]) lv = std::min(lv, baby[i]->v.level);
+    by_level[lv].push_back(j);
+  }
+  for (auto& kv : by_level) {
+    const int lv = kv.first;
+    const std::vector<int>& js = kv.second;
+    std::vector<int> terms;
+    for (int j : js) terms.insert(terms.end(), used[j].begin(), used[j].end());
+    std::sort(terms.begin(), terms.end());
+    terms.erase(std::unique(terms.begin(), terms.end()), terms.end());
+    if ((int)terms.size() <= lk::LC_MAXT) {
+      std::vector<CipherP> keep;
+      lk::LinMulti m{};
+      for (size_t t = 0; t < terms.size(); ++t) {
+        keep.push_back(aligned_power(terms[t], lv));
+        m.x[t] = keep.back()->v.d;
+      }
+      for (size_t s0 = 0; s0 < js.size(); s0 += lk::LC_MAXO) {
+        const int no = (int)std::min<size_t>(lk::LC_MAXO, js.size() - s0);
+        for (int o = 0; o < no; ++o) {
+          const int j = js[s0 + o];
+          CipherP acc = new_cipher(c, x->v.n, lv, x->v.t_exp);
+          m.out[o] = acc->v.d;
+          for (size_t t = 0; t < terms.size(); ++t)
+            m.row[o][t] = coef(j * kk + terms[t]) != 0 ? j * kk + terms[t] : -1;
+          m.cst_row[o] = coef(j * kk) != 0 ? j * kk : -1;
+          inner[j] = Inner{false, 0, acc};
+        }
+        lk::lincomb_multi(c, m, (int)terms.size(), no, tab, c->prm.L, x->v.n, lv);
+      }
+      continue;
     }
-    CipherP acc = new_cipher(c, x->v.n, lv, x->v.t_exp);
-    for (size_t s = 0; s < xs.size(); s += 16) {
-      const int nt = (int)std::min<size_t>(16, xs.size() - s);
-      CipherP part = s == 0 ? acc : new_cipher(c, x->v.n, lv, x->v.t_exp);
-      lk::lincomb(c, xs.data() + s, rws.data() + s, nt, tab, c->prm.L, (s == 0 && cst != 0) ? j * kk : -1,
-                  part->v.d, x->v.n, lv);
-      if (s > 0) op_add_sub(c, acc->v, part->v, acc->v, 0);
+    for (int j : js) {
+      // sum_i c_{jk+i} x^i (+ c_{jk}) in passes of at most 16 terms: the scalar
+      // products and additions are exact in every Z_q_i, so the linear
+      // combinations give the same words as the term-by-term accumulation
+      const int64_t cst = coef(j * kk);
+      std::vector<CipherP> keep;
+      std::vector<const uint64_t*> xs;
+      std::vector<int> rws;
+      for (int i : used[j]) {
+        keep.push_back(aligned_power(i, lv));
+        xs.push_back(keep.back()->v.d);
+        rws.push_back(j * kk + i);
+      }
+      CipherP acc = new_cipher(c, x->v.n, lv, x->v.t_exp);
+      for (size_t s = 0; s < xs.size(); s += 16) {
+        const int nt = (int)std::min<size_t>(16, xs.size() - s);
+        CipherP part = s == 0 ? acc : new_cipher(c, x->v.n, lv, x->v.t_exp);
+        lk::lincomb(c, xs.data() + s, rws.data() + s, nt, tab, c->prm.L, (s == 0 && cst != 0) ? j * kk : -1,
+                    part->v.d, x->v.n, lv);
+        if (s > 0) op_add_sub(c, acc->v, part->v, acc->v, 0);
+      }
+      inner[j] = Inner{false, 0, acc};
     }
-    inner[j] = Inner{false, 0, acc};
   }
   // the inner sums hold everything the outer sum needs from the baby steps
   aligned.clear();
