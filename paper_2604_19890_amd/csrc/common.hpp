@@ -36,7 +36,17 @@ struct LimbMap {
   int dnum_p;
   int first;
   int offset;  // added to the launch's limb index before the map is applied
+  // Optional physical placement: with grp > 0, launch limb l is stored at row
+  // (l / grp) * grp_stride + grp_first + l % grp of the data (groups of rows at a
+  // stride, e.g. the special rows of every polynomial of a wider buffer).
+  int grp;
+  int grp_stride;
+  int grp_first;
 };
+
+__device__ __forceinline__ int limb_phys(const LimbMap& lm, int l) {
+  return lm.grp > 0 ? (l / lm.grp) * lm.grp_stride + lm.grp_first + l % lm.grp : l;
+}
 
 __device__ __forceinline__ int limb_prime(const LimbMap& lm, int l) {
   l += lm.offset;

@@ -90,11 +90,15 @@ namespace lk {
 void ntt_split(const bgv_ctx* c, int* p1, int* p2);
 // true when the forward NTT has two passes (log N > 8), so the second can be fused
 bool ntt_fused_inner_ok(const bgv_ctx* c);
-// ModUp output y [n][dn][level+K][N] (coefficient form except the own-digit rows):
-// first NTT pass in place, then the second pass fused with the inner product -> u [n][2][level+K][N]
-void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* key, uint64_t* u, int n, int level);
+// ModUp output y [n][dn][level+K][N] (coefficient form; the own-digit rows are not
+// read): first NTT pass in place, then the second pass fused with the inner product
+// -> u [n][2][level+K][N].  The own-digit rows are the rows of x, the switched
+// polynomial in evaluation form ([n][level][N] at ciphertext stride x_ct_stride).
+void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,
+                         uint64_t* u, int n, int level);
 // NTT over n_limbs limbs of length N at d (limb l uses the prime given by lm).
-void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse);
+// the first pass reads src when it is given (out of place), every pass writes d
+void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse, const uint64_t* src = nullptr);
 
 // out = a (op) b elementwise per limb; op 0 add, 1 sub; b_bcast: b has one ciphertext
 void add_sub(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n, int level, int op,
@@ -114,9 +118,10 @@ void mod_up(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level);
 void mod_up_copy_own(bgv_ctx* c, const uint64_t* x_eval, int64_t x_ct_stride, uint64_t* y, int n, int level);
 // u [n][2][level+K][N] = sum_j y[n][j][m] * key[j][c][row(m)]
 void key_inner(bgv_ctx* c, const uint64_t* y, const uint64_t* key, uint64_t* u, int n, int level);
-// delta rows: from the coefficient-form special limbs up [n*2][K][N]
-// write dl [n][2][level][N] (coefficient form) = FBC_{P->Q}([u_P t^-1]_P)
-void mod_down_delta(bgv_ctx* c, const uint64_t* u_coeff, uint64_t* dl, int n, int level, int t_exp);
+// delta rows: from the coefficient-form special limbs of polynomial cc (K rows at
+// u_coeff + cc * u_stride) write dl [n][2][level][N] (coefficient form) = FBC_{P->Q}([u_P t^-1]_P)
+void mod_down_delta(bgv_ctx* c, const uint64_t* u_coeff, int64_t u_stride, uint64_t* dl, int n, int level,
+                    int t_exp);
 // out[n][2][level] = add[n][c][i] + (u[n][c][i] - t dl[n][c][i]) * P^-1   (evaluation form)
 // add points at [n][3][level][N] tensor output (components 0, 1) or [n][2][level][N] with add_stride
 void mod_down_final(bgv_ctx* c, const uint64_t* u, const uint64_t* dl, const uint64_t* addsrc,
@@ -145,7 +150,8 @@ void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* 
 void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, const double* sc, int sc_stride,
              int cst_row, uint64_t* out, int n, int level);
 // product step with the modulus switch merged into ModDown (see kernels.hip)
-void ms_corr(bgv_ctx* c, const uint64_t* up, const uint64_t* tops, uint64_t* e, int n, int level, int t_exp);
+void ms_corr(bgv_ctx* c, const uint64_t* up, int64_t up_stride, const uint64_t* utop, int64_t ut_stride,
+             const uint64_t* dtop, int64_t dt_stride, uint64_t* e, int n, int level, int t_exp);
 void ms_final(bgv_ctx* c, const uint64_t* d, const uint64_t* u, const uint64_t* e, uint64_t* out, int n, int level);
 // out (one ciphertext) = sum of the n ciphertexts of x
 void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level);

@@ -178,14 +178,16 @@ __global__ void k_key_inner(const uint64_t* __restrict__ y, const uint64_t* __re
   }
 }
 
-// ModDown correction: from the coefficient-form special rows up [n*2][K][N], w_k = [u_k t^-1]_{p_k},
-// v_k = [w_k Phat_k^-1]_{p_k} (both in [0, p_k)), dl_i = sum_k v_k (Phat_k mod q_i) mod q_i.
-__global__ void k_mod_down_delta(const uint64_t* __restrict__ u, uint64_t* __restrict__ dl, int level, int N, int K,
+// ModDown correction: from the coefficient-form special rows of polynomial cc (K rows
+// at u + cc * u_stride, N words apart), w_k = [u_k t^-1]_{p_k}, v_k = [w_k Phat_k^-1]_{p_k}
+// (both in [0, p_k)), dl_i = sum_k v_k (Phat_k mod q_i) mod q_i.
+__global__ void k_mod_down_delta(const uint64_t* __restrict__ u, int64_t u_stride, uint64_t* __restrict__ dl,
+                                 int level, int N, int K,
                                  int Lfull, const double* __restrict__ md, const double* __restrict__ tinv,
                                  const PrimeD* __restrict__ pc) {
   const int cc = blockIdx.y;  // ct * 2 + comp
   const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t* U = u + (size_t)cc * K * N + n0;
+  const uint64_t* U = u + (size_t)cc * u_stride + n0;
   const double* phat_inv = md;
   const double* phat_mod = md + K;  // [K][Lfull]
   double v[8];
@@ -389,15 +391,18 @@ __global__ void k_lincomb_multi(lk::LinMulti m, int nt, int no, const double* __
 }
 
 // Product step with the modulus switch merged into ModDown, part 1 (coefficient form).
-// For ciphertext ct and component c: from the special rows up [ct*2+c][K][N] the
-// ModDown correction wt_i = FBC_{P->Q}([u_P t^-1]_P) is formed for every q_i; the top
+// For polynomial cc = ct*2+c: from its coefficient-form special rows (K rows at
+// up + cc * up_stride, N words apart) the ModDown correction
+// wt_i = FBC_{P->Q}([u_P t^-1]_P) is formed for every q_i; the top
 // limb of the relinearised product in coefficient form is
 //   o_top = d_top + (u_top - t wt_top) P^-1,
 // its switch correction w = centered([o_top t^-1]_{q_top}), and the combined
 // correction e_i = t P^-1 wt_i + t w (mod q_i) for i < level-1 is written to e.
-// tops [2][n*2][N] holds u_top (first half) and d_top (second half).
-__global__ void k_ms_corr(const uint64_t* __restrict__ up, const uint64_t* __restrict__ tops,
-                          uint64_t* __restrict__ e, int n, int level, int N, int K, int Lfull,
+// u_top and d_top of polynomial cc (coefficient form) are at utop + cc * ut_stride and
+// dtop + cc * dt_stride.
+__global__ void k_ms_corr(const uint64_t* __restrict__ up, int64_t up_stride, const uint64_t* __restrict__ utop,
+                          int64_t ut_stride, const uint64_t* __restrict__ dtop, int64_t dt_stride,
+                          uint64_t* __restrict__ e, int level, int N, int K, int Lfull,
                           const double* __restrict__ md, const double* __restrict__ tinv,
                           const double* __restrict__ tmod, const PrimeD* __restrict__ pc) {
   const int cc = blockIdx.y;  // ct * 2 + comp
@@ -405,7 +410,7 @@ __global__ void k_ms_corr(const uint64_t* __restrict__ up, const uint64_t* __res
   const double* phat_inv = md;
   const double* phat_mod = md + K;
   const double* pinv = md + K + (size_t)K * Lfull;
-  const uint64_t* U = up + (size_t)cc * K * N + n0;
+  const uint64_t* U = up + (size_t)cc * up_stride + n0;
   double v[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -430,8 +435,8 @@ __global__ void k_ms_corr(const uint64_t* __restrict__ up, const uint64_t* __res
   {
     const double q = pc[it].q, qinv = pc[it].qinv;
     const double wt = fbc(it, q, qinv);
-    const double ut = u2d(tops[(size_t)cc * N + n0]);
-    const double dt = u2d(tops[((size_t)n * 2 + cc) * N + n0]);
+    const double ut = u2d(utop[(size_t)cc * ut_stride + n0]);
+    const double dt = u2d(dtop[(size_t)cc * dt_stride + n0]);
     const double diff = red(ut - mul_lazy(wt, tmod[it], q, qinv), q, qinv);
     const double o = canon(red(dt + mul_lazy(diff, pinv[it], q, qinv), q, qinv), q);
     const double w = canon(mul_lazy(o, tinv[it], q, qinv), q);
@@ -615,9 +620,10 @@ void key_inner(bgv_ctx* c, const uint64_t* y, const uint64_t* key, uint64_t* u, 
                        c->Ltot, n, c->d_prime);
 }
 
-void mod_down_delta(bgv_ctx* c, const uint64_t* u, uint64_t* dl, int n, int level, int t_exp) {
-  hipLaunchKernelGGL(k_mod_down_delta, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, u, dl, level,
-                     c->N, c->prm.K, c->prm.L, c->d_moddown, c->d_tconst + (size_t)2 * t_exp * c->Ltot, c->d_prime);
+void mod_down_delta(bgv_ctx* c, const uint64_t* u, int64_t u_stride, uint64_t* dl, int n, int level, int t_exp) {
+  hipLaunchKernelGGL(k_mod_down_delta, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, u, u_stride, dl,
+                     level, c->N, c->prm.K, c->prm.L, c->d_moddown, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
+                     c->d_prime);
 }
 
 void mod_down_final(bgv_ctx* c, const uint64_t* u, const uint64_t* dl, const uint64_t* add, int64_t add_stride,
@@ -671,9 +677,10 @@ void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* 
                      sc, sc_stride, level, c->N, c->d_prime);
 }
 
-void ms_corr(bgv_ctx* c, const uint64_t* up, const uint64_t* tops, uint64_t* e, int n, int level, int t_exp) {
-  hipLaunchKernelGGL(k_ms_corr, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, up, tops, e, n, level,
-                     c->N, c->prm.K, c->prm.L, c->d_moddown, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
+void ms_corr(bgv_ctx* c, const uint64_t* up, int64_t up_stride, const uint64_t* utop, int64_t ut_stride,
+             const uint64_t* dtop, int64_t dt_stride, uint64_t* e, int n, int level, int t_exp) {
+  hipLaunchKernelGGL(k_ms_corr, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, up, up_stride, utop,
+                     ut_stride, dtop, dt_stride, e, level, c->N, c->prm.K, c->prm.L, c->d_moddown, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
                      c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
 }
 

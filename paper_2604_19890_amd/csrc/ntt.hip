@@ -102,9 +102,11 @@ __device__ __forceinline__ void gs_stages(double* v, const double* __restrict__ 
   }
 }
 
+// One pass over data; the pass reads from src (data itself when src is null,
+// the transform then being in place) and writes to data.
 template <int LOGS, bool INV>
-__global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data, int logN, int s0, LimbMap lm,
-                                                     const PrimeD* __restrict__ pc,
+__global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint64_t* src, int logN, int s0,
+                                                     LimbMap lm, const PrimeD* __restrict__ pc,
                                                      const double* __restrict__ tw, int last) {
   constexpr int S = 1 << LOGS;
   constexpr int T = S / 16;
@@ -125,7 +127,9 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
   const int pi = limb_prime(lm, limb);
   const double q = pc[pi].q, qinv = pc[pi].qinv;
   const double* __restrict__ w = tw + (size_t)pi * N;
-  uint64_t* __restrict__ x = data + (size_t)limb * N;
+  const size_t row = (size_t)limb_phys(lm, limb) * N;
+  uint64_t* x = data + row;
+  const uint64_t* xs = (src ? src : data) + row;
   const int tmax_log = logN - s0 - 1;
   const int tmin_log = logN - s0 - LOGS;
   const int tmin = 1 << tmin_log;
@@ -146,12 +150,13 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
   const int gs1_log = T_LOG + tmin_log;
   // consecutive layout: register i holds global index g2 + i * tmin
   const int g2 = base + ((16 * tau) << tmin_log);
-  uint64_t* __restrict__ xp = x + g1;
+  uint64_t* xp = x + g1;
+  const uint64_t* xsp = xs + g1;
   const bool wave_local = tmin == 1;
   double v[16];
 
 #pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = u2d(xp[(size_t)i << gs1_log]);
+  for (int i = 0; i < 16; ++i) v[i] = u2d(xsp[(size_t)i << gs1_log]);
 
   if (!INV) {
     ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
@@ -194,8 +199,9 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
 }
 
 // Second forward pass fused with the key-switching inner product, over the
-// ModUp output y [n][dn][rows][N] whose first pass is done (rows of a digit's own
-// primes are already in evaluation form and are used as they are).  A block
+// ModUp output y [n][dn][rows][N] whose first pass is done.  The rows of a
+// digit's own primes are not in y: they are the input x itself (evaluation form,
+// [n][level][N] at ciphertext stride xs) and are used as they are.  A block
 // handles one (row block, target row m, ciphertext): for every digit j it
 // finishes the transform of y[ct][j][m] in registers and LDS, multiplies it by
 // key[j][comp][prime(m)] and accumulates; u[ct][comp][m] receives the sums.
@@ -205,6 +211,7 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* __restrict__ data
 // rows are then read once into that XCD's L2 and shared by all ciphertexts.
 template <int LOGS>
 __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __restrict__ y,
+                                                           const uint64_t* __restrict__ xown, int64_t xs,
                                                            const uint64_t* __restrict__ key,
                                                            uint64_t* __restrict__ u, int logN, int s0, int level,
                                                            int dn, int K, int alpha, int Lfull, int Ltot, int n_ct,
@@ -252,19 +259,23 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
   // and twiddles instead of two.
   const uint64_t* __restrict__ yrow = y + ((size_t)ct * dn * rows + m) * N + g1;
   const size_t ystep = (size_t)rows * N;
+  const int own_j = m < level ? m / alpha : -1;  // the digit whose own prime m is
+  const uint64_t* __restrict__ xrow = xown + (size_t)ct * xs + (size_t)m * N + g1;
   uint64_t yn[16];
+  {
+    const uint64_t* __restrict__ yp = own_j == 0 ? xrow : yrow;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) yn[i] = yrow[(size_t)i << gs1_log];
+    for (int i = 0; i < 16; ++i) yn[i] = yp[(size_t)i << gs1_log];
+  }
   for (int j = 0; j < dn; ++j) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = u2d(yn[i]);
     if (j + 1 < dn) {
-      const uint64_t* __restrict__ yp = yrow + (size_t)(j + 1) * ystep;
+      const uint64_t* __restrict__ yp = own_j == j + 1 ? xrow : yrow + (size_t)(j + 1) * ystep;
 #pragma unroll
       for (int i = 0; i < 16; ++i) yn[i] = yp[(size_t)i << gs1_log];
     }
-    const bool own = m < level && m / alpha == j;
-    if (!own) {
+    if (j != own_j) {
       ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
       if (T > 1) {  // with T = 1 the four register stages were all of the pass
 #pragma unroll
@@ -308,7 +319,8 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
 }
 
 template <bool INV>
-void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int s0, int last) {
+void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int s0, int last,
+                 const uint64_t* src = nullptr) {
   const int N = c->N;
   const int S = 1 << logS;
   const int T = S / 16;
@@ -319,8 +331,8 @@ void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int
   switch (logS) {
 #define CASE(LS)                                                                                           \
   case LS:                                                                                                 \
-    hipLaunchKernelGGL((k_ntt_pass<LS, INV>), grid, dim3(NT), 0, c->stream, d, c->logN, s0, lm, c->d_prime, \
-                       tw, last);                                                                          \
+    hipLaunchKernelGGL((k_ntt_pass<LS, INV>), grid, dim3(NT), 0, c->stream, d, src, c->logN, s0, lm,   \
+                       c->d_prime, tw, last);                                                              \
     break;
     CASE(4)
     CASE(5)
@@ -352,7 +364,8 @@ void ntt_split(const bgv_ctx* c, int* p1, int* p2) {
 
 bool ntt_fused_inner_ok(const bgv_ctx* c) { return c->logN > 8; }
 
-void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* key, uint64_t* u, int n, int level) {
+void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,
+                         uint64_t* u, int n, int level) {
   const int logN = c->logN;
   int p1, p2;
   ntt_split(c, &p1, &p2);
@@ -367,8 +380,8 @@ void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* key, uint64_t*
   switch (p2) {
 #define CASE2(LS)                                                                                              \
   case LS:                                                                                                     \
-    hipLaunchKernelGGL((k_ntt2_key_inner<LS>), grid, dim3(NT), 0, c->stream, y, key, u, logN, p1, level, dn, K, A, \
-                       L, c->Ltot, n, c->d_prime, c->d_tw);                                                    \
+    hipLaunchKernelGGL((k_ntt2_key_inner<LS>), grid, dim3(NT), 0, c->stream, y, x, x_ct_stride, key, u, logN, p1, \
+                       level, dn, K, A, L, c->Ltot, n, c->d_prime, c->d_tw);                                   \
     break;
     CASE2(4)
     CASE2(5)
@@ -381,28 +394,30 @@ void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* key, uint64_t*
   }
 }
 
-void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse) {
+void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse, const uint64_t* src) {
   if (n_limbs <= 0) return;
   int p1, p2;
   ntt_split(c, &p1, &p2);
   // Two-pass transforms run chunk by chunk so that a chunk's first-pass output is
   // still in L2 / Infinity Cache when the second pass reads it.  The limb map is
   // shifted with the chunk: limb l of the chunk is limb off + l of the launch.
-  const int chunk = (p2 && c->ntt_chunk > 0) ? c->ntt_chunk : n_limbs;
+  // Transforms with a physical row placement or a separate source run whole.
+  const bool whole = lm.grp > 0 || src != nullptr;
+  const int chunk = (p2 && c->ntt_chunk > 0 && !whole) ? c->ntt_chunk : n_limbs;
   for (int off = 0; off < n_limbs; off += chunk) {
     const int cnt = n_limbs - off < chunk ? n_limbs - off : chunk;
     uint64_t* dc = d + (size_t)off * c->N;
     LimbMap lc = lm;
     lc.offset = lm.offset + off;
     if (!inverse) {
-      launch_pass<false>(c, dc, cnt, lc, p1, 0, p2 == 0);
+      launch_pass<false>(c, dc, cnt, lc, p1, 0, p2 == 0, src);
       if (p2) launch_pass<false>(c, dc, cnt, lc, p2, p1, 1);
     } else {
       if (p2) {
-        launch_pass<true>(c, dc, cnt, lc, p2, p1, 0);
+        launch_pass<true>(c, dc, cnt, lc, p2, p1, 0, src);
         launch_pass<true>(c, dc, cnt, lc, p1, 0, 1);
       } else {
-        launch_pass<true>(c, dc, cnt, lc, p1, 0, 1);
+        launch_pass<true>(c, dc, cnt, lc, p1, 0, 1, src);
       }
     }
   }

@@ -95,18 +95,22 @@ void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out) {
 }
 
 // Hybrid key switching, first half: ModUp of each digit of the polynomial x
-// (X = [n][level][N] in evaluation form; overwritten), NTT, and the inner product
+// (X = [n][level][N] in evaluation form, left as it is), NTT, and the inner product
 // with the key.  Returns u [n][2][level+K][N] in evaluation form.
-static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, Scratch& X, int n, int level) {
+static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const Scratch& X, int n, int level) {
   const int N = c->N, K = c->prm.K, L = c->prm.L, A = c->alpha;
   const int dn = (level + A - 1) / A, rows = level + K;
   Scratch Y(c, (size_t)n * dn * rows * N);
-  lk::mod_up_copy_own(c, X.d, (int64_t)level * N, Y.d, n, level);  // the digit's own rows stay as they are
-  op_ntt(c, X.d, n, level, true);
-  lk::mod_up(c, X.d, Y.d, n, level);
+  Scratch Xc(c, (size_t)n * level * N);
+  const bool fused = lk::ntt_fused_inner_ok(c);
+  // a digit's own rows are x as it is: the fused pass reads them from X, the
+  // unfused path from a copy in Y
+  if (!fused) lk::mod_up_copy_own(c, X.d, (int64_t)level * N, Y.d, n, level);
+  lk::ntt(c, Xc.d, n * level, lm_chain(c, level), true, X.d);  // coefficient form of x, out of place
+  lk::mod_up(c, Xc.d, Y.d, n, level);
   std::unique_ptr<Scratch> U(new Scratch(c, (size_t)n * 2 * rows * N));
-  if (lk::ntt_fused_inner_ok(c)) {
-    lk::ntt_pass1_key_inner(c, Y.d, key, U->d, n, level);
+  if (fused) {
+    lk::ntt_pass1_key_inner(c, Y.d, X.d, (int64_t)level * N, key, U->d, n, level);
   } else {
     lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0}, false);
     lk::key_inner(c, Y.d, key, U->d, n, level);
@@ -114,26 +118,24 @@ static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, Scratc
   return U;
 }
 
-// special rows of u -> coefficient form [n*2][K][N]
-static std::unique_ptr<Scratch> special_rows_coeff(bgv_ctx* c, const Scratch& U, int n, int level) {
-  const int N = c->N, K = c->prm.K, rows = level + K;
-  std::unique_ptr<Scratch> Up(new Scratch(c, (size_t)n * 2 * K * N));
-  check_hip(c,
-            hipMemcpy2DAsync(Up->d, (size_t)K * N * 8, U.d + (size_t)level * N, (size_t)rows * N * 8, (size_t)K * N * 8,
-                             (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
-            "gather special");
-  lk::ntt(c, Up->d, n * 2 * K, LimbMap{K, 0, c->prm.L, 0, 1, 0, 0}, true);
-  return Up;
+// The special rows of u [n][2][level+K][N] to coefficient form, in place.
+static void special_rows_coeff(bgv_ctx* c, Scratch& U, int n, int level) {
+  const int K = c->prm.K, rows = level + K;
+  LimbMap lm{K, 0, c->prm.L, 0, 1, 0, 0};
+  lm.grp = K;
+  lm.grp_stride = rows;
+  lm.grp_first = level;
+  lk::ntt(c, U.d, n * 2 * K, lm, true);
 }
 
 // Hybrid key switching of X under `key`; out[b][comp] = add[b][comp] (comp < add_comps) + switched[comp].
 static void key_switch(bgv_ctx* c, const uint64_t* key, Scratch& X, int n, int level, int t_exp, const uint64_t* add,
                        int64_t add_stride, int add_comps, uint64_t* out) {
-  const int N = c->N;
+  const int N = c->N, rows = level + c->prm.K;
   auto U = ks_inner(c, key, X, n, level);
-  auto Up = special_rows_coeff(c, *U, n, level);
+  special_rows_coeff(c, *U, n, level);
   Scratch DL(c, (size_t)n * 2 * level * N);
-  lk::mod_down_delta(c, Up->d, DL.d, n, level, t_exp);
+  lk::mod_down_delta(c, U->d + (size_t)level * N, (int64_t)rows * N, DL.d, n, level, t_exp);
   op_ntt(c, DL.d, n * 2, level, false);
   lk::mod_down_final(c, U->d, DL.d, add, add_comps == 2 ? add_stride : -add_stride, out, n, level, t_exp);
 }
@@ -141,7 +143,8 @@ static void key_switch(bgv_ctx* c, const uint64_t* key, Scratch& X, int n, int l
 // Relinearised product followed by one modulus switch, with the switch merged into
 // ModDown: both corrections are formed in coefficient form and go through one NTT
 // (the transform is linear over every Z_q_i, so the words equal those of the
-// relinearised product followed by the separate switch).
+// relinearised product followed by the separate switch).  The top rows of u and d
+// are dropped by the switch, so they are brought to coefficient form in place.
 void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
   const int n = a.n, lv = a.level, N = c->N, K = c->prm.K;
   if (lv < 2) throw OpError{BGV_E_LEVEL};
@@ -149,22 +152,17 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
   lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1);
   auto U = ks_inner(c, keys->relin, X, n, lv);
-  auto Up = special_rows_coeff(c, *U, n, lv);
-  // top limbs in coefficient form: u tops [n*2][N], then d tops [n*2][N]
-  Scratch Tp(c, (size_t)4 * n * N);
-  check_hip(c,
-            hipMemcpy2DAsync(Tp.d, (size_t)N * 8, U->d + (size_t)(lv - 1) * N, (size_t)rows * N * 8, (size_t)N * 8,
-                             (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
-            "gather u top");
-  for (int comp = 0; comp < 2; ++comp)
-    check_hip(c,
-              hipMemcpy2DAsync(Tp.d + ((size_t)2 * n + comp) * N, (size_t)2 * N * 8,
-                               D.d + ((size_t)comp * lv + (lv - 1)) * N, (size_t)2 * lv * N * 8, (size_t)N * 8,
-                               (size_t)n, hipMemcpyDeviceToDevice, c->stream),
-              "gather d top");
-  lk::ntt(c, Tp.d, 4 * n, LimbMap{1, 1, c->prm.L, 0, 1, lv - 1, 0}, true);
+  special_rows_coeff(c, *U, n, lv);
+  LimbMap top{1, 1, c->prm.L, 0, 1, lv - 1, 0};
+  top.grp = 1;
+  top.grp_stride = rows;
+  top.grp_first = lv - 1;
+  lk::ntt(c, U->d, 2 * n, top, true);  // u tops
+  top.grp_stride = lv;
+  lk::ntt(c, D.d, 2 * n, top, true);  // d tops
   Scratch E(c, (size_t)n * 2 * (lv - 1) * N);
-  lk::ms_corr(c, Up->d, Tp.d, E.d, n, lv, a.t_exp);
+  lk::ms_corr(c, U->d + (size_t)lv * N, (int64_t)rows * N, U->d + (size_t)(lv - 1) * N, (int64_t)rows * N,
+              D.d + (size_t)(lv - 1) * N, (int64_t)lv * N, E.d, n, lv, a.t_exp);
   op_ntt(c, E.d, n * 2, lv - 1, false);
   lk::ms_final(c, D.d, U->d, E.d, out.d, n, lv);
 }
