@@ -226,11 +226,10 @@ void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out) {
     op_mod_switch(c, in, out);
     return;
   }
-  // coefficient form, then at most 16 drops per launch; chained launches are the
-  // same sequence of single-prime drops
+  // coefficient form (out of place), then at most 16 drops per launch; chained
+  // launches are the same sequence of single-prime drops
   std::unique_ptr<Scratch> A(new Scratch(c, (size_t)n * 2 * lv * N));
-  check_hip(c, hipMemcpyAsync(A->d, in.d, (size_t)n * 2 * lv * N * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
-  op_ntt(c, A->d, n * 2, lv, true);
+  lk::ntt(c, A->d, n * 2 * lv, lm_chain(c, lv), true, in.d);
   const int maxd = 16;
   int cur = lv;
   while (cur - to > maxd) {
