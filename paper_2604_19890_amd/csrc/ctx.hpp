@@ -97,8 +97,26 @@ bool ntt_fused_inner_ok(const bgv_ctx* c);
 void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,
                          uint64_t* u, int n, int level);
 // NTT over n_limbs limbs of length N at d (limb l uses the prime given by lm).
-// the first pass reads src when it is given (out of place), every pass writes d
-void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse, const uint64_t* src = nullptr);
+// Epilogue of the last forward pass over rows (cc, i), i < rows, of the
+// transformed data: with e the transformed value,
+//   out = ((a - e * sv_i) + b * sb_i) * qt_i          (mod q_i)
+// where a row (cc, i) is at a + cc * a_cc + i * N, b (optional: null) likewise,
+// sv null stands for 1, and out has the layout of the data.
+struct NttEpi {
+  const uint64_t* a;
+  int64_t a_cc;
+  const uint64_t* b;
+  int64_t b_cc;
+  const double* sb;
+  const double* sv;
+  const double* qt;
+  uint64_t* out;
+  int rows;
+};
+// the first pass reads src when it is given (out of place), every pass writes d;
+// with epi the last forward pass writes epi->out instead (see NttEpi)
+void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse, const uint64_t* src = nullptr,
+         const NttEpi* epi = nullptr);
 
 // out = a (op) b elementwise per limb; op 0 add, 1 sub; b_bcast: b has one ciphertext
 void add_sub(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n, int level, int op,
@@ -129,8 +147,7 @@ void mod_down_final(bgv_ctx* c, const uint64_t* u, const uint64_t* dl, const uin
 // single drop: w rows from the coefficient-form top limbs top [n][2][N]:
 // wrow [n][2][level-1][N] = centered([top t^-1]_{q_top}) mod q_i  (coefficient form)
 void msw_w(bgv_ctx* c, const uint64_t* top, uint64_t* wrow, int n, int level, int t_exp);
-// out [n][2][level-1] = (a_i - t w_i) q_top^-1 (evaluation form)
-void msw_final(bgv_ctx* c, const uint64_t* a, const uint64_t* w, uint64_t* out, int n, int level, int t_exp);
+// (part 2, out_i = (a_i - t w_i) q_top^-1, is the epilogue of the forward NTT of w)
 // multi-drop in coefficient form: x [n][2][level][N] -> y [n][2][to][N]
 void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int to, int t_exp);
 // copy limb rows: y[b][c][i] = x[b][c][i] for i < to_level (x has from_level rows)
@@ -149,10 +166,10 @@ void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* 
 // out = sum_t sc[rows[t]][i] * xs[t] (+ sc[cst_row][i] on component 0); nt <= 16 terms, all at `level`
 void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, const double* sc, int sc_stride,
              int cst_row, uint64_t* out, int n, int level);
-// product step with the modulus switch merged into ModDown (see kernels.hip)
+// product step with the modulus switch merged into ModDown, part 1 (part 2 is the
+// epilogue of the forward NTT of e)
 void ms_corr(bgv_ctx* c, const uint64_t* up, int64_t up_stride, const uint64_t* utop, int64_t ut_stride,
              const uint64_t* dtop, int64_t dt_stride, uint64_t* e, int n, int level, int t_exp);
-void ms_final(bgv_ctx* c, const uint64_t* d, const uint64_t* u, const uint64_t* e, uint64_t* out, int n, int level);
 // out (one ciphertext) = sum of the n ciphertexts of x
 void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level);
 // automorphism in evaluation form: for each of n ciphertexts, `rows` limbs at x + ct*xs -> y + ct*ys

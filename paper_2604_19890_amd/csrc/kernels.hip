@@ -251,21 +251,6 @@ __global__ void k_msw_w(const uint64_t* __restrict__ top, uint64_t* __restrict__
   }
 }
 
-// single modulus switch, part 2: out_i = (a_i - t w_i) q_top^-1   (evaluation form)
-__global__ void k_msw_final(const uint64_t* __restrict__ a, const uint64_t* __restrict__ w, uint64_t* __restrict__ out,
-                            int level, int N, const double* __restrict__ qinv_top, const double* __restrict__ tmod,
-                            const PrimeD* __restrict__ pc) {
-  const int lv = level - 1;
-  const int i = blockIdx.y % lv;
-  const int cc = blockIdx.y / lv;
-  const double q = pc[i].q, qinv = pc[i].qinv;
-  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double x = u2d(a[((size_t)cc * level + i) * N + n0]);
-  const double ww = u2d(w[((size_t)cc * lv + i) * N + n0]);
-  const double diff = x - mul_lazy(ww, tmod[i], q, qinv);
-  out[((size_t)cc * lv + i) * N + n0] = to_u(mul_lazy(red(diff, q, qinv), qinv_top[i], q, qinv), q, qinv);
-}
-
 // repeated modulus switch in coefficient form: x [n*2][level][N] -> y [n*2][to][N],
 // at most MAXD = 16 drops per launch (longer drops are chained launches).  The
 // loops over drops are unrolled so that the per-drop corrections stay in registers.
@@ -452,24 +437,6 @@ __global__ void k_ms_corr(const uint64_t* __restrict__ up, int64_t up_stride, co
   }
 }
 
-// part 2 (evaluation form): out_i = (d_i + u_i P^-1 - e_i) q_top^-1 for i < level-1
-__global__ void k_ms_final(const uint64_t* __restrict__ d, const uint64_t* __restrict__ u,
-                           const uint64_t* __restrict__ e, uint64_t* __restrict__ out, int level, int N, int K,
-                           const double* __restrict__ pinv, const double* __restrict__ qinv_top,
-                           const PrimeD* __restrict__ pc) {
-  const int lv = level - 1;
-  const int i = blockIdx.y % lv;
-  const int cc = blockIdx.y / lv;
-  const int ct = cc >> 1, comp = cc & 1;
-  const double q = pc[i].q, qinv = pc[i].qinv;
-  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double dd = u2d(d[((size_t)ct * 2 * level + (size_t)comp * level + i) * N + n0]);
-  const double uu = u2d(u[((size_t)cc * (level + K) + i) * N + n0]);
-  const double ee = u2d(e[((size_t)cc * lv + i) * N + n0]);
-  const double s = red(dd - ee + mul_lazy(uu, pinv[i], q, qinv), q, qinv);
-  out[((size_t)cc * lv + i) * N + n0] = to_u(mul_lazy(s, qinv_top[i], q, qinv), q, qinv);
-}
-
 __device__ __forceinline__ uint32_t brv32(uint32_t v, int bits) { return __brev(v) >> (32 - bits); }
 
 // X -> X^g in evaluation form: slot j holds a(psi^(2 brv(j)+1)); the image holds
@@ -643,12 +610,6 @@ void msw_w(bgv_ctx* c, const uint64_t* top, uint64_t* w, int n, int level, int t
                      tinv_top, c->d_prime);
 }
 
-void msw_final(bgv_ctx* c, const uint64_t* a, const uint64_t* w, uint64_t* out, int n, int level, int t_exp) {
-  hipLaunchKernelGGL(k_msw_final, grid_for(c->N, n * 2 * (level - 1)), dim3(block_for(c->N)), 0, c->stream, a, w, out,
-                     level, c->N, c->d_msw + (size_t)(level - 1) * c->prm.L,
-                     c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
-}
-
 void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int to, int t_exp) {
   hipLaunchKernelGGL(k_msw_multi, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, x, y, level, to, c->N,
                      c->d_msw, c->prm.L, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
@@ -682,12 +643,6 @@ void ms_corr(bgv_ctx* c, const uint64_t* up, int64_t up_stride, const uint64_t* 
   hipLaunchKernelGGL(k_ms_corr, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, up, up_stride, utop,
                      ut_stride, dtop, dt_stride, e, level, c->N, c->prm.K, c->prm.L, c->d_moddown, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
                      c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
-}
-
-void ms_final(bgv_ctx* c, const uint64_t* d, const uint64_t* u, const uint64_t* e, uint64_t* out, int n, int level) {
-  const double* pinv = c->d_moddown + c->prm.K + (size_t)c->prm.K * c->prm.L;
-  hipLaunchKernelGGL(k_ms_final, grid_for(c->N, n * 2 * (level - 1)), dim3(block_for(c->N)), 0, c->stream, d, u, e,
-                     out, level, c->N, c->prm.K, pinv, c->d_msw + (size_t)(level - 1) * c->prm.L, c->d_prime);
 }
 
 void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level) {

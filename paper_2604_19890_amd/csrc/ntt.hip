@@ -103,11 +103,12 @@ __device__ __forceinline__ void gs_stages(double* v, const double* __restrict__ 
 }
 
 // One pass over data; the pass reads from src (data itself when src is null,
-// the transform then being in place) and writes to data.
-template <int LOGS, bool INV>
+// the transform then being in place) and writes to data, or with EPI (the last
+// forward pass) applies the epilogue ep and writes ep.out.
+template <int LOGS, bool INV, bool EPI>
 __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint64_t* src, int logN, int s0,
                                                      LimbMap lm, const PrimeD* __restrict__ pc,
-                                                     const double* __restrict__ tw, int last) {
+                                                     const double* __restrict__ tw, int last, lk::NttEpi ep) {
   constexpr int S = 1 << LOGS;
   constexpr int T = S / 16;
   constexpr int T_LOG = LOGS - 4;
@@ -194,8 +195,25 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
       for (int i = 0; i < 16; ++i) v[i] = mul_lazy(red(v[i], q, qinv), ninv, q, qinv);
     }
   }
+  if constexpr (EPI) {
+    const int gl = limb + lm.offset;
+    const int cc = gl / ep.rows, ii = gl - cc * ep.rows;
+    const size_t rr = (size_t)ii * N + g1;
+    const uint64_t* ap = ep.a + (size_t)cc * ep.a_cc + rr;
+    const uint64_t* bp = ep.b ? ep.b + (size_t)cc * ep.b_cc + rr : nullptr;
+    uint64_t* op = ep.out + row + g1;
+    const double qt = ep.qt[ii];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) xp[(size_t)i << gs1_log] = d2u(canon(red(v[i], q, qinv), q));
+    for (int i = 0; i < 16; ++i) {
+      const double e = canon(red(v[i], q, qinv), q);
+      double s = u2d(ap[(size_t)i << gs1_log]) - (ep.sv ? mul_lazy(e, ep.sv[ii], q, qinv) : e);
+      if (bp) s += mul_lazy(u2d(bp[(size_t)i << gs1_log]), ep.sb[ii], q, qinv);
+      op[(size_t)i << gs1_log] = to_u(mul_lazy(red(s, q, qinv), qt, q, qinv), q, qinv);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) xp[(size_t)i << gs1_log] = d2u(canon(red(v[i], q, qinv), q));
+  }
 }
 
 // Second forward pass fused with the key-switching inner product, over the
@@ -320,7 +338,7 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
 
 template <bool INV>
 void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int s0, int last,
-                 const uint64_t* src = nullptr) {
+                 const uint64_t* src = nullptr, const lk::NttEpi* epi = nullptr) {
   const int N = c->N;
   const int S = 1 << logS;
   const int T = S / 16;
@@ -331,8 +349,15 @@ void launch_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, int logS, int
   switch (logS) {
 #define CASE(LS)                                                                                           \
   case LS:                                                                                                 \
-    hipLaunchKernelGGL((k_ntt_pass<LS, INV>), grid, dim3(NT), 0, c->stream, d, src, c->logN, s0, lm,   \
-                       c->d_prime, tw, last);                                                              \
+    if constexpr (!INV) {                                                                                  \
+      if (epi) {                                                                                           \
+        hipLaunchKernelGGL((k_ntt_pass<LS, false, true>), grid, dim3(NT), 0, c->stream, d, src, c->logN, s0, \
+                           lm, c->d_prime, tw, last, *epi);                                                \
+        break;                                                                                             \
+      }                                                                                                    \
+    }                                                                                                      \
+    hipLaunchKernelGGL((k_ntt_pass<LS, INV, false>), grid, dim3(NT), 0, c->stream, d, src, c->logN, s0, lm,  \
+                       c->d_prime, tw, last, lk::NttEpi{});                                                \
     break;
     CASE(4)
     CASE(5)
@@ -394,15 +419,15 @@ void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_c
   }
 }
 
-void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse, const uint64_t* src) {
+void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse, const uint64_t* src, const NttEpi* epi) {
   if (n_limbs <= 0) return;
   int p1, p2;
   ntt_split(c, &p1, &p2);
   // Two-pass transforms run chunk by chunk so that a chunk's first-pass output is
   // still in L2 / Infinity Cache when the second pass reads it.  The limb map is
   // shifted with the chunk: limb l of the chunk is limb off + l of the launch.
-  // Transforms with a physical row placement or a separate source run whole.
-  const bool whole = lm.grp > 0 || src != nullptr;
+  // Transforms with a physical row placement, a separate source or an epilogue run whole.
+  const bool whole = lm.grp > 0 || src != nullptr || epi != nullptr;
   const int chunk = (p2 && c->ntt_chunk > 0 && !whole) ? c->ntt_chunk : n_limbs;
   for (int off = 0; off < n_limbs; off += chunk) {
     const int cnt = n_limbs - off < chunk ? n_limbs - off : chunk;
@@ -410,8 +435,8 @@ void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse, const u
     LimbMap lc = lm;
     lc.offset = lm.offset + off;
     if (!inverse) {
-      launch_pass<false>(c, dc, cnt, lc, p1, 0, p2 == 0, src);
-      if (p2) launch_pass<false>(c, dc, cnt, lc, p2, p1, 1);
+      launch_pass<false>(c, dc, cnt, lc, p1, 0, p2 == 0, src, p2 ? nullptr : epi);
+      if (p2) launch_pass<false>(c, dc, cnt, lc, p2, p1, 1, nullptr, epi);
     } else {
       if (p2) {
         launch_pass<true>(c, dc, cnt, lc, p2, p1, 0, src);

@@ -163,8 +163,18 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   Scratch E(c, (size_t)n * 2 * (lv - 1) * N);
   lk::ms_corr(c, U->d + (size_t)lv * N, (int64_t)rows * N, U->d + (size_t)(lv - 1) * N, (int64_t)rows * N,
               D.d + (size_t)(lv - 1) * N, (int64_t)lv * N, E.d, n, lv, a.t_exp);
-  op_ntt(c, E.d, n * 2, lv - 1, false);
-  lk::ms_final(c, D.d, U->d, E.d, out.d, n, lv);
+  // forward NTT of e with the final step in its last pass:
+  // out_i = (d_i - e_i + u_i P^-1) q_top^-1 for i < level-1
+  lk::NttEpi ep{};
+  ep.a = D.d;
+  ep.a_cc = (int64_t)lv * N;
+  ep.b = U->d;
+  ep.b_cc = (int64_t)rows * N;
+  ep.sb = c->d_moddown + K + (size_t)K * c->prm.L;  // P^-1 mod q_i
+  ep.qt = c->d_msw + (size_t)(lv - 1) * c->prm.L;   // q_top^-1 mod q_i
+  ep.out = out.d;
+  ep.rows = lv - 1;
+  lk::ntt(c, E.d, n * 2 * (lv - 1), lm_chain(c, lv - 1), false, nullptr, &ep);
 }
 
 void op_mul_relin(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
@@ -204,15 +214,19 @@ void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out) {
   lk::ntt(c, T.d, n * 2, LimbMap{1, 1, c->prm.L, 0, 1, lv - 1, 0}, true);
   Scratch W(c, (size_t)n * 2 * (lv - 1) * N);
   lk::msw_w(c, T.d, W.d, n, lv, in.t_exp);
-  op_ntt(c, W.d, n * 2, lv - 1, false);
-  if (out.d == in.d) {
-    Scratch O(c, (size_t)n * 2 * (lv - 1) * N);
-    lk::msw_final(c, in.d, W.d, O.d, n, lv, in.t_exp);
-    check_hip(c, hipMemcpyAsync(out.d, O.d, (size_t)n * 2 * (lv - 1) * N * 8, hipMemcpyDeviceToDevice, c->stream),
+  // forward NTT of w with the final step in its last pass:
+  // out_i = (x_i - t w_i) q_top^-1 for i < level-1
+  lk::NttEpi ep{};
+  ep.a = in.d;
+  ep.a_cc = (int64_t)lv * N;
+  ep.sv = c->d_tconst + ((size_t)2 * in.t_exp + 1) * c->Ltot;  // t mod q_i
+  ep.qt = c->d_msw + (size_t)(lv - 1) * c->prm.L;              // q_top^-1 mod q_i
+  ep.out = out.d == in.d ? W.d : out.d;  // in place: the result goes through w
+  ep.rows = lv - 1;
+  lk::ntt(c, W.d, n * 2 * (lv - 1), lm_chain(c, lv - 1), false, nullptr, &ep);
+  if (out.d == in.d)
+    check_hip(c, hipMemcpyAsync(out.d, W.d, (size_t)n * 2 * (lv - 1) * N * 8, hipMemcpyDeviceToDevice, c->stream),
               "copy");
-  } else {
-    lk::msw_final(c, in.d, W.d, out.d, n, lv, in.t_exp);
-  }
 }
 
 void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out) {

@@ -100,6 +100,9 @@ def test_mul_relin_and_mod_switch_match(pf):
     ms = c.lib.mod_switch(m)
     oms = [B.mod_switch(P, x) for x in om]
     c.assert_equal(ms, oms, "mod_switch")
+    # in place: the output buffer is the input's
+    m2 = c.lib.mul_relin(c.keys, ga, gb)
+    c.assert_equal(c.lib.mod_switch(m2, out=m2), oms, "mod_switch in place")
     to = max(1, P.L - 4)
     mt = c.lib.mod_switch_to(m, to)
     c.assert_equal(mt, [B.align(P, x, to) for x in om], "mod_switch_to")
@@ -191,7 +194,10 @@ def test_workload_glue_matches():
     gc, oc = c.enc_both(c_rows)
     gt, ot = c.enc_both([[100] * P.ell])
     m = c.lib.mul(c.keys, gb, gc)
-    c.assert_equal(m, [S._mul(P, c.okeys, x, y) for x, y in zip(ob, oc)], "mul")
+    om = [S._mul(P, c.okeys, x, y) for x, y in zip(ob, oc)]
+    c.assert_equal(m, om, "mul")
+    gbc = c.lib.mul_scalar(gb, 1)  # a copy of gb's words
+    c.assert_equal(c.lib.mul(c.keys, gbc, gc, out=gbc), om, "mul into its first operand")
     bs = c.lib.batch_sum(gb)
     c.assert_equal(bs, [B.add(P, ob[0], ob[1])], "batch_sum")
     fs = c.lib.filter_sum(c.keys, ga, gt, gb, gc)
