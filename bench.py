@@ -16,6 +16,7 @@ Also reported on the same line:
                   to rows/s by the query's count of schoolbook limb products.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +29,39 @@ sys.path.insert(0, ROOT)
 
 LOG_N, P_, R_, L_, K_ = 16, 257, 2, 30, 6
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of the forward NTT (both passes) on 960 limbs of N = 2^16, per pass, from
+# `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of `bench.py --ntt-only --cts 16
+# --steps 3` (profiles/ntt_n65536_960limbs_counters.md).  In the same runs a 480 MiB device
+# copy reads FETCH_SIZE = 245772 KiB and WRITE_SIZE = 491520 KiB, so FETCH_SIZE counts half
+# the bytes moved (scale 2.0) and WRITE_SIZE all of them (1.0).  The figures belong to the
+# NTT sources they were taken on (hash below) and are reported only while those are unchanged.
+NTT_COUNTERS = {
+    "sources_sha256": "178e738396b7ad16158f5ff98688cbce87fa20cb63987040a0ca917f22b25d6e",
+    "limbs": 960,
+    "fetch_kib": [246092, 253497],
+    "write_kib": [491520, 491520],
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+}
+
+
+def ntt_sources_sha256():
+    h = hashlib.sha256()
+    for name in ("ntt.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2604_19890_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def ntt_traffic_bytes(limbs):
+    """Counter-measured HBM bytes of one forward NTT over `limbs` limbs, or None when the NTT
+    sources differ from the ones the counters were read on."""
+    c = NTT_COUNTERS
+    if ntt_sources_sha256() != c["sources_sha256"]:
+        return None
+    per_transform = 1024 * (sum(c["fetch_kib"]) * c["fetch_scale"] + sum(c["write_kib"]) * c["write_scale"])
+    return per_transform * limbs / c["limbs"]
 
 
 def log(*a):
@@ -299,6 +333,12 @@ def main():
     ctx, keys, s, cols, thr, cts = setup(args)
     rows = args.cts * ctx.slots
 
+    # the dominant kernel, the forward NTT at the query's ciphertext shape, timed before the
+    # query so that it runs in the state the profiled `--ntt-only` command measures
+    ntt_s, ntt_bytes, ntt_limbs = time_ntt(ctx, min(args.cts, 16))
+    ntt_gbs = ntt_bytes / ntt_s / 1e9
+    log(f"[bench] NTT: {ntt_limbs} limbs in {ntt_s * 1e3:.3f} ms = {ntt_gbs:.0f} GB/s")
+
     elapsed, out = time_batched(ctx, keys, cts, args.steps, args.warmup)
     per_step = elapsed / args.steps
     value = rows / per_step
@@ -317,10 +357,7 @@ def main():
     if t_plain:
         log(f"[bench] plain: {t_plain * 1e3:.1f} ms for {args.plain} ciphertexts, {plain_rows:.1f} rows/s")
 
-    ntt_s, ntt_bytes, ntt_limbs = time_ntt(ctx, min(args.cts, 16))
-    ntt_gbs = ntt_bytes / ntt_s / 1e9
-    log(f"[bench] NTT: {ntt_limbs} limbs in {ntt_s * 1e3:.3f} ms = {ntt_gbs:.0f} GB/s")
-
+    traffic = ntt_traffic_bytes(ntt_limbs)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cts)
     line = {
         "metric": "encrypted filter+SUM rows/s @N=2^16 (batched)",
@@ -342,8 +379,10 @@ def main():
         "batched_over_plain": (value / plain_rows) if plain_rows else None,
         "ntt_gb_per_s": ntt_gbs,
         "roofline": {"bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ntt_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"forward NTT (both passes), {ntt_limbs} limbs of N=2^16 per launch pair"},
+                     "frac": ntt_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"k_ntt_pass, forward NTT (two passes) over {ntt_limbs} limbs of N=2^16; "
+                               f"achieved = 16 N bytes per limb / transform time; traffic = counter bytes "
+                               f"per transform"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

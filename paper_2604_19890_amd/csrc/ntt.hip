@@ -158,6 +158,24 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
 
 #pragma unroll
   for (int i = 0; i < 16; ++i) v[i] = u2d(xsp[(size_t)i << gs1_log]);
+  // the epilogue's rows are requested with the pass's own, so that they arrive
+  // while the butterflies run
+  uint64_t av[EPI ? 16 : 1], bv[EPI ? 16 : 1];
+  int ii = 0;
+  if constexpr (EPI) {
+    const int gl = limb + lm.offset;
+    const int cc = gl / ep.rows;
+    ii = gl - cc * ep.rows;
+    const size_t rr = (size_t)ii * N + g1;
+    const uint64_t* ap = ep.a + (size_t)cc * ep.a_cc + rr;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) av[i] = ap[(size_t)i << gs1_log];
+    if (ep.b) {
+      const uint64_t* bp = ep.b + (size_t)cc * ep.b_cc + rr;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) bv[i] = bp[(size_t)i << gs1_log];
+    }
+  }
 
   if (!INV) {
     ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
@@ -196,18 +214,13 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
     }
   }
   if constexpr (EPI) {
-    const int gl = limb + lm.offset;
-    const int cc = gl / ep.rows, ii = gl - cc * ep.rows;
-    const size_t rr = (size_t)ii * N + g1;
-    const uint64_t* ap = ep.a + (size_t)cc * ep.a_cc + rr;
-    const uint64_t* bp = ep.b ? ep.b + (size_t)cc * ep.b_cc + rr : nullptr;
     uint64_t* op = ep.out + row + g1;
     const double qt = ep.qt[ii];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const double e = canon(red(v[i], q, qinv), q);
-      double s = u2d(ap[(size_t)i << gs1_log]) - (ep.sv ? mul_lazy(e, ep.sv[ii], q, qinv) : e);
-      if (bp) s += mul_lazy(u2d(bp[(size_t)i << gs1_log]), ep.sb[ii], q, qinv);
+      double s = u2d(av[i]) - (ep.sv ? mul_lazy(e, ep.sv[ii], q, qinv) : e);
+      if (ep.b) s += mul_lazy(u2d(bv[i]), ep.sb[ii], q, qinv);
       op[(size_t)i << gs1_log] = to_u(mul_lazy(red(s, q, qinv), qt, q, qinv), q, qinv);
     }
   } else {
