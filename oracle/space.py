@@ -53,10 +53,27 @@ def _add(P, a, b):
     return B.add(P, B.align(P, a, lv), B.align(P, b, lv))
 
 
-def bsgs_shape(D: int):
+def odd_structured(c, D: int) -> bool:
+    """True when D >= 3 and every coefficient at an even index 2 <= i < D is zero: the
+    polynomial is odd apart from its constant and leading terms (G_{p,e} for odd p is odd,
+    Section IV's parity property; F_LT has odd terms and x^(p-1))."""
+    return D >= 3 and all(c[i] == 0 for i in range(2, D, 2))
+
+
+def bsgs_shape(D: int, odd: bool = False):
+    """Paterson-Stockmeyer split (Theorem 2): k baby powers, g giant steps in y = x^k.
+
+    Dense polynomials: k = smallest power of two with 2k^2 >= D+1.  Odd-structured ones
+    need only the odd baby powers, which halves the baby steps; the balance point moves to
+    k = smallest power of two with k^2 >= D+1 (a constant or a leading term at a multiple
+    of k lands in an inner sum as a constant)."""
     k = 1
-    while 2 * k * k < D + 1:
-        k *= 2
+    if odd:
+        while k * k < D + 1:
+            k *= 2
+    else:
+        while 2 * k * k < D + 1:
+            k *= 2
     g = -(-(D + 1) // k)
     return k, g
 
@@ -80,14 +97,15 @@ def power(P, keys, x, e, cnt=None):
     return _power_rule(table, e, P, keys, cnt)
 
 
-def eval_poly(P, keys, x, coeffs, cnt=None):
-    """Evaluate sum_i coeffs[i] x^i (coefficients mod t = p^t_exp of x)."""
+def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
+    """Evaluate sum_i coeffs[i] x^i (coefficients mod t = p^t_exp of x).  With parity
+    (the default) an odd-structured polynomial takes the odd split of bsgs_shape."""
     t = P.t(x.t_exp)
     c = [int(v) % t for v in coeffs]
     D = len(c) - 1
     while D > 0 and c[D] == 0:
         D -= 1
-    k, g = bsgs_shape(D)
+    k, g = bsgs_shape(D, parity and odd_structured(c, D))
     baby = {1: x}
     for i in range(2, k + 1):
         _power_rule(baby, i, P, keys, cnt)

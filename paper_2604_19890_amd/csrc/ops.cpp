@@ -553,7 +553,8 @@ static const double* coeff_table(bgv_ctx* c, int t_exp, const std::vector<int64_
 }
 
 // Baby-step/giant-step evaluation (Paterson-Stockmeyer, Theorem 2) with the
-// schedule: k = smallest power of two with 2k^2 >= D+1, g = ceil((D+1)/k);
+// schedule: k = smallest power of two with 2k^2 >= D+1 (k^2 >= D+1 for an
+// odd-structured polynomial, see below), g = ceil((D+1)/k);
 // baby powers x^2..x^k and giant powers y^2..y^(g-1) (y = x^k) by the power
 // rule; inner sums over the nonzero coefficients with every power first brought
 // to the lowest level among those used, scalar terms accumulated in increasing
@@ -569,8 +570,14 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   int D = (int)cf.size() - 1;
   while (D > 0 && cf[D] == 0) --D;
   if (D < 1) throw OpError{BGV_E_ARG};
+  // An odd-structured polynomial (every even coefficient strictly between the
+  // constant and the leading term zero: G_{p,e} for odd p, F_LT) needs only the odd
+  // baby powers, so its split moves to k = smallest power of two with k^2 >= D+1.
+  bool odd = D >= 3;
+  for (int i = 2; i < D && odd; i += 2)
+    if (cf[i] != 0) odd = false;
   int kk = 1;
-  while (2 * kk * kk < D + 1) kk *= 2;
+  while ((odd ? 1 : 2) * kk * kk < D + 1) kk *= 2;
   const int g = (D + kk) / kk;
   auto coef = [&](int n) -> int64_t { return n <= D ? cf[n] : 0; };
 

@@ -40,6 +40,85 @@ def test_bsgs_matches_horner_and_theorem2_depth(deg):
     assert cnt.mul <= (k - 1) + (gg - 2) + (gg - 1)
 
 
+@pytest.mark.parametrize("deg", [3, 5, 9, 17, 33])
+def test_odd_split_matches_horner_and_is_no_deeper(deg):
+    """Odd-structured polynomials (odd terms and a constant) take the odd split: the same
+    plaintext values as Horner, depth within Theorem 2 and no deeper than the dense split."""
+    c = tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(100 + deg)
+    coeffs = [0] * (deg + 1)
+    for i in range(1, deg + 1, 2):
+        coeffs[i] = int(g.integers(1, t))
+    coeffs[0] = int(g.integers(0, t))
+    assert S.odd_structured(coeffs, deg)
+    xs = [int(x) for x in g.integers(0, t, size=P.ell)]
+    a = c.enc(xs)
+    out = S.eval_poly(P, c.keys, a, coeffs)
+    dense = S.eval_poly(P, c.keys, a, coeffs, parity=False)
+    want = [polys.eval_mod(coeffs, x, t) for x in xs]
+    assert c.dec(out) == want and c.dec(dense) == want
+    assert P.L - out.level <= min(P.L - dense.level, math.ceil(math.log2(deg)) + 1)
+
+
+def _products_needed(c, k, g):
+    """Products a split needs when only the powers some term uses are formed: the power-rule
+    closure of the used baby powers (and x^k), of the used giant powers, and one product per
+    outer term whose inner sum is not a constant."""
+    D = len(c) - 1
+    coef = lambda n: c[n] if n <= D else 0
+
+    def closure(need):
+        need = set(need)
+        for i in sorted(need, reverse=True):
+            stack = [i]
+            while stack:
+                v = stack.pop()
+                if v < 2:
+                    continue
+                h = 1 << (v.bit_length() - 1)
+                parts = [v // 2] if v == h else [h, v - h]
+                for q in parts:
+                    if q not in need:
+                        need.add(q)
+                        stack.append(q)
+        return {v for v in need if v >= 2}
+
+    baby = closure([k] + [i for j in range(g) for i in range(1, k) if coef(j * k + i)])
+    used_inner = [any(coef(j * k + i) for i in range(1, k)) for j in range(g)]
+    giant = closure([j for j in range(1, g) if used_inner[j] or coef(j * k)])
+    outer = sum(1 for j in range(1, g) if used_inner[j])
+    return len(baby) + len(giant) + outer
+
+
+def test_odd_split_of_the_space_switching_polynomials():
+    """G_{p,2} (odd) and F_LT (odd terms and x^(p-1)) take the odd split, which keeps the
+    dense split's depth of 9 at p = 257 and cuts the products it needs:
+    - G: 20 baby (x^2, x^4, .., x^32 and the odd x^3..x^31) + 7 giant + 8 outer = 35, against
+      11 + 15 + 16 = 42 with k = 16;
+    - F_LT: 19 baby (it vanishes at every 17 + 32j, so x^17 is never formed) + 7 giant + 7
+      outer (x^256 enters as a scalar multiple of the last giant power) = 33, against
+      11 + 15 + 15 = 41.
+    x^(p-1) stays the last giant power, which the comparison reuses for EQ."""
+    for p, shape in ((17, (8, 3)), (257, (32, 9))):
+        t = p * p
+        G = [v % t for v in polys.g_poly(p, 2)]
+        F = [v % p for v in polys.f_lt(p)]
+        for poly in (G, F):
+            D = len(poly) - 1
+            assert S.odd_structured(poly, D)
+            assert S.bsgs_shape(D, True) == shape
+        k, g = shape
+        assert (g - 1) * k == p - 1
+    G = [v % 66049 for v in polys.g_poly(257, 2)]
+    F = [v % 257 for v in polys.f_lt(257)]
+    assert _products_needed(G, *S.bsgs_shape(257, True)) == 35
+    assert _products_needed(G, *S.bsgs_shape(257)) == 42
+    assert all(F[17 + 32 * j] == 0 for j in range(8))
+    assert _products_needed(F, *S.bsgs_shape(256, True)) == 33
+    assert _products_needed(F, *S.bsgs_shape(256)) == 41
+
+
 @pytest.mark.parametrize("ctx", [tiny5, tiny17])
 def test_space_reduce_brute_force(ctx):
     c = ctx()
