@@ -181,12 +181,14 @@ def time_graph(ctx, keys, cts, steps):
     return start.elapsed_time(stop) / 1e3 / steps
 
 
-def time_ntt(ctx, n_cts, reps=20):
-    """Forward NTT over n_cts ciphertexts at the top level: per-NTT time with HIP events."""
+def time_ntt(ctx, n_cts, reps=20, warm=10):
+    """Forward NTT over n_cts ciphertexts at the top level: per-NTT time with HIP events on the
+    context's stream, after `warm` untimed transforms (which bring the clocks up)."""
     import torch
     limbs = n_cts * 2 * ctx.L
     x = torch.randint(0, 1 << 49, (limbs * ctx.N,), dtype=torch.int64, device="cuda")
-    ctx.ntt(x, n_cts * 2, ctx.L)
+    for _ in range(warm):
+        ctx.ntt(x, n_cts * 2, ctx.L)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()

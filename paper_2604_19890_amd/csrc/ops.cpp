@@ -152,13 +152,17 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
   lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1);
   auto U = ks_inner(c, keys->relin, X, n, lv);
-  special_rows_coeff(c, *U, n, lv);
+  // u's top row and its special rows are the K + 1 consecutive rows lv-1 .. lv+K-1
+  // of every polynomial: one inverse transform brings them all to coefficient form
+  LimbMap ut{K + 1, 1, c->prm.L, 0, 1, lv - 1, 0};
+  ut.grp = K + 1;
+  ut.grp_stride = rows;
+  ut.grp_first = lv - 1;
+  lk::ntt(c, U->d, 2 * n * (K + 1), ut, true);
   LimbMap top{1, 1, c->prm.L, 0, 1, lv - 1, 0};
   top.grp = 1;
-  top.grp_stride = rows;
-  top.grp_first = lv - 1;
-  lk::ntt(c, U->d, 2 * n, top, true);  // u tops
   top.grp_stride = lv;
+  top.grp_first = lv - 1;
   lk::ntt(c, D.d, 2 * n, top, true);  // d tops
   Scratch E(c, (size_t)n * 2 * (lv - 1) * N);
   lk::ms_corr(c, U->d + (size_t)lv * N, (int64_t)rows * N, U->d + (size_t)(lv - 1) * N, (int64_t)rows * N,
