@@ -42,10 +42,20 @@ struct LimbMap {
   int grp;
   int grp_stride;
   int grp_first;
+  // Optional source placement of an out-of-place first pass (sgrp > 0): launch limb
+  // l is read from row (l / sgrp) * sgrp_stride + sgrp_first + l % sgrp of the source;
+  // otherwise from the row it is written to.
+  int sgrp;
+  int sgrp_stride;
+  int sgrp_first;
 };
 
 __device__ __forceinline__ int limb_phys(const LimbMap& lm, int l) {
   return lm.grp > 0 ? (l / lm.grp) * lm.grp_stride + lm.grp_first + l % lm.grp : l;
+}
+
+__device__ __forceinline__ int limb_src(const LimbMap& lm, int l) {
+  return lm.sgrp > 0 ? (l / lm.sgrp) * lm.sgrp_stride + lm.sgrp_first + l % lm.sgrp : limb_phys(lm, l);
 }
 
 __device__ __forceinline__ int limb_prime(const LimbMap& lm, int l) {

@@ -285,6 +285,17 @@ bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream) {
   for (int top = 0; top < L; ++top)
     for (int i = 0; i < L; ++i)
       if (i != top) msw[(size_t)top * L + i] = (double)invmod(c->primes[top] % c->primes[i], c->primes[i]);
+  // repeated switch: mswpi[level][to][i] = prod_{j=to}^{level-1} q_j^-1 mod q_i
+  std::vector<double> mswpi((size_t)(L + 1) * (L + 1) * L, 0.0);
+  for (int lv = 2; lv <= L; ++lv)
+    for (int i = 0; i < lv - 1; ++i) {
+      const uint64_t qi = c->primes[i];
+      uint64_t v = 1;
+      for (int to = lv - 1; to > i; --to) {
+        v = mulmod(v, invmod(c->primes[to] % qi, qi), qi);
+        mswpi[((size_t)lv * (L + 1) + to) * L + i] = (double)v;
+      }
+    }
   // t constants [r+1][2][Lt] and the host copy of t^-1
   std::vector<double> tc((size_t)(prm->r + 1) * 2 * Lt);
   c->h_tinv.assign((size_t)(prm->r + 1) * Lt, 0.0);
@@ -302,7 +313,7 @@ bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream) {
 
   if (!upload(c, &c->d_prime, pd) || !upload(c, &c->d_tw, tw) || !upload(c, &c->d_itw, itw) ||
       !upload(c, &c->d_modup, mu) || !upload(c, &c->d_moddown, md) || !upload(c, &c->d_msw, msw) ||
-      !upload(c, &c->d_tconst, tc))
+      !upload(c, &c->d_mswpi, mswpi) || !upload(c, &c->d_tconst, tc))
     return BGV_E_DEVICE;
   if (!build_encoder(c)) { c->err = "slot encoder construction failed"; return BGV_E_PARAM; }
   return BGV_OK;
@@ -314,7 +325,7 @@ void ctx_free(bgv_ctx* c) {
   c->pool.release();
   for (auto& kv : c->coeff_tabs) (void)hipFree(kv.second);
   c->coeff_tabs.clear();
-  void* ptrs[] = {c->d_prime, c->d_tw, c->d_itw, c->d_modup, c->d_moddown, c->d_msw, c->d_tconst};
+  void* ptrs[] = {c->d_prime, c->d_tw, c->d_itw, c->d_modup, c->d_moddown, c->d_msw, c->d_mswpi, c->d_tconst};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

@@ -52,6 +52,9 @@ struct bgv_ctx {
   double* d_moddown = nullptr;
   // modulus switching: qinv_tab [L][L] (q_top^-1 mod q_i at [top][i])
   double* d_msw = nullptr;
+  // repeated switch from `level` down to `to`: prod_{j=to}^{level-1} q_j^-1 mod q_i
+  // at [(level * (L+1) + to) * L + i]
+  double* d_mswpi = nullptr;
   // t-dependent scalars: tinv_tab [r+1][Ltot] (t^-1 mod prime), tmod_tab [r+1][Ltot]
   double* d_tconst = nullptr;
 
@@ -148,8 +151,10 @@ void mod_down_final(bgv_ctx* c, const uint64_t* u, const uint64_t* dl, const uin
 // wrow [n][2][level-1][N] = centered([top t^-1]_{q_top}) mod q_i  (coefficient form)
 void msw_w(bgv_ctx* c, const uint64_t* top, uint64_t* wrow, int n, int level, int t_exp);
 // (part 2, out_i = (a_i - t w_i) q_top^-1, is the epilogue of the forward NTT of w)
-// multi-drop in coefficient form: x [n][2][level][N] -> y [n][2][to][N]
-void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int to, int t_exp);
+// multi-drop correction: from the dropped limbs tl [n][2][level-to][N] (coefficient form),
+// e [n][2][to][N] = t S (coefficient form) with S the combined drop correction; the
+// switched limb is (c_i - NTT(e_i)) prod q_dropped^-1 (see kernels.hip)
+void msw_corr(bgv_ctx* c, const uint64_t* tl, uint64_t* e, int n, int level, int to, int t_exp);
 // copy limb rows: y[b][c][i] = x[b][c][i] for i < to_level (x has from_level rows)
 void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from_level, int to_level, int comps);
 // Terms and sums of one multi-output linear combination (at most LC_MAXT terms,

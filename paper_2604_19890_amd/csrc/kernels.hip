@@ -251,32 +251,36 @@ __global__ void k_msw_w(const uint64_t* __restrict__ top, uint64_t* __restrict__
   }
 }
 
-// repeated modulus switch in coefficient form: x [n*2][level][N] -> y [n*2][to][N],
-// at most MAXD = 16 drops per launch (longer drops are chained launches).  The
-// loops over drops are unrolled so that the per-drop corrections stay in registers.
+// at most MSW_MAXD drops per launch of the repeated switch (longer chains are chained steps)
 constexpr int MSW_MAXD = 16;
 
-__global__ void k_msw_multi(const uint64_t* __restrict__ x, uint64_t* __restrict__ y, int level, int to, int N,
-                            const double* __restrict__ msw, int L, const double* __restrict__ tinv,
-                            const double* __restrict__ tmod, const PrimeD* __restrict__ pc) {
+// Repeated modulus switch in correction form.  tl [n*2][nd][N] holds the nd = level - to
+// dropped limbs of every polynomial in coefficient form (limb to + k at row k).  The w of
+// every single drop is formed top down: the current value of the limb about to be dropped
+// is its input transformed by every drop above it.  The nd sequential drops then
+// amount to c_i -> (c_i - t S) prod_e q_e^-1 with S = w_0 + q_0 (w_1 + q_1 (w_2 + ...)), q_e
+// the e-th prime dropped.  e_i = t S mod q_i (coefficient form) is written for i < to; the
+// caller transforms it and applies (c_i - e_i) prod_e q_e^-1 in evaluation form.  The chain
+// is descending, so every dropped prime is below q_i and q_e mod q_i = q_e.
+__global__ void k_msw_corr(const uint64_t* __restrict__ tl, uint64_t* __restrict__ e, int level, int to, int N,
+                           const double* __restrict__ msw, int L, const double* __restrict__ tinv,
+                           const double* __restrict__ tmod, const PrimeD* __restrict__ pc) {
   const int cc = blockIdx.y;
   const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t* X = x + (size_t)cc * level * N + n0;
   const int nd = level - to;
+  const uint64_t* X = tl + (size_t)cc * nd * N + n0;
   double wv[MSW_MAXD];
-  // w for each dropped prime, from the top down; the current value of limb `top`
-  // is its input transformed by every drop above it
 #pragma unroll
   for (int d = 0; d < MSW_MAXD; ++d) {
     wv[d] = 0.0;
     if (d < nd) {
       const int top = level - 1 - d;
       const double q = pc[top].q, qinv = pc[top].qinv;
-      double cur = u2d(X[(size_t)top * N]);
+      double cur = u2d(X[(size_t)(top - to) * N]);
 #pragma unroll
-      for (int e = 0; e < d; ++e) {
-        const int up = level - 1 - e;
-        const double diff = cur - mul_lazy(wv[e] < 0.0 ? wv[e] + q : wv[e], tmod[top], q, qinv);
+      for (int f = 0; f < d; ++f) {
+        const int up = level - 1 - f;
+        const double diff = cur - mul_lazy(wv[f] < 0.0 ? wv[f] + q : wv[f], tmod[top], q, qinv);
         cur = mul_lazy(red(diff, q, qinv), msw[(size_t)up * L + top], q, qinv);
       }
       double wt = canon(mul_lazy(canon(red(cur, q, qinv), q), tinv[top], q, qinv), q);
@@ -284,19 +288,18 @@ __global__ void k_msw_multi(const uint64_t* __restrict__ x, uint64_t* __restrict
       wv[d] = wt > half ? wt - q : wt;
     }
   }
-  uint64_t* Y = y + (size_t)cc * to * N + n0;
+  uint64_t* E = e + (size_t)cc * to * N + n0;
   for (int i = 0; i < to; ++i) {
     const double q = pc[i].q, qinv = pc[i].qinv;
-    double cur = u2d(X[(size_t)i * N]);
+    double acc = 0.0;
 #pragma unroll
-    for (int e = 0; e < MSW_MAXD; ++e) {
-      if (e < nd) {
-        const int up = level - 1 - e;
-        const double diff = cur - mul_lazy(wv[e] < 0.0 ? wv[e] + q : wv[e], tmod[i], q, qinv);
-        cur = mul_lazy(red(diff, q, qinv), msw[(size_t)up * L + i], q, qinv);
+    for (int d = MSW_MAXD - 1; d >= 0; --d) {
+      if (d < nd) {
+        const double qd = pc[level - 1 - d].q;  // below q_i
+        acc = red(wv[d] + mul_lazy(acc, qd, q, qinv), q, qinv);
       }
     }
-    Y[(size_t)i * N] = to_u(cur, q, qinv);
+    E[(size_t)i * N] = to_u(mul_lazy(acc, tmod[i], q, qinv), q, qinv);
   }
 }
 
@@ -610,8 +613,8 @@ void msw_w(bgv_ctx* c, const uint64_t* top, uint64_t* w, int n, int level, int t
                      tinv_top, c->d_prime);
 }
 
-void msw_multi(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level, int to, int t_exp) {
-  hipLaunchKernelGGL(k_msw_multi, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, x, y, level, to, c->N,
+void msw_corr(bgv_ctx* c, const uint64_t* tl, uint64_t* e, int n, int level, int to, int t_exp) {
+  hipLaunchKernelGGL(k_msw_corr, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, tl, e, level, to, c->N,
                      c->d_msw, c->prm.L, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
                      c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
 }

@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
   const double* __restrict__ w = tw + (size_t)pi * N;
   const size_t row = (size_t)limb_phys(lm, limb) * N;
   uint64_t* x = data + row;
-  const uint64_t* xs = (src ? src : data) + row;
+  const uint64_t* xs = src ? src + (size_t)limb_src(lm, limb) * N : data + row;
   const int tmax_log = logN - s0 - 1;
   const int tmin_log = logN - s0 - LOGS;
   const int tmin = 1 << tmin_log;

@@ -244,21 +244,41 @@ void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out) {
     op_mod_switch(c, in, out);
     return;
   }
-  // coefficient form (out of place), then at most 16 drops per launch; chained
-  // launches are the same sequence of single-prime drops
-  std::unique_ptr<Scratch> A(new Scratch(c, (size_t)n * 2 * lv * N));
-  lk::ntt(c, A->d, n * 2 * lv, lm_chain(c, lv), true, in.d);
-  const int maxd = 16;
+  // At most 16 drops per step.  A step brings only the dropped limbs to coefficient
+  // form, forms the combined correction e for the kept ones, and finishes in the epilogue
+  // of e's forward NTT: out_i = (c_i - e_i) prod q_dropped^-1 with c in evaluation form.
+  // Chained steps are the same sequence of single-prime drops.
+  const int L = c->prm.L;
+  const uint64_t* src = in.d;
+  std::unique_ptr<Scratch> cur_buf;
   int cur = lv;
-  while (cur - to > maxd) {
-    const int nxt = cur - maxd;
-    std::unique_ptr<Scratch> B(new Scratch(c, (size_t)n * 2 * nxt * N));
-    lk::msw_multi(c, A->d, B->d, n, cur, nxt, in.t_exp);
-    A = std::move(B);  // the old buffer goes back to the pool; later users run after this launch
+  while (cur > to) {
+    const int nxt = std::max(to, cur - 16);
+    const int nd = cur - nxt;
+    Scratch T(c, (size_t)n * 2 * nd * N);
+    LimbMap tm{nd, nd, L, 0, 1, nxt, 0};
+    tm.sgrp = nd;
+    tm.sgrp_stride = cur;
+    tm.sgrp_first = nxt;
+    lk::ntt(c, T.d, n * 2 * nd, tm, true, src);  // the dropped rows of src, out of place
+    std::unique_ptr<Scratch> E(new Scratch(c, (size_t)n * 2 * nxt * N));
+    lk::msw_corr(c, T.d, E->d, n, cur, nxt, in.t_exp);
+    lk::NttEpi ep{};
+    ep.a = src;
+    ep.a_cc = (int64_t)cur * N;
+    ep.qt = c->d_mswpi + ((size_t)cur * (L + 1) + nxt) * L;
+    ep.rows = nxt;
+    // the result goes to out unless it is the input's own buffer (rows at another
+    // stride) or an intermediate step; then it stays in e, transformed in place
+    const bool direct = nxt == to && out.d != in.d;
+    ep.out = direct ? out.d : E->d;
+    lk::ntt(c, E->d, n * 2 * nxt, lm_chain(c, nxt), false, nullptr, &ep);
+    cur_buf = std::move(E);  // the previous step's buffer goes back to the pool: its readers are enqueued
+    src = cur_buf->d;
     cur = nxt;
+    if (direct) return;
   }
-  lk::msw_multi(c, A->d, out.d, n, cur, to, in.t_exp);
-  op_ntt(c, out.d, n * 2, to, false);
+  check_hip(c, hipMemcpyAsync(out.d, src, (size_t)n * 2 * to * N * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
 }
 
 // ------------------------------------------------------------------ encoding

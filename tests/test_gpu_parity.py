@@ -108,6 +108,11 @@ def test_mul_relin_and_mod_switch_match(pf):
     c.assert_equal(mt, [B.align(P, x, to) for x in om], "mod_switch_to")
     # all the way down (more than 16 drops in chained launches where the chain is that long)
     c.assert_equal(c.lib.mod_switch_to(m, 1), [B.align(P, x, 1) for x in om], "mod_switch_to level 1")
+    # in place, one step and chained
+    for lv in (to, 1):
+        m3 = c.lib.mul_relin(c.keys, ga, gb)
+        c.assert_equal(c.lib.mod_switch_to(m3, lv, out=m3), [B.align(P, x, lv) for x in om],
+                       f"mod_switch_to {lv} in place")
     # a product at a lower level (truncated last digit)
     la, lb = c.lib.mod_switch_to(ga, P.L - 3), c.lib.mod_switch_to(gb, P.L - 3)
     ol = [B.mul_relin(P, c.okeys.relin, B.align(P, x, P.L - 3), B.align(P, y, P.L - 3)) for x, y in zip(oa, ob)]
