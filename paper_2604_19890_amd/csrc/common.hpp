@@ -72,6 +72,10 @@ __device__ __forceinline__ bool limb_skipped(const LimbMap& lm, int l) {
   return m < lm.ell_q && m / lm.skip_alpha == j;
 }
 
+// A load of a word the kernel reads once and nothing reads again soon (streaming):
+// the non-temporal hint keeps it from displacing data that is reused from the caches.
+__device__ __forceinline__ uint64_t ld_once(const uint64_t* p) { return __builtin_nontemporal_load(p); }
+
 // exact conversions for integers in [0, 2^52)
 __device__ __forceinline__ double u2d(uint64_t x) {
   return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 4503599627370496.0;

@@ -76,7 +76,9 @@ __global__ void k_tensor(const uint64_t* __restrict__ a, const uint64_t* __restr
   const uint64_t* A = a + (size_t)ct * 2 * L2 + (size_t)i * N + n0;
   const uint64_t* B = b + (size_t)(b_bcast ? 0 : ct) * 2 * L2 + (size_t)i * N + n0;
   uint64_t* D = d + (size_t)ct * 2 * L2 + (size_t)i * N + n0;
-  const double a0 = u2d(A[0]), a1 = u2d(A[L2]), b0 = u2d(B[0]), b1 = u2d(B[L2]);
+  // a is read once; a broadcast b is shared by every ciphertext and stays cached
+  const double a0 = u2d(ld_once(A)), a1 = u2d(ld_once(A + L2));
+  const double b0 = u2d(b_bcast ? B[0] : ld_once(B)), b1 = u2d(b_bcast ? B[L2] : ld_once(B + L2));
   D[0] = d2u(canon(mul_lazy(a0, b0, q, qinv), q));
   const double m = mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv);
   D[L2] = d2u(canon(red(m, q, qinv), q));
@@ -104,7 +106,7 @@ __global__ void k_mod_up(const uint64_t* __restrict__ x, uint64_t* __restrict__ 
     if (a < na) {
       const int i = lo + a;
       const double q = pc[i].q, qinv = pc[i].qinv;
-      v[a] = canon(mul_lazy(u2d(X[(size_t)i * N]), inv[a], q, qinv), q);
+      v[a] = canon(mul_lazy(u2d(ld_once(X + (size_t)i * N)), inv[a], q, qinv), q);
     } else {
       v[a] = 0.0;
     }
@@ -276,7 +278,7 @@ __global__ void k_msw_corr(const uint64_t* __restrict__ tl, uint64_t* __restrict
     if (d < nd) {
       const int top = level - 1 - d;
       const double q = pc[top].q, qinv = pc[top].qinv;
-      double cur = u2d(X[(size_t)(top - to) * N]);
+      double cur = u2d(ld_once(X + (size_t)(top - to) * N));
 #pragma unroll
       for (int f = 0; f < d; ++f) {
         const int up = level - 1 - f;
@@ -361,7 +363,7 @@ __global__ void k_lincomb_multi(lk::LinMulti m, int nt, int no, const double* __
   const size_t off = (size_t)limb * N + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   double x[lk::LC_MAXT];
 #pragma unroll
-  for (int t = 0; t < lk::LC_MAXT; ++t) x[t] = t < nt ? u2d(m.x[t][off]) : 0.0;
+  for (int t = 0; t < lk::LC_MAXT; ++t) x[t] = t < nt ? u2d(ld_once(m.x[t] + off)) : 0.0;
   for (int o = 0; o < no; ++o) {
     double acc = 0.0;
     int cnt = 0;
@@ -405,7 +407,7 @@ __global__ void k_ms_corr(const uint64_t* __restrict__ up, int64_t up_stride, co
     if (k < K) {
       const int pk = Lfull + k;
       const double q = pc[pk].q, qinv = pc[pk].qinv;
-      const double w = canon(mul_lazy(u2d(U[(size_t)k * N]), tinv[pk], q, qinv), q);
+      const double w = canon(mul_lazy(u2d(ld_once(U + (size_t)k * N)), tinv[pk], q, qinv), q);
       v[k] = canon(mul_lazy(w, phat_inv[k], q, qinv), q);
     } else {
       v[k] = 0.0;
@@ -423,8 +425,8 @@ __global__ void k_ms_corr(const uint64_t* __restrict__ up, int64_t up_stride, co
   {
     const double q = pc[it].q, qinv = pc[it].qinv;
     const double wt = fbc(it, q, qinv);
-    const double ut = u2d(utop[(size_t)cc * ut_stride + n0]);
-    const double dt = u2d(dtop[(size_t)cc * dt_stride + n0]);
+    const double ut = u2d(ld_once(utop + (size_t)cc * ut_stride + n0));
+    const double dt = u2d(ld_once(dtop + (size_t)cc * dt_stride + n0));
     const double diff = red(ut - mul_lazy(wt, tmod[it], q, qinv), q, qinv);
     const double o = canon(red(dt + mul_lazy(diff, pinv[it], q, qinv), q, qinv), q);
     const double w = canon(mul_lazy(o, tinv[it], q, qinv), q);

@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
   double v[16];
 
 #pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = u2d(xsp[(size_t)i << gs1_log]);
+  for (int i = 0; i < 16; ++i) v[i] = u2d(__builtin_nontemporal_load(&xsp[(size_t)i << gs1_log]));
   // the epilogue's rows are requested with the pass's own, so that they arrive
   // while the butterflies run
   uint64_t av[EPI ? 16 : 1], bv[EPI ? 16 : 1];
@@ -169,11 +169,11 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
     const size_t rr = (size_t)ii * N + g1;
     const uint64_t* ap = ep.a + (size_t)cc * ep.a_cc + rr;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) av[i] = ap[(size_t)i << gs1_log];
+    for (int i = 0; i < 16; ++i) av[i] = __builtin_nontemporal_load(&ap[(size_t)i << gs1_log]);
     if (ep.b) {
       const uint64_t* bp = ep.b + (size_t)cc * ep.b_cc + rr;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) bv[i] = bp[(size_t)i << gs1_log];
+      for (int i = 0; i < 16; ++i) bv[i] = __builtin_nontemporal_load(&bp[(size_t)i << gs1_log]);
     }
   }
 
@@ -221,11 +221,11 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
       const double e = canon(red(v[i], q, qinv), q);
       double s = u2d(av[i]) - (ep.sv ? mul_lazy(e, ep.sv[ii], q, qinv) : e);
       if (ep.b) s += mul_lazy(u2d(bv[i]), ep.sb[ii], q, qinv);
-      op[(size_t)i << gs1_log] = to_u(mul_lazy(red(s, q, qinv), qt, q, qinv), q, qinv);
+      __builtin_nontemporal_store(to_u(mul_lazy(red(s, q, qinv), qt, q, qinv), q, qinv), &op[(size_t)i << gs1_log]);
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) xp[(size_t)i << gs1_log] = d2u(canon(red(v[i], q, qinv), q));
+    for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(d2u(canon(red(v[i], q, qinv), q)), &xp[(size_t)i << gs1_log]);
   }
 }
 
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
   {
     const uint64_t* __restrict__ yp = own_j == 0 ? xrow : yrow;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) yn[i] = yp[(size_t)i << gs1_log];
+    for (int i = 0; i < 16; ++i) yn[i] = __builtin_nontemporal_load(&yp[(size_t)i << gs1_log]);
   }
   for (int j = 0; j < dn; ++j) {
 #pragma unroll
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
     if (j + 1 < dn) {
       const uint64_t* __restrict__ yp = own_j == j + 1 ? xrow : yrow + (size_t)(j + 1) * ystep;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) yn[i] = yp[(size_t)i << gs1_log];
+      for (int i = 0; i < 16; ++i) yn[i] = __builtin_nontemporal_load(&yp[(size_t)i << gs1_log]);
     }
     if (j != own_j) {
       ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
