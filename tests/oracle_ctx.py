@@ -38,6 +38,12 @@ def tiny5():
 
 
 @functools.lru_cache(maxsize=None)
+def tiny5_r3():
+    """r = 3 (t = 125): Algorithm 3 with G_{5,3} and G_{5,2}; the chain covers less_than's depth."""
+    return Ctx(4, 5, 3, 17, 1)
+
+
+@functools.lru_cache(maxsize=None)
 def tiny17():
     return Ctx(5, 17, 2, 18, 1, steps=(1, 2), conj=True)
 

@@ -65,6 +65,31 @@ def test_g_p2_satisfies_lemma3_on_all_of_z_p2(p):
     assert np.array_equal(acc, z0 % t)
 
 
+@pytest.mark.parametrize("p,e", [(3, 3), (5, 3), (5, 4), (5, 5), (7, 3), (7, 4), (13, 3), (17, 3)])
+def test_g_pe_satisfies_lemma3_on_all_of_z_pe(p, e):
+    """The lifted G_{p,e}: Lemma 3's property G(z0 + p z1) = z0 (mod p^e) on every element of
+    Z_{p^e}, within Lemma 3's degree bound (e-1)(p-1)+1, odd."""
+    G = polys.g_poly(p, e)
+    t = p ** e
+    assert len(G) - 1 <= (e - 1) * (p - 1) + 1
+    assert all(c == 0 for c in G[0::2])
+    assert all(0 <= c < t for c in G)
+    xs = np.arange(t, dtype=np.int64)
+    acc = np.zeros(t, dtype=np.int64)
+    for c in reversed(G):
+        acc = (acc * xs + c) % t
+    z0 = ((xs + (p - 1) // 2) % p) - (p - 1) // 2
+    assert np.array_equal(acc, z0 % t)
+
+
+def test_g_pe_lift_needs_e_at_most_p():
+    """The lift samples the error polynomial at e distinct points mod p."""
+    with pytest.raises(ValueError):
+        polys.g_poly(3, 4)
+    assert polys.g_poly(5, 2) == polys.g_p2(5)
+    assert polys.g_poly(7, 1) == [0, 1]
+
+
 def test_g_p2_small_closed_forms():
     """Worked by hand: G_{3,2} = x^3 and G_{5,2} = x^5 + 20 x^3 + 5 x (mod 25).
     For p = 3: H interpolates (z - z^3)/3 = 0 at z in {-1, 0, 1}.  For p = 5: H

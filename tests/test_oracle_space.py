@@ -8,7 +8,7 @@ import pytest
 from oracle import bgv as B
 from oracle import polys
 from oracle import space as S
-from tests.oracle_ctx import tiny5, tiny17
+from tests.oracle_ctx import tiny5, tiny5_r3, tiny17
 
 
 def _balanced_digits(v, p):
@@ -161,6 +161,47 @@ def test_predicate_family_brute_force(ctx):
         dg = S.space_reduce(P, c.keys, c.enc(vals))
         for op, f in ref.items():
             assert c.dec(S.compare(P, c.keys, dg, op)) == [1 if f(v) else 0 for v in vals], op
+
+
+def _balanced_digits_r(v, p, r):
+    h = (p - 1) // 2
+    out = []
+    for _ in range(r):
+        z = ((v + h) % p) - h
+        out.append(z)
+        v = (v - z) // p
+    return out
+
+
+def test_space_reduce_r3_brute_force():
+    """Algorithm 3 with r = 3 (G_{5,3}, then G_{5,2}): the three balanced base-5 digits of
+    every value of Z_125."""
+    c = tiny5_r3()
+    P, p, t = c.P, c.P.p, c.P.t_full
+    assert t == 125
+    for start in range(0, t, P.ell):
+        vals = [(start + i) % t for i in range(P.ell)]
+        dg = S.space_reduce(P, c.keys, c.enc(vals))
+        assert [d.t_exp for d in dg] == [1, 1, 1]
+        got = [c.dec(d) for d in dg]
+        for k, v in enumerate(vals):
+            assert [g[k] for g in got] == [z % p for z in _balanced_digits_r(v, p, 3)]
+
+
+def test_compare_and_raise_r3_brute_force():
+    """r = 3: LT and EQ of every d in Z_125 against zero through three digits, and raise of the
+    LT result back to Z_125 (G_{5,3})."""
+    c = tiny5_r3()
+    P, p, t = c.P, c.P.p, c.P.t_full
+    for start in range(0, t, P.ell):
+        vals = [(start + i) % t for i in range(P.ell)]
+        dg = S.space_reduce(P, c.keys, c.enc(vals))
+        lt = S.compare(P, c.keys, dg, "lt")
+        assert c.dec(lt) == [1 if _centered(v, t) < 0 else 0 for v in vals]
+        assert c.dec(S.compare(P, c.keys, dg, "eq")) == [1 if v == 0 else 0 for v in vals]
+        up = S.space_raise(P, c.keys, lt)
+        assert up.t_exp == 3
+        assert c.dec(up) == [1 if _centered(v, t) < 0 else 0 for v in vals]
 
 
 def test_fgt_truth_table():
