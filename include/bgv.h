@@ -182,16 +182,20 @@ bgv_status bgv_mod_switch_to(bgv_ctx* ctx, const bgv_ct* in, int32_t level, bgv_
  *   documented in the library's design notes; every product is followed by one
  *   modulus switch.  The output level is input level minus the schedule depth;
  *   BGV_E_LEVEL if the chain is too short.
- * bgv_space_reduce: Algorithm 3 for r = 2: digits[0] = G_{p,2}(in) and
- *   digits[1] = DivideByP(in - digits[0]), both tagged t = p (ChangeModToP); the
- *   digits are the balanced base-p digits of each slot.  `digits` has r entries.
+ * bgv_space_reduce: Algorithm 3 on a value tagged t = p^e (1 <= e <= r): e - 1 rounds
+ *   of digits[i] = G_{p,e-i}(b), b <- DivideByP(b - digits[i]) (b starts as `in`),
+ *   and digits[e-1] = b, all tagged t = p (ChangeModToP); the digits are the
+ *   balanced base-p digits of each slot, least significant first.  `digits` has e
+ *   entries.  G_{p,e} (Lemma 3) for e >= 3 is lifted from G_{p,e-1} one digit at
+ *   a time, which needs e <= p; a context whose r exceeds p fails at creation.
  * bgv_compare: Algorithm 4 on r digit batches (least significant first), op one of
  *   BGV_OP_LT / GT (digit polynomial and the aggregation LT = LT + EQ * LT_i),
  *   BGV_OP_EQ (product of the digit equalities) or the complements LE = 1 - GT,
  *   GE = 1 - LT, NEQ = 1 - EQ (the comparison subsection's predicate family).
  * bgv_space_raise: RaiseModToP2R -- tag t = p^r, then G_{p,r}; a slot holding k
  *   mod p becomes centered_p(k) mod p^r.
- * bgv_less_than: reduce -> compare(LT) -> raise of (x - y), or of x if y is NULL.
+ * bgv_less_than: reduce -> compare(LT) -> raise of (x - y), or of x if y is NULL;
+ *   x (and y) tagged t = p^r (BGV_E_PTXT_MOD otherwise).
  * bgv_rotate_sum: every slot receives the sum of all slots (row rotations by
  *   1, 2, 4, .., ell/4 and the row swap; all those keys are needed).           */
 bgv_status bgv_eval_poly(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, const int64_t* coeffs,

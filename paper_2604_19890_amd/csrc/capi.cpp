@@ -332,7 +332,6 @@ BGV_EXPORT bgv_status bgv_space_reduce(bgv_ctx* c, const bgv_keys* k, const bgv_
   NEED_CTX(c);
   if (!k || !digits) return fail(c, BGV_E_ARG, "bad space_reduce arguments");
   CHECK(check_in(c, in, "null input"));
-  if (in->t_exp != 2) return fail(c, BGV_E_UNSUPPORTED, "the reduction is built for t = p^2");
   return guarded(c, [&] {
     std::vector<CipherP> d = ev_space_reduce(c, k, borrow(in));
     for (size_t i = 0; i < d.size(); ++i) CHECK(check_out(c, &digits[i], d[i]->v.n, d[i]->v.level));
@@ -369,7 +368,7 @@ BGV_EXPORT bgv_status bgv_less_than(bgv_ctx* c, const bgv_keys* k, const bgv_ct*
   if (!k) return fail(c, BGV_E_ARG, "no keys");
   CHECK(check_in(c, x, "null x"));
   if (y) CHECK(binary_check(c, x, y));  // y: same batch size or a single broadcast ciphertext
-  if (x->t_exp != 2) return fail(c, BGV_E_UNSUPPORTED, "the reduction is built for t = p^2");
+  if (x->t_exp != c->prm.r) return fail(c, BGV_E_PTXT_MOD, "less_than takes values tagged t = p^r");
   return guarded(c, [&] {
     return deliver(c, ev_less_than(c, k, borrow(x), y ? borrow(y) : nullptr), out);
   });
@@ -409,8 +408,9 @@ static bgv_status filter_check(bgv_ctx* c, const bgv_keys* k, const bgv_ct* a, c
   CHECK(check_in(c, thr, "null thr"));
   CHECK(check_in(c, b, "null b"));
   CHECK(check_in(c, cc, "null c"));
-  if (a->t_exp != 2 || thr->t_exp != 2 || b->t_exp != 2 || cc->t_exp != 2)
-    return fail(c, BGV_E_PTXT_MOD, "the query runs on t = p^2 inputs");
+  const int r = c->prm.r;
+  if (a->t_exp != r || thr->t_exp != r || b->t_exp != r || cc->t_exp != r)
+    return fail(c, BGV_E_PTXT_MOD, "the query runs on inputs tagged t = p^r");
   if (b->n != a->n || cc->n != a->n || (thr->n != 1 && thr->n != a->n)) return fail(c, BGV_E_ARG, "batch sizes differ");
   if (a->level != thr->level) return fail(c, BGV_E_LEVEL, "a and thr at different levels");
   return BGV_OK;
@@ -439,7 +439,7 @@ BGV_EXPORT bgv_status bgv_relu(bgv_ctx* c, const bgv_keys* k, const bgv_ct* x, b
   NEED_CTX(c);
   if (!k || !k->relin) return fail(c, BGV_E_NOKEY, "no keys");
   CHECK(check_in(c, x, "null x"));
-  if (x->t_exp != 2) return fail(c, BGV_E_UNSUPPORTED, "the reduction is built for t = p^2");
+  if (x->t_exp != c->prm.r) return fail(c, BGV_E_PTXT_MOD, "the input must be tagged t = p^r");
   return guarded(c, [&] { return deliver(c, ev_relu(c, k, borrow(x)), out); });
 }
 

@@ -125,6 +125,92 @@ bool interpolate_fp(int64_t p, const std::vector<int64_t>& zs, const std::vector
 
 }  // namespace
 
+// Lemma 3 for e >= 3: G_{p,k+1} from G_{p,k}, one digit at a time.  With Q(x) = x^p - x,
+// Q(z0 + p y)/p = c(z0) - y (mod p), c(z0) = (z0^p - z0)/p, so Q reaches the digit y.  If
+// G_k(z0 + p y) = z0 + p^k E(z0, y) (mod p^(k+1)) -- E of degree <= k in y, found from its
+// values at y = 0..k -- then with -E(z0, c - u) = sum_m e_m(z0) u^m and M_m the interpolant
+// of e_m over the balanced z0, G_{k+1} = G_k + sum_m p^(k-m) Q^m M_m (mod p^(k+1)).
+// Needs k + 1 <= p (distinct sample points) and p^(k+1) < 2^62.
+static bool lift_g(int64_t p, int k, const std::vector<int64_t>& G, std::vector<int64_t>& out) {
+  if (k + 1 > p) return false;
+  int64_t pk = 1;
+  for (int i = 0; i < k; ++i) pk *= p;
+  const int64_t mod = pk * p;
+  if (mod <= 0 || mod > ((int64_t)1 << 62) / p) return false;
+  auto mulm = [&](int64_t a, int64_t b) { return (int64_t)((__int128)a * b % mod); };
+  auto horner = [&](const std::vector<int64_t>& f, int64_t x) {  // f(x) mod p^(k+1), x in [0, mod)
+    int64_t acc = 0;
+    for (size_t i = f.size(); i-- > 0;) acc = (mulm(acc, x) + f[i]) % mod;
+    return acc;
+  };
+  auto polymul = [&](const std::vector<int64_t>& a, const std::vector<int64_t>& b) {
+    std::vector<int64_t> r(a.size() + b.size() - 1, 0);
+    for (size_t i = 0; i < a.size(); ++i)
+      if (a[i])
+        for (size_t j = 0; j < b.size(); ++j) r[i + j] = (r[i + j] + mulm(a[i], b[j])) % mod;
+    return r;
+  };
+  const int64_t h = (p - 1) / 2;
+  std::vector<int64_t> zs, ys;
+  for (int64_t z = -h; z <= h; ++z) zs.push_back(z);
+  for (int y = 0; y <= k; ++y) ys.push_back(y);
+  // binomials mod p (k < p, so they are small)
+  std::vector<std::vector<int64_t>> C(k + 1, std::vector<int64_t>(k + 1, 0));
+  for (int j = 0; j <= k; ++j) {
+    C[j][0] = 1;
+    for (int m = 1; m <= j; ++m) C[j][m] = (C[j - 1][m - 1] + (m <= j - 1 ? C[j - 1][m] : 0)) % p;
+  }
+  std::vector<std::vector<int64_t>> em(k + 1, std::vector<int64_t>(zs.size(), 0));
+  for (size_t zi = 0; zi < zs.size(); ++zi) {
+    const int64_t z = zs[zi];
+    std::vector<int64_t> ev;
+    for (int y = 0; y <= k; ++y) {
+      const int64_t x = ((z + p * y) % mod + mod) % mod;
+      const int64_t v = ((horner(G, x) - z) % mod + mod) % mod;  // divisible by p^k
+      if (v % pk != 0) return false;
+      ev.push_back(v / pk);
+    }
+    std::vector<int64_t> E;
+    if (!interpolate_fp(p, ys, ev, E)) return false;
+    // c(z) = (z^p - z)/p mod p, from z^p mod p^2
+    const int64_t t2 = p * p;
+    int64_t zz = ((z % t2) + t2) % t2, pw = 1;
+    for (int64_t i = 0; i < p; ++i) pw = (int64_t)((__int128)pw * zz % t2);
+    const int64_t cz = ((pw - zz) % t2 + t2) % t2 / p;
+    // -E(c - u) = sum_m e_m u^m
+    for (int j = 0; j <= k; ++j) {
+      int64_t cpow = 1;  // c^(j-m), built from m = j downwards
+      for (int m = j; m >= 0; --m) {
+        int64_t term = E[j] % p * C[j][m] % p * cpow % p;
+        if (m & 1) term = (p - term) % p;
+        em[m][zi] = ((em[m][zi] - term) % p + p) % p;
+        cpow = cpow * cz % p;
+      }
+    }
+  }
+  out.assign(G.begin(), G.end());
+  for (auto& v : out) v %= mod;
+  std::vector<int64_t> Q(p + 1, 0), Qm{1};
+  Q[1] = mod - 1;
+  Q[p] = 1;
+  int64_t pw = pk;  // p^(k-m)
+  for (int m = 0; m <= k; ++m) {
+    bool any = false;
+    for (int64_t v : em[m]) any = any || v != 0;
+    if (any) {
+      std::vector<int64_t> M;
+      if (!interpolate_fp(p, zs, em[m], M)) return false;
+      std::vector<int64_t> term = polymul(Qm, M);
+      if (out.size() < term.size()) out.resize(term.size(), 0);
+      for (size_t i = 0; i < term.size(); ++i) out[i] = (out[i] + mulm(pw, term[i])) % mod;
+    }
+    Qm = polymul(Qm, Q);
+    pw /= p;
+  }
+  while (out.size() > 1 && out.back() == 0) out.pop_back();
+  return true;
+}
+
 // F_LT, F_GT: the interpolants over Z_p of [z < 0] and [z > 0] on the balanced representatives.
 // G_{p,2} = x^p + p H(x) with H the interpolant of (z - z^p)/p on balanced z:
 // then G(z) = z mod p^2 and G'(z) = 0 mod p for every balanced z, so
@@ -151,6 +237,11 @@ static bool build_poly_tables(bgv_ctx* c) {
   c->g2.assign(p + 1, 0);
   for (int64_t k = 0; k < p; ++k) c->g2[k] = (p * H[k]) % t2;
   c->g2[p] = (c->g2[p] + 1) % t2;
+  c->gpe.assign(c->prm.r + 1, {});
+  if (c->prm.r >= 1) c->gpe[1] = {0, 1};
+  if (c->prm.r >= 2) c->gpe[2] = c->g2;
+  for (int e = 3; e <= c->prm.r; ++e)
+    if (!lift_g(p, e - 1, c->gpe[e - 1], c->gpe[e])) return false;
   return true;
 }
 

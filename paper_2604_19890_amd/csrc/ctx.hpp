@@ -63,6 +63,7 @@ struct bgv_ctx {
 
   // polynomial tables (ascending coefficients)
   std::vector<int64_t> g2;    // G_{p,2} mod p^2
+  std::vector<std::vector<int64_t>> gpe;  // gpe[e] = G_{p,e} mod p^e for 1 <= e <= r
   std::vector<int64_t> flt;   // F_LT mod p
   std::vector<int64_t> fgt;   // F_GT mod p
   // slot structure

@@ -754,17 +754,27 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   return result;
 }
 
-// Algorithm 3 with r = 2: a0 = G_{p,2}(x), a1 = DivideByP(x - a0), both tagged t = p.
+// Algorithm 3: for a value tagged t = p^e, e - 1 rounds of a_i = G_{p,e-i}(b),
+// b <- DivideByP(align(b) - a_i); the digits a_0 .. a_{e-2}, b are tagged t = p.
 std::vector<CipherP> ev_space_reduce(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
-  if (x->v.t_exp == 1) return {x};
-  if (x->v.t_exp != 2) throw OpError{BGV_E_UNSUPPORTED};
-  CipherP a0 = ev_eval_poly(c, k, x, c->g2);
-  CipherP xb = ev_align(c, x, a0->v.level);
-  CipherP d = new_cipher(c, x->v.n, a0->v.level, 2);
-  op_add_sub(c, xb->v, a0->v, d->v, 1);
-  CipherP a1 = new_cipher(c, x->v.n, a0->v.level, 1);
-  op_divide_by_p(c, d->v, a1->v);
-  return {with_t(a0, 1), a1};
+  const int e = x->v.t_exp;
+  if (e == 1) return {x};
+  if (e >= (int)c->gpe.size() || c->gpe[e].empty()) throw OpError{BGV_E_UNSUPPORTED};
+  std::vector<CipherP> digits;
+  CipherP b = x;
+  for (int i = 0; i < e - 1; ++i) {
+    const int te = e - i;  // b is tagged t = p^te
+    CipherP ai = ev_eval_poly(c, k, b, c->gpe[te]);
+    CipherP bb = ev_align(c, b, ai->v.level);
+    CipherP d = new_cipher(c, x->v.n, ai->v.level, te);
+    op_add_sub(c, bb->v, ai->v, d->v, 1);
+    CipherP nb = new_cipher(c, x->v.n, ai->v.level, te - 1);
+    op_divide_by_p(c, d->v, nb->v);
+    digits.push_back(with_t(ai, 1));
+    b = nb;
+  }
+  digits.push_back(b);
+  return digits;
 }
 
 static CipherP one_minus(bgv_ctx* c, const CipherP& x) { return ev_const(c, ev_neg(c, x), 1); }
@@ -810,9 +820,10 @@ CipherP ev_compare(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& di
 }
 
 CipherP ev_space_raise(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
-  if (c->prm.r == 1) return with_t(x, 1);
-  if (c->prm.r != 2) throw OpError{BGV_E_UNSUPPORTED};
-  return ev_eval_poly(c, k, with_t(x, c->prm.r), c->g2);
+  const int r = c->prm.r;
+  if (r == 1) return with_t(x, 1);
+  if (r >= (int)c->gpe.size() || c->gpe[r].empty()) throw OpError{BGV_E_UNSUPPORTED};
+  return ev_eval_poly(c, k, with_t(x, r), c->gpe[r]);
 }
 
 CipherP ev_rotate_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {

@@ -94,6 +94,18 @@ def pair_tiny5():
 
 
 @functools.lru_cache(maxsize=None)
+def pair_tiny5_r3():
+    """r = 3 (t = 125): Algorithm 3 with G_{5,3} and G_{5,2}."""
+    return Pair(4, 5, 3, 17, 1, steps=(), conj=True)
+
+
+@functools.lru_cache(maxsize=None)
+def pair_r3_17():
+    """r = 3 with p = 17 (t = 4913): G_{17,3} of degree 33 and G_{17,2}."""
+    return Pair(5, 17, 3, 26, 1, steps=(), conj=True)
+
+
+@functools.lru_cache(maxsize=None)
 def pair_two_pass():
     """A ring large enough for the two-pass NTT (and its fused key-switching pass), with 2-prime digits."""
     return Pair(10, 17, 2, 6, 2, steps=(1,), conj=True)

@@ -7,7 +7,7 @@ from oracle import _ring as R
 from oracle import bgv as B
 from oracle import space as S
 from oracle.params import Params
-from tests.gpu_ctx import Pair, log, pair_hybrid17, pair_tiny17, pair_tiny5
+from tests.gpu_ctx import Pair, log, pair_hybrid17, pair_r3_17, pair_tiny17, pair_tiny5, pair_tiny5_r3
 
 pytestmark = pytest.mark.gpu
 
@@ -144,7 +144,7 @@ def test_eval_poly_matches(deg):
     c.assert_equal(out, [S.eval_poly(P, c.okeys, x, coeffs) for x in oa], f"eval_poly deg {deg}")
 
 
-@pytest.mark.parametrize("pf", [pair_tiny5, pair_tiny17])
+@pytest.mark.parametrize("pf", [pair_tiny5, pair_tiny17, pair_tiny5_r3, pair_r3_17])
 def test_space_switching_composites_match(pf):
     c = pf()
     P, t = c.P, c.P.t_full
@@ -152,7 +152,8 @@ def test_space_switching_composites_match(pf):
     ga, oa = c.enc_both(rows)
     gd = c.lib.space_reduce(c.keys, ga)
     od = [S.space_reduce(P, c.okeys, x) for x in oa]
-    for k in range(2):
+    assert len(gd) == P.r
+    for k in range(P.r):
         c.assert_equal(gd[k], [d[k] for d in od], f"reduce digit {k}")
     glt = c.lib.compare(c.keys, gd, c.G.OP_LT)
     olt = [S.compare(P, c.okeys, d, "lt") for d in od]
