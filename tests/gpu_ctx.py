@@ -106,6 +106,18 @@ def pair_r3_17():
 
 
 @functools.lru_cache(maxsize=None)
+def pair_tiny5_r4():
+    """r = 4 (t = 625): G_{5,4}, G_{5,3}, G_{5,2}."""
+    return Pair(4, 5, 4, 26, 1, steps=(), conj=True)
+
+
+@functools.lru_cache(maxsize=None)
+def pair_r4_37():
+    """p = 37, r = 4 (Table 6's setting): G_{37,4} of degree 109, 40 primes."""
+    return Pair(4, 37, 4, 40, 1, steps=(), conj=True)
+
+
+@functools.lru_cache(maxsize=None)
 def pair_two_pass():
     """A ring large enough for the two-pass NTT (and its fused key-switching pass), with 2-prime digits."""
     return Pair(10, 17, 2, 6, 2, steps=(1,), conj=True)

@@ -44,6 +44,18 @@ def tiny5_r3():
 
 
 @functools.lru_cache(maxsize=None)
+def tiny5_r4():
+    """r = 4 (t = 625): G_{5,4}, G_{5,3}, G_{5,2}."""
+    return Ctx(4, 5, 4, 26, 1)
+
+
+@functools.lru_cache(maxsize=None)
+def tiny37_r4():
+    """p = 37, r = 4 (Table 6's setting, t = 37^4): G_{37,4} of degree 109."""
+    return Ctx(4, 37, 4, 40, 1)
+
+
+@functools.lru_cache(maxsize=None)
 def tiny17():
     return Ctx(5, 17, 2, 18, 1, steps=(1, 2), conj=True)
 

@@ -7,7 +7,8 @@ from oracle import _ring as R
 from oracle import bgv as B
 from oracle import space as S
 from oracle.params import Params
-from tests.gpu_ctx import Pair, log, pair_hybrid17, pair_r3_17, pair_tiny17, pair_tiny5, pair_tiny5_r3
+from tests.gpu_ctx import (Pair, log, pair_hybrid17, pair_r3_17, pair_r4_37, pair_tiny17, pair_tiny5, pair_tiny5_r3,
+                           pair_tiny5_r4)
 
 pytestmark = pytest.mark.gpu
 
@@ -144,7 +145,7 @@ def test_eval_poly_matches(deg):
     c.assert_equal(out, [S.eval_poly(P, c.okeys, x, coeffs) for x in oa], f"eval_poly deg {deg}")
 
 
-@pytest.mark.parametrize("pf", [pair_tiny5, pair_tiny17, pair_tiny5_r3, pair_r3_17])
+@pytest.mark.parametrize("pf", [pair_tiny5, pair_tiny17, pair_tiny5_r3, pair_r3_17, pair_tiny5_r4])
 def test_space_switching_composites_match(pf):
     c = pf()
     P, t = c.P, c.P.t_full
@@ -167,6 +168,25 @@ def test_space_switching_composites_match(pf):
     c.assert_equal(graise, oraise, "raise")
     expect = [[1 if (v % t) > (t - 1) // 2 else 0 for v in r] for r in rows]
     assert np.array_equal(c.lib.decrypt(c.s, graise), np.array(expect))
+
+
+def test_reduce_compare_raise_table6_p37_r4():
+    """p = 37, r = 4 (Table 6): the four digits, LT and its raise against the oracle."""
+    c = pair_r4_37()
+    P, t = c.P, c.P.t_full
+    rows = [[0, t - 1], [(t - 1) // 2, (t + 1) // 2]]
+    ga, oa = c.enc_both(rows)
+    gd = c.lib.space_reduce(c.keys, ga)
+    od = [S.space_reduce(P, c.okeys, x) for x in oa]
+    assert len(gd) == 4
+    for k in range(4):
+        c.assert_equal(gd[k], [d[k] for d in od], f"reduce digit {k}")
+    glt = c.lib.compare(c.keys, gd, c.G.OP_LT)
+    olt = [S.compare(P, c.okeys, d, "lt") for d in od]
+    c.assert_equal(glt, olt, "compare lt")
+    graise = c.lib.space_raise(c.keys, glt)
+    c.assert_equal(graise, [S.space_raise(P, c.okeys, x) for x in olt], "raise")
+    assert np.array_equal(c.lib.decrypt(c.s, graise), np.array([[0, 1], [0, 1]]))
 
 
 def test_rotate_sum_and_batch_equals_singles():

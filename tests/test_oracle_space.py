@@ -8,7 +8,7 @@ import pytest
 from oracle import bgv as B
 from oracle import polys
 from oracle import space as S
-from tests.oracle_ctx import tiny5, tiny5_r3, tiny17
+from tests.oracle_ctx import tiny5, tiny5_r3, tiny5_r4, tiny17, tiny37_r4
 
 
 def _balanced_digits(v, p):
@@ -202,6 +202,26 @@ def test_compare_and_raise_r3_brute_force():
         up = S.space_raise(P, c.keys, lt)
         assert up.t_exp == 3
         assert c.dec(up) == [1 if _centered(v, t) < 0 else 0 for v in vals]
+
+
+@pytest.mark.parametrize("ctx,vals", [
+    (tiny5_r4, [0, 1, 2, 3, 312, 313, 314, 622, 623, 624, 100, 500]),
+    (tiny37_r4, [0, 1874160, 937080, 937081]),  # t = 37^4 = 1874161: 0, -1, and both sides of the middle
+])
+def test_space_switching_r4_sampled(ctx, vals):
+    """r = 4 (Table 6's r): the four balanced digits, LT against zero and its raise, on values
+    around zero, around the middle of Z_{p^4} and elsewhere."""
+    c = ctx()
+    P, p, t = c.P, c.P.p, c.P.t_full
+    for i in range(0, len(vals), P.ell):
+        v = (vals[i:i + P.ell] + vals[:P.ell])[:P.ell]
+        dg = S.space_reduce(P, c.keys, c.enc(v))
+        got = [c.dec(d) for d in dg]
+        for k, x in enumerate(v):
+            assert [g[k] for g in got] == [z % p for z in _balanced_digits_r(x, p, 4)]
+        lt = S.compare(P, c.keys, dg, "lt")
+        assert c.dec(lt) == [1 if _centered(x, t) < 0 else 0 for x in v]
+        assert c.dec(S.space_raise(P, c.keys, lt)) == [1 if _centered(x, t) < 0 else 0 for x in v]
 
 
 def test_fgt_truth_table():
