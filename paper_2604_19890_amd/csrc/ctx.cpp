@@ -27,22 +27,30 @@ static size_t size_class(size_t bytes) {
   return (bytes + step - 1) / step * step;
 }
 
+// A request takes a cached block of its class, else the smallest cached block up to
+// twice its class, else a new allocation.  When device memory is short, cached blocks
+// are freed largest first only until the allocation fits (every hipFree waits for the
+// device, so freeing the whole cache on each miss would serialise the stream).
 void* DevPool::get(size_t bytes) {
   bytes = size_class(bytes);
-  auto it = free_.find(bytes);
-  if (it != free_.end()) {
+  auto it = free_.lower_bound(bytes);
+  if (it != free_.end() && it->first <= 2 * bytes) {
     void* p = it->second;
     free_.erase(it);
     return p;
   }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  while (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();  // clear the sticky allocation error
-    trim();
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      return nullptr;
+    if (free_.empty() || (pinned && *pinned > 0)) return nullptr;
+    auto big = std::prev(free_.end());
+    (void)hipFree(big->second);
+    auto a = all_.find(big->second);
+    if (a != all_.end()) {
+      held -= a->second;
+      all_.erase(a);
     }
+    free_.erase(big);
   }
   all_[p] = bytes;
   held += bytes;
