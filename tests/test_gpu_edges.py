@@ -1,0 +1,91 @@
+"""Edge cases through the C-ABI: rejected arguments (typed statuses, decided on the host before
+anything is enqueued), ragged and broadcast batches, and the degenerate cases of the method."""
+import numpy as np
+import pytest
+
+from oracle import bgv as B
+from oracle import space as S
+from tests.gpu_ctx import pair_tiny17, pair_tiny5
+
+pytestmark = pytest.mark.gpu
+
+
+def _status(c, fn, *args, **kw):
+    with pytest.raises(c.G.BgvError) as ei:
+        fn(*args, **kw)
+    return c.G.STATUS[ei.value.status]
+
+
+def test_rejected_arguments_carry_their_status():
+    c = pair_tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(21)
+    ga, _ = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    lib = c.lib
+    # an empty batch
+    empty = c.G.Ct(ga.tensor, 0, ga.level, ga.t_exp)
+    assert _status(c, lib.negate, empty) == "E_ARG"
+    # input and output buffers smaller than the batch they describe
+    short_in = c.G.Ct(ga.tensor[: ga.tensor.numel() // 2], 2, ga.level, ga.t_exp)
+    assert _status(c, lib.negate, short_in) == "E_ARG"
+    short_out = lib.empty(1, ga.level)
+    assert _status(c, lib.negate, ga, out=short_out) == "E_ARG"
+    # a chain too short for the operation
+    low = lib.mod_switch_to(ga, 1)
+    assert _status(c, lib.mod_switch, low) == "E_LEVEL"
+    assert _status(c, lib.mul, c.keys, low, low) == "E_LEVEL"
+    assert _status(c, lib.eval_poly, c.keys, lib.mod_switch_to(ga, 2), [1, 2, 3, 4, 5, 6, 7, 8, 9]) == "E_LEVEL"
+    # operands tagged with different plaintext moduli
+    gp = lib.set_t_exp(lib.mul_scalar(ga, P.p), 1)
+    assert _status(c, lib.add, ga, gp) == "E_PTXT_MOD"
+    assert _status(c, lib.less_than, c.keys, gp, None) == "E_PTXT_MOD"
+    # a rotation without its key (keys for steps 1 and 2 only)
+    assert _status(c, lib.rotate, c.keys, ga, 3) == "E_NOKEY"
+    # a constant polynomial has nothing to evaluate
+    assert _status(c, lib.eval_poly, c.keys, ga, [5]) == "E_ARG"
+    # the failed calls left the context usable
+    assert np.array_equal(lib.decrypt(c.s, lib.add(ga, ga)), (2 * lib.decrypt(c.s, ga)) % t)
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_ragged_batches_match(n):
+    """Batch sizes that are not powers of two (products, switches, rotations)."""
+    c = pair_tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(30 + n)
+    ga, oa = c.enc_both(g.integers(0, t, size=(n, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(n, P.ell)))
+    c.assert_equal(c.lib.mul_relin(c.keys, ga, gb), [B.mul_relin(P, c.okeys.relin, x, y) for x, y in zip(oa, ob)],
+                   f"mul_relin n={n}")
+    c.assert_equal(c.lib.mod_switch_to(ga, P.L - 5), [B.align(P, x, P.L - 5) for x in oa], f"mod_switch_to n={n}")
+    c.assert_equal(c.lib.rotate(c.keys, gb, 1), [B.rotate(P, c.okeys.galois, x, 1) for x in ob], f"rotate n={n}")
+
+
+def test_broadcast_operand_matches():
+    """One ciphertext against a batch of three (the encrypted threshold of the query)."""
+    c = pair_tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(40)
+    ga, oa = c.enc_both(g.integers(0, t, size=(3, P.ell)))
+    g1, o1 = c.enc_both(g.integers(0, t, size=(1, P.ell)))
+    c.assert_equal(c.lib.sub(ga, g1), [B.sub(P, x, o1[0]) for x in oa], "sub broadcast")
+    c.assert_equal(c.lib.mul(c.keys, ga, g1), [S._mul(P, c.okeys, x, o1[0]) for x in oa], "mul broadcast")
+
+
+def test_degenerate_cases_match():
+    """A linear polynomial (no product), the reduction of a value already in digit space (its
+    single digit is the value itself), and comparison with one digit."""
+    c = pair_tiny5()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(50)
+    ga, oa = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    lin = c.lib.eval_poly(c.keys, ga, [3, 7])
+    assert lin.level == ga.level
+    c.assert_equal(lin, [S.eval_poly(P, c.okeys, x, [3, 7]) for x in oa], "linear polynomial")
+    gp = c.lib.set_t_exp(ga, 1)
+    digits = c.lib.space_reduce(c.keys, gp)
+    assert len(digits) == 1
+    op = [B.change_mod_to_p(P, x) for x in oa]
+    c.assert_equal(digits[0], op, "reduce of a digit-space value")
+    c.assert_equal(c.lib.compare(c.keys, digits, c.G.OP_LT), [S.compare(P, c.okeys, [x], "lt") for x in op],
+                   "compare with one digit")
