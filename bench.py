@@ -241,15 +241,27 @@ def limb_products_per_query_ct():
         count["prod"] += 4 * lv + 2 * dn * (lv + K_)
         return Fake(lv, a.t_exp)
 
+    def tensor(P_, a, b):
+        count["prod"] += 4 * a.level
+        return Fake(a.level, a.t_exp)
+
+    def relin(P_, rk, d, level, t_exp):
+        count["prod"] += 2 * len(P.digits(level)) * (level + K_)
+        return Fake(level, t_exp)
+
     def rotate(P_, gk, a, step):
         lv = a.level
         count["prod"] += 2 * len(P.digits(lv)) * (lv + K_)
         return Fake(lv, a.t_exp)
 
     saved = {k: getattr(OB, k) for k in ("mul_relin", "mod_switch", "add", "sub", "neg", "mul_scalar",
-                                        "add_const", "divide_by_p", "change_mod_to_p", "raise_tag", "rotate")}
+                                        "add_const", "divide_by_p", "change_mod_to_p", "raise_tag", "rotate",
+                                        "tensor", "relin", "add_tensor")}
     try:
         OB.mul_relin = mul_relin
+        OB.tensor = tensor
+        OB.relin = relin
+        OB.add_tensor = lambda P_, d, e, level: d
         OB.rotate = rotate
         OB.mod_switch = lambda P_, a: Fake(a.level - 1, a.t_exp)
         OB.add = lambda P_, a, b: Fake(a.level, a.t_exp)

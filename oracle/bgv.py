@@ -391,14 +391,22 @@ def tensor(P: Params, a: Ct, b: Ct):
     return d
 
 
+def add_tensor(P: Params, d: np.ndarray, e: np.ndarray, level: int) -> np.ndarray:
+    """Sum of two tensor-product triples [3][level][N] (component-wise, mod every q_i)."""
+    return (d + e) % _qcol(P.q[:level])
+
+
+def relin(P: Params, rk: SwitchKey, d: np.ndarray, level: int, t_exp: int) -> Ct:
+    """Relinearisation of a triple (d0, d1, d2): (d0 + u0, d1 + u1) with (u0, u1) the key
+    switch of d2 (no modulus switch inside)."""
+    u0, u1 = key_switch(P, d[2], rk, level, t_exp)
+    q = _qcol(P.q[:level])
+    return Ct(np.stack([(d[0] + u0) % q, (d[1] + u1) % q]), level, t_exp)
+
+
 def mul_relin(P: Params, rk: SwitchKey, a: Ct, b: Ct) -> Ct:
     """Tensor product and relinearisation (no modulus switch inside)."""
-    d = tensor(P, a, b)
-    lv = a.level
-    u0, u1 = key_switch(P, d[2], rk, lv, a.t_exp)
-    q = _qcol(P.q[:lv])
-    c = np.stack([(d[0] + u0) % q, (d[1] + u1) % q])
-    return Ct(c, lv, a.t_exp)
+    return relin(P, rk, tensor(P, a, b), a.level, a.t_exp)
 
 
 # ----------------------------------------------------------------------------- automorphisms

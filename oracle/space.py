@@ -48,6 +48,19 @@ def _mul(P, keys, a, b, cnt=None):
     return B.mod_switch(P, r)
 
 
+def _lazy_products(P, keys, pairs, cnt=None):
+    """sum_j a_j b_j relinearised once: every operand aligned to the lowest level among the
+    pairs, the tensor products summed, one key switch of the summed d2, one modulus switch."""
+    lv = min(min(a.level, b.level) for a, b in pairs)
+    acc = None
+    for a, b in pairs:
+        d = B.tensor(P, B.align(P, a, lv), B.align(P, b, lv))
+        acc = d if acc is None else B.add_tensor(P, acc, d, lv)
+        if cnt is not None:
+            cnt.mul += 1
+    return B.mod_switch(P, B.relin(P, keys.relin, acc, lv, pairs[0][0].t_exp))
+
+
 def _add(P, a, b):
     lv = min(a.level, b.level)
     return B.add(P, B.align(P, a, lv), B.align(P, b, lv))
@@ -99,7 +112,8 @@ def power(P, keys, x, e, cnt=None):
 
 def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
     """Evaluate sum_i coeffs[i] x^i (coefficients mod t = p^t_exp of x).  With parity
-    (the default) an odd-structured polynomial takes the odd split of bsgs_shape."""
+    (the default) an odd-structured polynomial takes the odd split of bsgs_shape.  The outer
+    products I_j y^j are relinearised once, after their tensor products are summed."""
     t = P.t(x.t_exp)
     c = [int(v) % t for v in coeffs]
     D = len(c) - 1
@@ -132,16 +146,15 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
             acc = B.add_const(P, acc, const)
         inner.append(("ct", acc))
 
-    result = None
+    # outer sum: the products I_j y^j, relinearised once together, then the scalar
+    # multiples c_jk y^j of constant inner sums in increasing j, then I_0
+    pairs = [(v, giant[j]) for j, (kind, v) in enumerate(inner) if j >= 1 and kind == "ct"]
+    result = _lazy_products(P, keys, pairs, cnt) if pairs else None
     for j in range(1, g):
         kind, v = inner[j]
-        if kind == "const":
-            if v == 0:
-                continue
+        if kind == "const" and v != 0:
             term = B.mul_scalar(P, giant[j], v)
-        else:
-            term = _mul(P, keys, v, giant[j], cnt)
-        result = term if result is None else _add(P, result, term)
+            result = term if result is None else _add(P, result, term)
     kind, v = inner[0]
     if kind == "const":
         if result is None:

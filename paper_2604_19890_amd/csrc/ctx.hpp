@@ -130,9 +130,10 @@ void negate(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level);
 void mul_scalar(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);
 // add s_i to every word of component 0
 void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);
-// tensor: d01 [n][2][level][N] (d0, d1) and d2 [n][level][N] from a, b [n][2][level][N]
+// tensor: d01 [n][2][level][N] (d0, d1) and d2 [n][level][N] from a, b [n][2][level][N];
+// with acc the triple is added to the one d01 and d2 hold
 void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d01, uint64_t* d2, int n, int level,
-            bool b_bcast);
+            bool b_bcast, bool acc = false);
 // ModUp of the coefficient-form limbs x [n][level][N] -> y [n][dnum'][level+K][N] (coefficient form,
 // own-digit rows left untouched)
 void mod_up(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level);

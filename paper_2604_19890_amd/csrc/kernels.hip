@@ -66,8 +66,11 @@ __global__ void k_add_const(const uint64_t* __restrict__ a, uint64_t* __restrict
 }
 
 // d01[b][0] = a0 b0, d01[b][1] = a0 b1 + a1 b0, d2[b] = a1 b1
+// Tensor product (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); with acc the triple is added
+// to what d and d2 hold (sums of products relinearised once).
 __global__ void k_tensor(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b, uint64_t* __restrict__ d,
-                         uint64_t* __restrict__ d2, int level, int N, int b_bcast, const PrimeD* __restrict__ pc) {
+                         uint64_t* __restrict__ d2, int level, int N, int b_bcast, int acc,
+                         const PrimeD* __restrict__ pc) {
   const int ct = blockIdx.y / level;
   const int i = blockIdx.y % level;
   const double q = pc[i].q, qinv = pc[i].qinv;
@@ -79,10 +82,18 @@ __global__ void k_tensor(const uint64_t* __restrict__ a, const uint64_t* __restr
   // a is read once; a broadcast b is shared by every ciphertext and stays cached
   const double a0 = u2d(ld_once(A)), a1 = u2d(ld_once(A + L2));
   const double b0 = u2d(b_bcast ? B[0] : ld_once(B)), b1 = u2d(b_bcast ? B[L2] : ld_once(B + L2));
-  D[0] = d2u(canon(mul_lazy(a0, b0, q, qinv), q));
-  const double m = mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv);
-  D[L2] = d2u(canon(red(m, q, qinv), q));
-  d2[(size_t)ct * L2 + (size_t)i * N + n0] = d2u(canon(mul_lazy(a1, b1, q, qinv), q));
+  uint64_t* E = d2 + (size_t)ct * L2 + (size_t)i * N + n0;
+  double v0 = mul_lazy(a0, b0, q, qinv);
+  double v1 = mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv);
+  double v2 = mul_lazy(a1, b1, q, qinv);
+  if (acc) {  // |v| < 2q, stored words < q
+    v0 += u2d(D[0]);
+    v1 += u2d(D[L2]);
+    v2 += u2d(E[0]);
+  }
+  D[0] = d2u(canon(red(v0, q, qinv), q));
+  D[L2] = d2u(canon(red(v1, q, qinv), q));
+  E[0] = d2u(canon(red(v2, q, qinv), q));
 }
 
 // ModUp: x [n][level][N] coefficient form -> y [n][dn][level+K][N].  For digit j
@@ -556,9 +567,10 @@ void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, c
                      c->N, t, c->d_prime);
 }
 
-void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, uint64_t* d2, int n, int level, bool bb) {
+void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, uint64_t* d2, int n, int level, bool bb,
+            bool acc) {
   hipLaunchKernelGGL(k_tensor, grid_for(c->N, n * level), dim3(block_for(c->N)), 0, c->stream, a, b, d, d2, level,
-                     c->N, bb ? 1 : 0, c->d_prime);
+                     c->N, bb ? 1 : 0, acc ? 1 : 0, c->d_prime);
 }
 
 void mod_up(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level) {

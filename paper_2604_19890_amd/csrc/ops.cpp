@@ -140,17 +140,16 @@ static void key_switch(bgv_ctx* c, const uint64_t* key, Scratch& X, int n, int l
   lk::mod_down_final(c, U->d, DL.d, add, add_comps == 2 ? add_stride : -add_stride, out, n, level, t_exp);
 }
 
-// Relinearised product followed by one modulus switch, with the switch merged into
-// ModDown: both corrections are formed in coefficient form and go through one NTT
-// (the transform is linear over every Z_q_i, so the words equal those of the
-// relinearised product followed by the separate switch).  The top rows of u and d
-// are dropped by the switch, so they are brought to coefficient form in place.
-void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
-  const int n = a.n, lv = a.level, N = c->N, K = c->prm.K;
-  if (lv < 2) throw OpError{BGV_E_LEVEL};
+// Relinearisation of a tensor triple followed by one modulus switch, with the switch
+// merged into ModDown: both corrections are formed in coefficient form and go through one
+// NTT (the transform is linear over every Z_q_i, so the words equal those of the
+// relinearised triple followed by the separate switch).  D [n][2][lv][N] holds d0, d1 and
+// X [n][lv][N] holds d2; the top rows of u and d are dropped by the switch, so they are
+// brought to coefficient form in place.
+static void relin_ms(bgv_ctx* c, const bgv_keys* keys, Scratch& D, Scratch& X, int n, int lv, int t_exp,
+                     const CtV& out) {
+  const int N = c->N, K = c->prm.K;
   const int rows = lv + K;
-  Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
-  lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1);
   auto U = ks_inner(c, keys->relin, X, n, lv);
   // u's top row and its special rows are the K + 1 consecutive rows lv-1 .. lv+K-1
   // of every polynomial: one inverse transform brings them all to coefficient form
@@ -166,7 +165,7 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   lk::ntt(c, D.d, 2 * n, top, true);  // d tops
   Scratch E(c, (size_t)n * 2 * (lv - 1) * N);
   lk::ms_corr(c, U->d + (size_t)lv * N, (int64_t)rows * N, U->d + (size_t)(lv - 1) * N, (int64_t)rows * N,
-              D.d + (size_t)(lv - 1) * N, (int64_t)lv * N, E.d, n, lv, a.t_exp);
+              D.d + (size_t)(lv - 1) * N, (int64_t)lv * N, E.d, n, lv, t_exp);
   // forward NTT of e with the final step in its last pass:
   // out_i = (d_i - e_i + u_i P^-1) q_top^-1 for i < level-1
   lk::NttEpi ep{};
@@ -179,6 +178,38 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   ep.out = out.d;
   ep.rows = lv - 1;
   lk::ntt(c, E.d, n * 2 * (lv - 1), lm_chain(c, lv - 1), false, nullptr, &ep);
+}
+
+// Relinearised product followed by one modulus switch.
+void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
+  const int n = a.n, lv = a.level, N = c->N;
+  if (lv < 2) throw OpError{BGV_E_LEVEL};
+  Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
+  lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1);
+  relin_ms(c, keys, D, X, n, lv, a.t_exp, out);
+}
+
+// sum_j a_j b_j relinearised once: every operand aligned to the lowest level among the
+// pairs, the tensor products accumulated, one key switch and one modulus switch.
+static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector<std::pair<CipherP, CipherP>>& pairs) {
+  int lv = 1 << 30, n = 1;
+  for (const auto& pr : pairs) {
+    lv = std::min(lv, std::min(pr.first->v.level, pr.second->v.level));
+    n = std::max(n, std::max(pr.first->v.n, pr.second->v.n));
+    if (pr.first->v.t_exp != pairs[0].first->v.t_exp || pr.second->v.t_exp != pairs[0].first->v.t_exp)
+      throw OpError{BGV_E_PTXT_MOD};
+  }
+  if (lv < 2) throw OpError{BGV_E_LEVEL};
+  const int t_exp = pairs[0].first->v.t_exp, N = c->N;
+  Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
+  for (size_t i = 0; i < pairs.size(); ++i) {
+    CipherP a = ev_align(c, pairs[i].first, lv), b = ev_align(c, pairs[i].second, lv);
+    if (a->v.n == 1 && n > 1) std::swap(a, b);
+    lk::tensor(c, a->v.d, b->v.d, D.d, X.d, n, lv, b->v.n == 1 && n > 1, i > 0);
+  }
+  CipherP r = new_cipher(c, n, lv - 1, t_exp);
+  relin_ms(c, k, D, X, n, lv, t_exp, r->v);
+  return r;
 }
 
 void op_mul_relin(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
@@ -582,10 +613,11 @@ static const double* coeff_table(bgv_ctx* c, int t_exp, const std::vector<int64_
 // baby powers x^2..x^k and giant powers y^2..y^(g-1) (y = x^k) by the power
 // rule; inner sums over the nonzero coefficients with every power first brought
 // to the lowest level among those used, scalar terms accumulated in increasing
-// order and the constant added last; outer terms I_j y^j for j = 1..g-1 in
-// increasing order (a scalar multiple of y^j when I_j is a constant), with I_0
-// added at the end.  Each product aligns its operands, relinearises and
-// switches down one prime.
+// order and the constant added last; the outer products I_j y^j (j = 1..g-1, I_j
+// not a constant) tensored at their lowest common level, summed, relinearised once
+// and switched down one prime; then the scalar multiples c_jk y^j of constant inner
+// sums in increasing j, then I_0.  Every other product aligns its operands,
+// relinearises and switches down one prime.
 CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std::vector<int64_t>& coeffs,
                      std::vector<CipherP>* giant_out, int* giant_k) {
   const int64_t t = c->tpow[x->v.t_exp];
@@ -728,15 +760,17 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   // the inner sums hold everything the outer sum needs from the baby steps
   aligned.clear();
   for (auto it = baby.begin(); it != baby.end();) it = (it->first != 1 && it->first != kk) ? baby.erase(it) : std::next(it);
+  // outer sum: the products I_j y^j, relinearised once together, then the scalar
+  // multiples c_jk y^j of constant inner sums in increasing j, then I_0
   CipherP result;
+  std::vector<std::pair<CipherP, CipherP>> pairs;
+  for (int j = 1; j < g; ++j)
+    if (!inner[j].is_const) pairs.push_back({inner[j].ct, giant[j]});
+  if (!pairs.empty()) result = ev_lazy_products(c, k, pairs);
+  pairs.clear();
   for (int j = 1; j < g; ++j) {
-    CipherP term;
-    if (inner[j].is_const) {
-      if (inner[j].cst == 0) continue;
-      term = ev_scalar(c, giant[j], inner[j].cst);
-    } else {
-      term = ev_mul(c, k, inner[j].ct, giant[j]);
-    }
+    if (!inner[j].is_const || inner[j].cst == 0) continue;
+    CipherP term = ev_scalar(c, giant[j], inner[j].cst);
     result = result ? ev_add(c, result, term) : term;
   }
   if (inner[0].is_const) {
