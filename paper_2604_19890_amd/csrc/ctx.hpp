@@ -157,8 +157,6 @@ void msw_w(bgv_ctx* c, const uint64_t* top, uint64_t* wrow, int n, int level, in
 // e [n][2][to][N] = t S (coefficient form) with S the combined drop correction; the
 // switched limb is (c_i - NTT(e_i)) prod q_dropped^-1 (see kernels.hip)
 void msw_corr(bgv_ctx* c, const uint64_t* tl, uint64_t* e, int n, int level, int to, int t_exp);
-// copy limb rows: y[b][c][i] = x[b][c][i] for i < to_level (x has from_level rows)
-void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from_level, int to_level, int comps);
 // Terms and sums of one multi-output linear combination (at most LC_MAXT terms,
 // LC_MAXO sums per launch).
 constexpr int LC_MAXT = 16;

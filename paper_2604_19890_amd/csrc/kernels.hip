@@ -316,13 +316,6 @@ __global__ void k_msw_corr(const uint64_t* __restrict__ tl, uint64_t* __restrict
   }
 }
 
-__global__ void k_copy_rows(const uint64_t* __restrict__ x, uint64_t* __restrict__ y, int from, int to, int N) {
-  const int i = blockIdx.y % to;
-  const int cc = blockIdx.y / to;
-  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  y[((size_t)cc * to + i) * N + n0] = x[((size_t)cc * from + i) * N + n0];
-}
-
 // out[c][i] = sum over the batch of in[b][c][i]  (one block row per limb of one ciphertext)
 __global__ void k_batch_sum(const uint64_t* __restrict__ x, uint64_t* __restrict__ out, int n, int level, int N,
                             const PrimeD* __restrict__ pc) {
@@ -631,11 +624,6 @@ void msw_corr(bgv_ctx* c, const uint64_t* tl, uint64_t* e, int n, int level, int
   hipLaunchKernelGGL(k_msw_corr, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, tl, e, level, to, c->N,
                      c->d_msw, c->prm.L, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
                      c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
-}
-
-void copy_rows(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int from, int to, int comps) {
-  hipLaunchKernelGGL(k_copy_rows, grid_for(c->N, n * comps * to), dim3(block_for(c->N)), 0, c->stream, x, y, from, to,
-                     c->N);
 }
 
 void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, const double* sc, int sc_stride,
