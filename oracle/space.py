@@ -113,7 +113,8 @@ def power(P, keys, x, e, cnt=None):
 def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
     """Evaluate sum_i coeffs[i] x^i (coefficients mod t = p^t_exp of x).  With parity
     (the default) an odd-structured polynomial takes the odd split of bsgs_shape.  The outer
-    products I_j y^j are relinearised once, after their tensor products are summed."""
+    products I_j y^j are relinearised once, after their tensor products are summed; the
+    inner sums are formed at the level where those products meet."""
     t = P.t(x.t_exp)
     c = [int(v) % t for v in coeffs]
     D = len(c) - 1
@@ -130,14 +131,20 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
     def coef(n):
         return c[n] if n <= D else 0
 
+    # every inner sum is formed at the level where the outer products meet (the lowest
+    # level among the non-constant I_j and their y^j), or at its own lowest level if lower
+    used_all = [[i for i in range(1, k) if coef(j * k + i) != 0] for j in range(g)]
+    own = [min(baby[i].level for i in u) if u else None for u in used_all]
+    prods = [j for j in range(1, g) if used_all[j]]
+    meet = min(min(own[j], giant[j].level) for j in prods) if prods else None
     inner = []
     for j in range(g):
-        used = [i for i in range(1, k) if coef(j * k + i) != 0]
+        used = used_all[j]
         const = coef(j * k)
         if not used:
             inner.append(("const", const))
             continue
-        lv = min(baby[i].level for i in used)
+        lv = own[j] if meet is None else min(own[j], meet)
         acc = None
         for i in used:
             term = B.mul_scalar(P, B.align(P, baby[i], lv), coef(j * k + i))

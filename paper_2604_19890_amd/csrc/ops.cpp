@@ -612,12 +612,12 @@ static const double* coeff_table(bgv_ctx* c, int t_exp, const std::vector<int64_
 // odd-structured polynomial, see below), g = ceil((D+1)/k);
 // baby powers x^2..x^k and giant powers y^2..y^(g-1) (y = x^k) by the power
 // rule; inner sums over the nonzero coefficients with every power first brought
-// to the lowest level among those used, scalar terms accumulated in increasing
-// order and the constant added last; the outer products I_j y^j (j = 1..g-1, I_j
-// not a constant) tensored at their lowest common level, summed, relinearised once
-// and switched down one prime; then the scalar multiples c_jk y^j of constant inner
-// sums in increasing j, then I_0.  Every other product aligns its operands,
-// relinearises and switches down one prime.
+// to the level where the outer products meet (or its own lowest level if lower),
+// scalar terms accumulated in increasing order and the constant added last; the
+// outer products I_j y^j (j = 1..g-1, I_j not a constant) tensored at their lowest
+// common level, summed, relinearised once and switched down one prime; then the
+// scalar multiples c_jk y^j of constant inner sums in increasing j, then I_0.
+// Every other product aligns its operands, relinearises and switches down one prime.
 CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std::vector<int64_t>& coeffs,
                      std::vector<CipherP>* giant_out, int* giant_k) {
   const int64_t t = c->tpow[x->v.t_exp];
@@ -691,18 +691,26 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   // Sums at the same level read the same aligned baby powers: one multi-output
   // pass per level reads each power once for all of them (a power absent from
   // a sum has no term there, so every sum gets the words of its own pass).
+  // Every inner sum is formed at the level where the outer products meet (the lowest
+  // level among the non-constant I_j and their y^j), or at its own lowest level if lower.
   std::map<int, std::vector<int>> by_level;
   std::vector<std::vector<int>> used(g);
+  std::vector<int> own(g, 1 << 30);
+  int meet = 1 << 30;
   for (int j = 0; j < g; ++j) {
     for (int i = 1; i < kk; ++i)
-      if (coef(j * kk + i) != 0) used[j].push_back(i);
+      if (coef(j * kk + i) != 0) {
+        used[j].push_back(i);
+        own[j] = std::min(own[j], baby[i]->v.level);
+      }
+    if (j >= 1 && !used[j].empty()) meet = std::min(meet, std::min(own[j], giant[j]->v.level));
+  }
+  for (int j = 0; j < g; ++j) {
     if (used[j].empty()) {
       inner[j] = Inner{true, coef(j * kk), nullptr};
       continue;
     }
-    int lv = 1 << 30;
-    for (int i : used[j]) lv = std::min(lv, baby[i]->v.level);
-    by_level[lv].push_back(j);
+    by_level[std::min(own[j], meet)].push_back(j);
   }
   for (auto& kv : by_level) {
     const int lv = kv.first;
