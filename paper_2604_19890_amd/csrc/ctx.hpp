@@ -130,10 +130,18 @@ void negate(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level);
 void mul_scalar(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);
 // add s_i to every word of component 0
 void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);
-// tensor: d01 [n][2][level][N] (d0, d1) and d2 [n][level][N] from a, b [n][2][level][N];
-// with acc the triple is added to the one d01 and d2 hold
+// tensor: d01 [n][2][level][N] (d0, d1) and d2 [n][level][N] from a, b [n][2][level][N]
 void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d01, uint64_t* d2, int n, int level,
-            bool b_bcast, bool acc = false);
+            bool b_bcast);
+// Pairs of one multi-pair tensor sum (at most TS_MAX per launch).
+constexpr int TS_MAX = 16;
+struct TensorPairs {
+  const uint64_t* a[TS_MAX];
+  const uint64_t* b[TS_MAX];
+  int bb[TS_MAX];  // b is one ciphertext broadcast over the batch
+};
+// d01, d2 = sum over the np pairs of their tensor products (added to what they hold with acc)
+void tensor_sum(bgv_ctx* c, const TensorPairs& tp, int np, uint64_t* d01, uint64_t* d2, int n, int level, bool acc);
 // ModUp of the coefficient-form limbs x [n][level][N] -> y [n][dnum'][level+K][N] (coefficient form,
 // own-digit rows left untouched)
 void mod_up(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level);

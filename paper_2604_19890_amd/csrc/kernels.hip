@@ -66,11 +66,9 @@ __global__ void k_add_const(const uint64_t* __restrict__ a, uint64_t* __restrict
 }
 
 // d01[b][0] = a0 b0, d01[b][1] = a0 b1 + a1 b0, d2[b] = a1 b1
-// Tensor product (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); with acc the triple is added
-// to what d and d2 hold (sums of products relinearised once).
+// Tensor product (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1).
 __global__ void k_tensor(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b, uint64_t* __restrict__ d,
-                         uint64_t* __restrict__ d2, int level, int N, int b_bcast, int acc,
-                         const PrimeD* __restrict__ pc) {
+                         uint64_t* __restrict__ d2, int level, int N, int b_bcast, const PrimeD* __restrict__ pc) {
   const int ct = blockIdx.y / level;
   const int i = blockIdx.y % level;
   const double q = pc[i].q, qinv = pc[i].qinv;
@@ -83,10 +81,38 @@ __global__ void k_tensor(const uint64_t* __restrict__ a, const uint64_t* __restr
   const double a0 = u2d(ld_once(A)), a1 = u2d(ld_once(A + L2));
   const double b0 = u2d(b_bcast ? B[0] : ld_once(B)), b1 = u2d(b_bcast ? B[L2] : ld_once(B + L2));
   uint64_t* E = d2 + (size_t)ct * L2 + (size_t)i * N + n0;
-  double v0 = mul_lazy(a0, b0, q, qinv);
-  double v1 = mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv);
-  double v2 = mul_lazy(a1, b1, q, qinv);
-  if (acc) {  // |v| < 2q, stored words < q
+  const double v0 = mul_lazy(a0, b0, q, qinv);
+  const double v1 = mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv);
+  const double v2 = mul_lazy(a1, b1, q, qinv);
+  D[0] = d2u(canon(red(v0, q, qinv), q));
+  D[L2] = d2u(canon(red(v1, q, qinv), q));
+  E[0] = d2u(canon(red(v2, q, qinv), q));
+}
+
+// Sum of the tensor products of np pairs in one pass: (d0, d1, d2) = sum_t (a0 b0, a0 b1 +
+// a1 b0, a1 b1) of pair t (b broadcast over the batch where bb[t]); with acc the sum is added
+// to what d and d2 hold.  Each operand is read once.
+__global__ void k_tensor_sum(lk::TensorPairs tp, int np, uint64_t* __restrict__ d, uint64_t* __restrict__ d2,
+                             int level, int N, int acc, const PrimeD* __restrict__ pc) {
+  const int ct = blockIdx.y / level;
+  const int i = blockIdx.y % level;
+  const double q = pc[i].q, qinv = pc[i].qinv;
+  const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t L2 = (size_t)level * N;
+  const size_t off = (size_t)i * N + n0;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int t = 0; t < np; ++t) {
+    const uint64_t* A = tp.a[t] + (size_t)ct * 2 * L2 + off;
+    const uint64_t* B = tp.b[t] + (size_t)(tp.bb[t] ? 0 : ct) * 2 * L2 + off;
+    const double a0 = u2d(ld_once(A)), a1 = u2d(ld_once(A + L2));
+    const double b0 = u2d(tp.bb[t] ? B[0] : ld_once(B)), b1 = u2d(tp.bb[t] ? B[L2] : ld_once(B + L2));
+    v0 = red(v0 + mul_lazy(a0, b0, q, qinv), q, qinv);
+    v1 = red(v1 + mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv), q, qinv);
+    v2 = red(v2 + mul_lazy(a1, b1, q, qinv), q, qinv);
+  }
+  uint64_t* D = d + (size_t)ct * 2 * L2 + off;
+  uint64_t* E = d2 + (size_t)ct * L2 + off;
+  if (acc) {
     v0 += u2d(D[0]);
     v1 += u2d(D[L2]);
     v2 += u2d(E[0]);
@@ -560,10 +586,14 @@ void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, c
                      c->N, t, c->d_prime);
 }
 
-void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, uint64_t* d2, int n, int level, bool bb,
-            bool acc) {
+void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, uint64_t* d2, int n, int level, bool bb) {
   hipLaunchKernelGGL(k_tensor, grid_for(c->N, n * level), dim3(block_for(c->N)), 0, c->stream, a, b, d, d2, level,
-                     c->N, bb ? 1 : 0, acc ? 1 : 0, c->d_prime);
+                     c->N, bb ? 1 : 0, c->d_prime);
+}
+
+void tensor_sum(bgv_ctx* c, const TensorPairs& tp, int np, uint64_t* d, uint64_t* d2, int n, int level, bool acc) {
+  hipLaunchKernelGGL(k_tensor_sum, grid_for(c->N, n * level), dim3(block_for(c->N)), 0, c->stream, tp, np, d, d2, level,
+                     c->N, acc ? 1 : 0, c->d_prime);
 }
 
 void mod_up(bgv_ctx* c, const uint64_t* x, uint64_t* y, int n, int level) {

@@ -202,10 +202,21 @@ static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector
   if (lv < 2) throw OpError{BGV_E_LEVEL};
   const int t_exp = pairs[0].first->v.t_exp, N = c->N;
   Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
-  for (size_t i = 0; i < pairs.size(); ++i) {
-    CipherP a = ev_align(c, pairs[i].first, lv), b = ev_align(c, pairs[i].second, lv);
-    if (a->v.n == 1 && n > 1) std::swap(a, b);
-    lk::tensor(c, a->v.d, b->v.d, D.d, X.d, n, lv, b->v.n == 1 && n > 1, i > 0);
+  // the pairs' tensor products summed in passes of at most TS_MAX pairs (each operand read once)
+  for (size_t s0 = 0; s0 < pairs.size(); s0 += lk::TS_MAX) {
+    const int np = (int)std::min<size_t>(lk::TS_MAX, pairs.size() - s0);
+    std::vector<CipherP> keep;
+    lk::TensorPairs tp{};
+    for (int t = 0; t < np; ++t) {
+      CipherP a = ev_align(c, pairs[s0 + t].first, lv), b = ev_align(c, pairs[s0 + t].second, lv);
+      if (a->v.n == 1 && n > 1) std::swap(a, b);
+      tp.a[t] = a->v.d;
+      tp.b[t] = b->v.d;
+      tp.bb[t] = b->v.n == 1 && n > 1;
+      keep.push_back(a);
+      keep.push_back(b);
+    }
+    lk::tensor_sum(c, tp, np, D.d, X.d, n, lv, s0 > 0);
   }
   CipherP r = new_cipher(c, n, lv - 1, t_exp);
   relin_ms(c, k, D, X, n, lv, t_exp, r->v);
