@@ -92,6 +92,9 @@ def setup(args):
     g = synth.rng(args.seed, wl, synth.SLOTS, 0)
     cols = {k: g.integers(0, 1 << 16, size=(B, ell), dtype=np.uint64) for k in "abc"}
     thr = int(g.integers(0, 1 << 16))
+    if args.bits < 16:  # the filter column and threshold on a narrower range
+        cols["a"] >>= np.uint64(16 - args.bits)
+        thr >>= 16 - args.bits
 
     def enc(rows, base):
         c1 = np.empty((len(rows), ctx.L, N), dtype=np.uint64)
@@ -113,6 +116,17 @@ def expected_sum(cols, thr, t=P_ ** R_):
     d = (a - thr) % t
     lt = d > (t - 1) // 2  # centered(a - thr) < 0
     return int((b * c * lt).sum() % t)
+
+
+def sql_agreement(cols, thr, t=P_ ** R_):
+    """How the circuit's predicate (centered a - thr < 0 in Z_t) compares with the integer
+    predicate a < thr: the fraction of rows where they agree (all rows when |a - thr| <=
+    (t - 1) / 2, e.g. 15-bit values), and whether the SUM equals the integer query's."""
+    a, b, c = (cols[k].astype(np.int64) for k in "abc")
+    circ = ((a - thr) % t) > (t - 1) // 2
+    sql = a < thr
+    return {"rows_agree": float((circ == sql).mean()),
+            "sum_equals_sql": int((b * c * sql).sum() % t) == expected_sum(cols, thr, t)}
 
 
 def time_batched(ctx, keys, cts, steps, warmup):
@@ -334,6 +348,9 @@ def main():
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the forward NTT at the query shape and a copy of the same bytes (for counters)")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--bits", type=int, default=16, choices=range(1, 17), metavar="1..16",
+                    help="range of the filter column and threshold (16: the workload; 15: the circuit's "
+                         "comparison equals the integer one on every row)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a design note only",
@@ -386,7 +403,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"filter_sum N=2^16 p=257 r=2 L=30 K=6, {args.cts} ciphertexts x 128 rows per column",
+        "config": {"workload": f"filter_sum N=2^16 p=257 r=2 L=30 K=6, {args.cts} ciphertexts x 128 rows per column"
+                               + (f", {args.bits}-bit filter column" if args.bits < 16 else ""),
                    "rows_per_step": rows, "parallelism": "batch"},
         "plain_rows_per_s": plain_rows,
         "graph_rows_per_s": (rows / t_graph) if t_graph else None,
@@ -398,6 +416,7 @@ def main():
                                f"achieved = 16 N bytes per limb / transform time; traffic = counter bytes "
                                f"per transform"},
         "cpu_baseline": cpu,
+        "sql_agreement": sql_agreement(cols, thr),
     }
     print(json.dumps(line), flush=True)
 

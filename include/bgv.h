@@ -69,7 +69,7 @@ typedef struct {
 typedef struct {
   uint64_t* d;       /* device buffer, n x [2][level][N] uint64, evaluation form */
   int64_t cap_words; /* capacity of d in uint64 words                            */
-  int32_t n;         /* ciphertexts in the batch (>= 1)                          */
+  int32_t n;         /* ciphertexts in the batch, 1 .. bgv_info.max_batch         */
   int32_t level;     /* active primes q_0..q_{level-1}                           */
   int32_t t_exp;     /* plaintext modulus p^t_exp                                */
   int32_t _pad;
@@ -79,6 +79,10 @@ typedef struct {
   int32_t N, log_n, p, r, L, K, alpha, dnum; /* dnum = ceil(L / alpha)       */
   int32_t slots, d;                          /* ell slots of degree d = N/ell */
   int64_t t;                                 /* p^r                          */
+  int32_t max_batch; /* largest n one call accepts: every launch of the call fits the
+                        grid limits (n * dnum * (L + K) <= 65535); larger batches are
+                        split by the caller, a call above it fails with BGV_E_ARG      */
+  int32_t _pad;
 } bgv_info;
 
 typedef struct bgv_ctx bgv_ctx;

@@ -49,7 +49,7 @@ class _Ct(ctypes.Structure):
 
 class _Info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in ("N", "log_n", "p", "r", "L", "K", "alpha", "dnum", "slots", "d")] + \
-               [("t", ctypes.c_int64)]
+               [("t", ctypes.c_int64), ("max_batch", ctypes.c_int32), ("_pad", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -190,6 +190,7 @@ class Context:
         self.N, self.log_n, self.p, self.r = info.N, info.log_n, info.p, info.r
         self.L, self.K, self.alpha, self.dnum = info.L, info.K, info.alpha, info.dnum
         self.slots, self.d, self.t = info.slots, info.d, info.t
+        self.max_batch = info.max_batch
         pr = np.empty(L + K, dtype=np.uint64)
         _lib.bgv_ctx_primes(h, _ptr(pr))
         self.primes = [int(x) for x in pr]

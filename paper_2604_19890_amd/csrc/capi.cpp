@@ -19,6 +19,7 @@ bgv_status fail(bgv_ctx* c, bgv_status st, const char* msg) {
 bgv_status check_in(bgv_ctx* c, const bgv_ct* x, const char* name) {
   if (!x || !x->d) return fail(c, BGV_E_ARG, name);
   if (x->n < 1) return fail(c, BGV_E_ARG, "batch count must be >= 1");
+  if (x->n > c->max_batch()) return fail(c, BGV_E_ARG, "batch count above the context's max_batch");
   if (x->level < 1 || x->level > c->prm.L) return fail(c, BGV_E_LEVEL, "level out of range");
   if (x->t_exp < 1 || x->t_exp > c->prm.r) return fail(c, BGV_E_PTXT_MOD, "t_exp out of range");
   if (x->cap_words < (int64_t)x->n * (int64_t)ct_words(c, x->level)) return fail(c, BGV_E_ARG, "input buffer too small");
@@ -132,6 +133,8 @@ BGV_EXPORT bgv_status bgv_ctx_info(const bgv_ctx* c, bgv_info* o) {
   o->slots = c->ell;
   o->d = c->dslot;
   o->t = c->t_full;
+  o->max_batch = c->max_batch();
+  o->_pad = 0;
   return BGV_OK;
 }
 
@@ -191,6 +194,7 @@ BGV_EXPORT bgv_status bgv_encrypt(bgv_ctx* c, const int8_t* s, const uint64_t* s
                                   const int32_t* e, bgv_ct* out) {
   NEED_CTX(c);
   if (!s || !slots || !c1 || !e || !out || out->n < 1) return fail(c, BGV_E_ARG, "bad encrypt arguments");
+  if (out->n > c->max_batch()) return fail(c, BGV_E_ARG, "batch count above the context's max_batch");
   CHECK(check_out(c, out, out->n, c->prm.L));
   set_out(out, out->n, c->prm.L, c->prm.r);
   return guarded(c, [&] { return op_encrypt(c, s, slots, c1, e, view(out)); });

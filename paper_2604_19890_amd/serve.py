@@ -244,7 +244,7 @@ def serve(queries, engines, mode: str = "batched", round_cts: dict = None, budge
                         admitted.remove(q)
                         e.queue.remove(q)
             if e.queue:
-                limit = round_cts.get(e.log_n, 32) if round_cts else 32
+                limit = min(round_cts.get(e.log_n, 32) if round_cts else 32, e.ctx.max_batch)
                 segs, used = [], 0
                 for q in e.queue:
                     if used >= limit:

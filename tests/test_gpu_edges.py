@@ -89,3 +89,21 @@ def test_degenerate_cases_match():
     c.assert_equal(digits[0], op, "reduce of a digit-space value")
     c.assert_equal(c.lib.compare(c.keys, digits, c.G.OP_LT), [S.compare(P, c.okeys, [x], "lt") for x in op],
                    "compare with one digit")
+
+
+def test_batch_limit():
+    """A call accepts up to max_batch ciphertexts (every launch of the call then fits the grid
+    limits); one more is rejected before anything is enqueued."""
+    c = pair_tiny17()
+    P, t, lib = c.P, c.P.t_full, c.lib
+    assert lib.max_batch == 65535 // (lib.dnum * (lib.L + lib.K))
+    g = np.random.default_rng(60)
+    m = g.integers(0, t, size=(1, P.ell))
+    ga, _ = c.enc_both(m)
+    full = lib.concat([ga] * lib.max_batch)
+    got = lib.decrypt(c.s, lib.mul_scalar(full, 3))
+    assert got.shape[0] == lib.max_batch
+    assert np.array_equal(got[0], (3 * m[0]) % t) and np.array_equal(got[-1], (3 * m[0]) % t)
+    over = lib.concat([full, ga])
+    assert _status(c, lib.mul_scalar, over, 3) == "E_ARG"
+    assert _status(c, lib.mod_switch, over) == "E_ARG"
