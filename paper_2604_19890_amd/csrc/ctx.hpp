@@ -179,7 +179,10 @@ struct LinMulti {
   int row[LC_MAXO][LC_MAXT];  // coefficient row of term t in sum o; -1: absent
   int cst_row[LC_MAXO];       // row of the constant of sum o; -1: none
 };
-void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* sc, int sc_stride, int n, int level);
+// scs (optional): the coefficient of every row as a centered integer, |c| < 2^24 (exact
+// accumulation of split terms; see kernels.hip); null: residues sc[row][i] only
+void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* sc, int sc_stride, const double* scs,
+                   int n, int level);
 // out = sum_t sc[rows[t]][i] * xs[t] (+ sc[cst_row][i] on component 0); nt <= 16 terms, all at `level`
 void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, const double* sc, int sc_stride,
              int cst_row, uint64_t* out, int n, int level);

@@ -382,31 +382,68 @@ __global__ void k_lincomb(LinTerms terms, int nt, const double* __restrict__ sc,
 }
 
 // Several inner sums over one set of terms in one pass: out_o[ct][c][i] =
-// sum_t sc[row[o][t]][i] * x_t[ct][c][i] (+ sc[cst_row[o]][i] on component 0), a term
-// with row -1 being absent from sum o.  Each term is read once for all sums.
+// sum_t c_ot x_t[ct][c][i] (+ the constant sc[cst_row[o]][i] on component 0), where
+// c_ot is the coefficient of row row[o][t] (-1: the term is absent from sum o).  Each
+// term is read once for all sums, and the block's coefficient matrix is staged in LDS
+// first.  With SPLIT the coefficients come as centered integers scs[row], |c| < 2^24:
+// every term is split into 25-bit halves, so that each product is below 2^49 and the
+// sums of at most 16 of them are exact in binary64; a sum then takes one modular
+// product (hi 2^25 + lo) instead of one per term.  Without SPLIT the coefficients are
+// residues sc[row][i] and every product is reduced.
+template <bool SPLIT>
 __global__ void k_lincomb_multi(lk::LinMulti m, int nt, int no, const double* __restrict__ sc, int sc_stride,
-                                int level, int N, const PrimeD* __restrict__ pc) {
+                                const double* __restrict__ scs, int level, int N, const PrimeD* __restrict__ pc) {
+  constexpr int T = lk::LC_MAXT;
+  __shared__ double cf[lk::LC_MAXO * T];
   const int limb = blockIdx.y;
   const int i = limb % level;
   const int comp = (limb / level) & 1;
+  for (int k = threadIdx.x; k < no * T; k += blockDim.x) {
+    const int o = k / T, t = k % T;
+    const int row = t < nt ? m.row[o][t] : -1;
+    cf[k] = row < 0 ? 0.0 : (SPLIT ? scs[row] : sc[(size_t)row * sc_stride + i]);
+  }
+  __syncthreads();
   const double q = pc[i].q, qinv = pc[i].qinv;
   const size_t off = (size_t)limb * N + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double x[lk::LC_MAXT];
+  if constexpr (SPLIT) {
+    double xh[T], xl[T];
 #pragma unroll
-  for (int t = 0; t < lk::LC_MAXT; ++t) x[t] = t < nt ? u2d(ld_once(m.x[t] + off)) : 0.0;
-  for (int o = 0; o < no; ++o) {
-    double acc = 0.0;
-    int cnt = 0;
-#pragma unroll
-    for (int t = 0; t < lk::LC_MAXT; ++t) {
-      const int row = m.row[o][t];
-      if (t < nt && row >= 0) {
-        acc += mul_lazy(x[t], sc[(size_t)row * sc_stride + i], q, qinv);
-        if ((++cnt & 3) == 0) acc = red(acc, q, qinv);
-      }
+    for (int t = 0; t < T; ++t) {
+      const uint64_t v = t < nt ? ld_once(m.x[t] + off) : 0;
+      xh[t] = u2d(v >> 25);
+      xl[t] = u2d(v & 0x1FFFFFFull);
     }
-    if (comp == 0 && m.cst_row[o] >= 0) acc += sc[(size_t)m.cst_row[o] * sc_stride + i];
-    m.out[o][off] = to_u(acc, q, qinv);
+    for (int o = 0; o < no; ++o) {
+      double hi = 0.0, lo = 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        if (t < nt) {
+          const double c = cf[o * T + t];
+          hi = __builtin_fma(c, xh[t], hi);
+          lo = __builtin_fma(c, xl[t], lo);
+        }
+      }
+      double acc = mul_lazy(red(hi, q, qinv), 33554432.0, q, qinv) + red(lo, q, qinv);
+      if (comp == 0 && m.cst_row[o] >= 0) acc += sc[(size_t)m.cst_row[o] * sc_stride + i];
+      __builtin_nontemporal_store(to_u(acc, q, qinv), m.out[o] + off);
+    }
+  } else {
+    double x[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) x[t] = t < nt ? u2d(ld_once(m.x[t] + off)) : 0.0;
+    for (int o = 0; o < no; ++o) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        if (t < nt) {
+          acc += mul_lazy(x[t], cf[o * T + t], q, qinv);
+          if ((t & 3) == 3) acc = red(acc, q, qinv);
+        }
+      }
+      if (comp == 0 && m.cst_row[o] >= 0) acc += sc[(size_t)m.cst_row[o] * sc_stride + i];
+      __builtin_nontemporal_store(to_u(acc, q, qinv), m.out[o] + off);
+    }
   }
 }
 
@@ -667,10 +704,14 @@ void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, con
                      sc_stride, cst_row, out, level, c->N, c->d_prime);
 }
 
-void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* sc, int sc_stride, int n,
-                   int level) {
-  hipLaunchKernelGGL(k_lincomb_multi, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, m, nt, no,
-                     sc, sc_stride, level, c->N, c->d_prime);
+void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* sc, int sc_stride,
+                   const double* scs, int n, int level) {
+  if (scs)
+    hipLaunchKernelGGL(k_lincomb_multi<true>, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, m,
+                       nt, no, sc, sc_stride, scs, level, c->N, c->d_prime);
+  else
+    hipLaunchKernelGGL(k_lincomb_multi<false>, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, m,
+                       nt, no, sc, sc_stride, scs, level, c->N, c->d_prime);
 }
 
 void ms_corr(bgv_ctx* c, const uint64_t* up, int64_t up_stride, const uint64_t* utop, int64_t ut_stride,

@@ -609,8 +609,12 @@ static const double* coeff_table(bgv_ctx* c, int t_exp, const std::vector<int64_
   if (it != c->coeff_tabs.end()) return it->second;
   const int L = c->prm.L;
   const int64_t t = c->tpow[t_exp];
-  std::vector<double> h(cf.size() * (size_t)L);
-  for (size_t r = 0; r < cf.size(); ++r) scalar_table(c, centered(cf[r], t), L, &h[r * L]);
+  // [rows][L] residues of the centered coefficients, then the centered values themselves
+  std::vector<double> h(cf.size() * (size_t)L + cf.size());
+  for (size_t r = 0; r < cf.size(); ++r) {
+    scalar_table(c, centered(cf[r], t), L, &h[r * L]);
+    h[cf.size() * (size_t)L + r] = (double)centered(cf[r], t);
+  }
   double* d = nullptr;
   check_hip(c, hipMalloc((void**)&d, h.size() * sizeof(double)), "coefficient table");
   check_hip(c, hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice), "coefficient table");
@@ -649,6 +653,9 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   auto coef = [&](int n) -> int64_t { return n <= D ? cf[n] : 0; };
 
   const double* tab = coeff_table(c, x->v.t_exp, cf);
+  // the centered coefficients follow the residue rows; they serve the exact split
+  // accumulation of the inner sums when |c| <= (t - 1) / 2 < 2^24
+  const double* scs = t <= ((int64_t)1 << 25) ? tab + cf.size() * (size_t)c->prm.L : nullptr;
   // Only the powers some term uses (and the factors the power rule builds them
   // from) are computed; each of them is the same product chain as in the full
   // table, so skipping the unused ones leaves every output word unchanged.
@@ -748,7 +755,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
           m.cst_row[o] = coef(j * kk) != 0 ? j * kk : -1;
           inner[j] = Inner{false, 0, acc};
         }
-        lk::lincomb_multi(c, m, (int)terms.size(), no, tab, c->prm.L, x->v.n, lv);
+        lk::lincomb_multi(c, m, (int)terms.size(), no, tab, c->prm.L, scs, x->v.n, lv);
       }
       continue;
     }
