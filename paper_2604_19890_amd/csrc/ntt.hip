@@ -142,7 +142,11 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
     sl = threadIdx.x % SUBS;
     tau = threadIdx.x / SUBS;
   }
-  const int st = blockIdx.x * SUBS + sl;
+  // Column pass: the column block turns with the row.  Block ids go round-robin over the
+  // eight XCDs, so with a fixed order an XCD would always take the same column blocks of
+  // every row (16 blocks per row at N = 2^16); turning the order spreads them.
+  const int bx = tmin > 1 ? ((blockIdx.x + blockIdx.y) & (gridDim.x - 1)) : blockIdx.x;
+  const int st = bx * SUBS + sl;
   const int lo = st & (tmin - 1);
   const int hi = st >> tmin_log;
   const int base = (hi << (tmax_log + 1)) + lo;
