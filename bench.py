@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of the forward NTT (both passes) on 960 limbs of N = 2^16, per pass, from
 # `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of `bench.py --ntt-only --cts 16
-# --steps 3` (profiles/ntt_n65536_960limbs_counters.md).  In the same runs a 480 MiB device
+# --steps 3` (profiles/ntt_n65536_960limbs.md).  In the same runs a 480 MiB device
 # copy reads FETCH_SIZE = 245782 KiB and WRITE_SIZE = 491520 KiB, so FETCH_SIZE counts half
 # the bytes moved (scale 2.0) and WRITE_SIZE all of them (1.0).  The figures belong to the
 # NTT sources they were taken on (hash below) and are reported only while those are unchanged.
@@ -195,15 +195,20 @@ def time_graph(ctx, keys, cts, steps):
     return start.elapsed_time(stop) / 1e3 / steps
 
 
-def time_ntt(ctx, n_cts, reps=20, warm=10):
+def time_ntt(ctx, n_cts, reps=20, warm_s=1.0):
     """Forward NTT over n_cts ciphertexts at the top level: per-NTT time with HIP events on the
-    context's stream, after `warm` untimed transforms (which bring the clocks up)."""
+    context's stream, after `warm_s` seconds of untimed transforms, which bring the clocks to their
+    sustained level (ten warm-up transforms leave the time 5-10% above it)."""
     import torch
     limbs = n_cts * 2 * ctx.L
     x = torch.randint(0, 1 << 49, (limbs * ctx.N,), dtype=torch.int64, device="cuda")
-    for _ in range(warm):
-        ctx.ntt(x, n_cts * 2, ctx.L)
-    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(10):
+            ctx.ntt(x, n_cts * 2, ctx.L)
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= warm_s:
+            break
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(reps):
@@ -228,7 +233,7 @@ def ntt_only(args):
         ctx.ntt(x, args.cts * 2, ctx.L)
         y.copy_(x)
     torch.cuda.synchronize()
-    per, algo_bytes, limbs = time_ntt(ctx, args.cts, reps=args.steps)
+    per, algo_bytes, limbs = time_ntt(ctx, args.cts, reps=args.steps, warm_s=0.0)
     log(f"[bench] ntt-only: {limbs} limbs, {algo_bytes / 2**30:.3f} GiB algorithmic per transform, "
         f"copy of {x.numel() * 8 / 2**30:.3f} GiB; {per * 1e6:.1f} us per transform")
 
@@ -348,6 +353,8 @@ def main():
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the forward NTT at the query shape and a copy of the same bytes (for counters)")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-ntt", action="store_true",
+                    help="skip the standalone NTT timing (roofline null), e.g. to profile the query alone")
     ap.add_argument("--bits", type=int, default=16, choices=range(1, 17), metavar="1..16",
                     help="range of the filter column and threshold (16: the workload; 15: the circuit's "
                          "comparison equals the integer one on every row)")
@@ -364,11 +371,13 @@ def main():
     ctx, keys, s, cols, thr, cts = setup(args)
     rows = args.cts * ctx.slots
 
-    # the dominant kernel, the forward NTT at the query's ciphertext shape, timed before the
-    # query so that it runs in the state the profiled `--ntt-only` command measures
-    ntt_s, ntt_bytes, ntt_limbs = time_ntt(ctx, min(args.cts, 16))
-    ntt_gbs = ntt_bytes / ntt_s / 1e9
-    log(f"[bench] NTT: {ntt_limbs} limbs in {ntt_s * 1e3:.3f} ms = {ntt_gbs:.0f} GB/s")
+    # the dominant kernel, the forward NTT at the query's ciphertext shape (16 ciphertexts),
+    # timed before the query after its own warm-up
+    ntt_gbs, ntt_limbs = None, min(args.cts, 16) * 2 * ctx.L
+    if not args.no_ntt:
+        ntt_s, ntt_bytes, ntt_limbs = time_ntt(ctx, min(args.cts, 16))
+        ntt_gbs = ntt_bytes / ntt_s / 1e9
+        log(f"[bench] NTT: {ntt_limbs} limbs in {ntt_s * 1e3:.3f} ms = {ntt_gbs:.0f} GB/s")
 
     elapsed, out = time_batched(ctx, keys, cts, args.steps, args.warmup)
     per_step = elapsed / args.steps
@@ -410,7 +419,8 @@ def main():
         "graph_rows_per_s": (rows / t_graph) if t_graph else None,
         "batched_over_plain": (value / plain_rows) if plain_rows else None,
         "ntt_gb_per_s": ntt_gbs,
-        "roofline": {"bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": None if ntt_gbs is None else {
+                     "bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ntt_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_ntt_pass, forward NTT (two passes) over {ntt_limbs} limbs of N=2^16; "
                                f"achieved = 16 N bytes per limb / transform time; traffic = counter bytes "
