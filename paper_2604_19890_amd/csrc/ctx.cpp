@@ -410,9 +410,18 @@ bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream) {
       c->h_tmod[(size_t)e * Lt + m] = (double)tm;
     }
 
+  // ModDown constants times t P^-1 for the merged switch: mdfold[e][k][i]
+  std::vector<double> mdfold((size_t)(prm->r + 1) * K * L, 0.0);
+  for (int e = 0; e <= prm->r; ++e)
+    for (int k = 0; k < K; ++k)
+      for (int i = 0; i < L; ++i) {
+        const uint64_t qi = c->primes[i];
+        const uint64_t tp = mulmod((uint64_t)c->tpow[e] % qi, (uint64_t)md[K + (size_t)K * L + i], qi);
+        mdfold[((size_t)e * K + k) * L + i] = (double)mulmod((uint64_t)md[K + (size_t)k * L + i], tp, qi);
+      }
   if (!upload(c, &c->d_prime, pd) || !upload(c, &c->d_tw, tw) || !upload(c, &c->d_itw, itw) ||
       !upload(c, &c->d_modup, mu) || !upload(c, &c->d_moddown, md) || !upload(c, &c->d_msw, msw) ||
-      !upload(c, &c->d_mswpi, mswpi) || !upload(c, &c->d_tconst, tc))
+      !upload(c, &c->d_mswpi, mswpi) || !upload(c, &c->d_tconst, tc) || !upload(c, &c->d_mdfold, mdfold))
     return BGV_E_DEVICE;
   if (!build_encoder(c)) { c->err = "slot encoder construction failed"; return BGV_E_PARAM; }
   return BGV_OK;
@@ -424,7 +433,7 @@ void ctx_free(bgv_ctx* c) {
   c->pool.release();
   for (auto& kv : c->coeff_tabs) (void)hipFree(kv.second);
   c->coeff_tabs.clear();
-  void* ptrs[] = {c->d_prime, c->d_tw, c->d_itw, c->d_modup, c->d_moddown, c->d_msw, c->d_mswpi, c->d_tconst};
+  void* ptrs[] = {c->d_prime, c->d_tw, c->d_itw, c->d_modup, c->d_moddown, c->d_msw, c->d_mswpi, c->d_tconst, c->d_mdfold};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

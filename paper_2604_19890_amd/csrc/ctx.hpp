@@ -57,6 +57,9 @@ struct bgv_ctx {
   double* d_mswpi = nullptr;
   // t-dependent scalars: tinv_tab [r+1][Ltot] (t^-1 mod prime), tmod_tab [r+1][Ltot]
   double* d_tconst = nullptr;
+  // ModDown constants with the factor t P^-1 of the merged switch folded in:
+  // [e][k][i] = Phat_k * p^e * P^-1 mod q_i (e <= r, k < K, i < L)
+  double* d_mdfold = nullptr;
 
   // host copies of scalar tables used to build kernel arguments
   std::vector<double> h_tinv, h_tmod;  // [r+1][Ltot]

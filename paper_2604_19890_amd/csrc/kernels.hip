@@ -460,8 +460,9 @@ __global__ void k_lincomb_multi(lk::LinMulti m, int nt, int no, const double* __
 __global__ void k_ms_corr(const uint64_t* __restrict__ up, int64_t up_stride, const uint64_t* __restrict__ utop,
                           int64_t ut_stride, const uint64_t* __restrict__ dtop, int64_t dt_stride,
                           uint64_t* __restrict__ e, int level, int N, int K, int Lfull,
-                          const double* __restrict__ md, const double* __restrict__ tinv,
-                          const double* __restrict__ tmod, const PrimeD* __restrict__ pc) {
+                          const double* __restrict__ md, const double* __restrict__ mdfold,
+                          const double* __restrict__ tinv, const double* __restrict__ tmod,
+                          const PrimeD* __restrict__ pc) {
   const int cc = blockIdx.y;  // ct * 2 + comp
   const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double* phat_inv = md;
@@ -499,13 +500,17 @@ __global__ void k_ms_corr(const uint64_t* __restrict__ up, int64_t up_stride, co
     const double w = canon(mul_lazy(o, tinv[it], q, qinv), q);
     wms = w > (q - 1.0) * 0.5 ? w - q : w;  // centered
   }
+  // e_i = t P^-1 wt_i + t w with t P^-1 folded into the conversion constants
+  // (mdfold[k][i] = Phat_k t P^-1 mod q_i): K + 1 products per word; |a| < K q <= 8 q
   uint64_t* E = e + (size_t)cc * (level - 1) * N + n0;
   for (int i = 0; i < level - 1; ++i) {
     const double q = pc[i].q, qinv = pc[i].qinv;
-    const double tp = mul_lazy(tmod[i], pinv[i], q, qinv);
-    const double a = mul_lazy(fbc(i, q, qinv), tp, q, qinv);
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < K) a += mul_lazy(v[k], mdfold[(size_t)k * Lfull + i], q, qinv);
     const double b = mul_lazy(wms < 0.0 ? wms + q : wms, tmod[i], q, qinv);
-    E[(size_t)i * N] = to_u(a + b, q, qinv);
+    E[(size_t)i * N] = to_u(red(a, q, qinv) + b, q, qinv);
   }
 }
 
@@ -717,7 +722,8 @@ void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* 
 void ms_corr(bgv_ctx* c, const uint64_t* up, int64_t up_stride, const uint64_t* utop, int64_t ut_stride,
              const uint64_t* dtop, int64_t dt_stride, uint64_t* e, int n, int level, int t_exp) {
   hipLaunchKernelGGL(k_ms_corr, grid_for(c->N, n * 2), dim3(block_for(c->N)), 0, c->stream, up, up_stride, utop,
-                     ut_stride, dtop, dt_stride, e, level, c->N, c->prm.K, c->prm.L, c->d_moddown, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
+                     ut_stride, dtop, dt_stride, e, level, c->N, c->prm.K, c->prm.L, c->d_moddown,
+                     c->d_mdfold + (size_t)t_exp * c->prm.K * c->prm.L, c->d_tconst + (size_t)2 * t_exp * c->Ltot,
                      c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot, c->d_prime);
 }
 
