@@ -99,3 +99,32 @@ def test_full_size_products_sampled(shape):
     # and the semantics at full size
     ta, tb = c.lib.decrypt(c.s, ga)[0], c.lib.decrypt(c.s, gb)[0]
     assert np.array_equal(c.lib.decrypt(c.s, prod)[0], (ta.astype(object) * tb.astype(object)) % t)
+
+
+def test_full_size_batch_in_the_bench_launch_shape():
+    """The product step on a batch of 32 ciphertexts at the top of the N = 2^16, L = 30, K = 6
+    chain, the launch shape the benchmark times.  Two ciphertext pairs alternate through the
+    batch, so an index mix-up between neighbours shows; four positions are compared with the
+    oracle on sampled coefficients."""
+    log("[batch32] N=2^16 L=30 K=6, 32 ciphertexts at level 30")
+    c = Pair(16, 257, 2, 30, 6, steps=(), conj=False, hw=120)
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(32)
+    ga, oa = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    A = c.lib.concat([c.lib.view(ga, i % 2, 1) for i in range(32)])
+    Bt = c.lib.concat([c.lib.view(gb, i % 2, 1) for i in range(32)])
+    prod = c.lib.mul(c.keys, A, Bt)
+    assert prod.n == 32 and prod.level == P.L - 1
+    idx = np.array([0, 1, 4097, P.N // 2 + 3, P.N - 1])
+    for k in (0, 1):
+        log(f"[batch32] oracle product of pair {k} at sampled columns ...")
+        ref = B.mul_relin_at(P, c.okeys.relin, oa[k], ob[k], idx)
+        ref_ms = B.mod_switch_cols(P, B.Ct(ref, P.L, oa[k].t_exp))
+        for pos in (k, 30 + k):
+            got = _sampled_words(c, c.lib.view(prod, pos, 1), idx)[0]
+            assert np.array_equal(got, ref_ms.c), f"position {pos} (pair {k})"
+    ta, tb = c.lib.decrypt(c.s, ga), c.lib.decrypt(c.s, gb)
+    got = c.lib.decrypt(c.s, prod)
+    for pos in range(32):
+        assert np.array_equal(got[pos], (ta[pos % 2].astype(object) * tb[pos % 2].astype(object)) % t)
