@@ -266,7 +266,7 @@ int32_t bgv_get_ntt_chunk(const bgv_ctx* ctx);
  * bgv_autotune_ntt: times every valid split on a scratch array of `limbs` limbs
  *   (`reps` forward transforms each, HIP events on the context stream), keeps the
  *   fastest in the context and reports it with its time per transform.  Results
- *   are identical for every split.                                                 */
+ *   are identical for every split.  BGV_E_ARG for limbs above 65535.               */
 bgv_status bgv_set_ntt_split(bgv_ctx* ctx, int32_t first_pass_stages);
 bgv_status bgv_autotune_ntt(bgv_ctx* ctx, int32_t limbs, int32_t reps, int32_t* best_split, float* best_us);
 
@@ -274,7 +274,8 @@ bgv_status bgv_autotune_ntt(bgv_ctx* ctx, int32_t limbs, int32_t reps, int32_t* 
  * bgv_ntt: in place on a DEVICE array holding n_polys polynomials of `level` limbs
  *   each ([n_polys][level][N] uint64 residues, limb i under q_i); forward (coefficient
  *   -> evaluation form, layout as for ciphertexts) when inverse == 0, else inverse.
- *   cap_words is the capacity of d.                                              */
+ *   cap_words is the capacity of d.  At most 65535 limbs (n_polys * level) per call
+ *   (the grid's y extent); BGV_E_ARG beyond.                                     */
 bgv_status bgv_ntt(bgv_ctx* ctx, uint64_t* d, int64_t cap_words, int32_t n_polys, int32_t level,
                    int32_t inverse);
 

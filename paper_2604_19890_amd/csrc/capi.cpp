@@ -452,6 +452,7 @@ BGV_EXPORT bgv_status bgv_ntt(bgv_ctx* c, uint64_t* d, int64_t cap_words, int32_
   NEED_CTX(c);
   if (!d || n_polys < 1 || level < 1 || level > c->Ltot) return fail(c, BGV_E_ARG, "bad ntt arguments");
   if (cap_words < (int64_t)n_polys * level * c->N) return fail(c, BGV_E_ARG, "buffer too small");
+  if ((int64_t)n_polys * level > 65535) return fail(c, BGV_E_ARG, "more than 65535 limbs in one call");
   return guarded(c, [&] {
     op_ntt(c, d, n_polys, level, inverse != 0);
     return BGV_OK;
@@ -563,6 +564,7 @@ BGV_EXPORT bgv_status bgv_set_ntt_split(bgv_ctx* c, int32_t s) {
 BGV_EXPORT bgv_status bgv_autotune_ntt(bgv_ctx* c, int32_t limbs, int32_t reps, int32_t* best_split, float* best_us) {
   NEED_CTX(c);
   if (limbs < 1 || reps < 1) return fail(c, BGV_E_ARG, "limbs and reps must be positive");
+  if (limbs > 65535) return fail(c, BGV_E_ARG, "more than 65535 limbs in one call");
   if (c->capturing) return fail(c, BGV_E_ARG, "cannot tune while capturing");
   return guarded(c, [&] {
     std::vector<int> cands;
@@ -572,9 +574,21 @@ BGV_EXPORT bgv_status bgv_autotune_ntt(bgv_ctx* c, int32_t limbs, int32_t reps, 
     // zero residues are valid input; the transform's time does not depend on the values
     Scratch buf(c, (size_t)limbs * c->N);
     if (hipMemsetAsync(buf.d, 0, buf.bytes, c->stream) != hipSuccess) throw OpError{BGV_E_DEVICE};
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) throw OpError{BGV_E_DEVICE};
+    // events and the split setting are restored on every exit, exceptions included
+    struct Ev {
+      hipEvent_t e = nullptr;
+      ~Ev() {
+        if (e) (void)hipEventDestroy(e);
+      }
+    } ev0, ev1;
+    if (hipEventCreate(&ev0.e) != hipSuccess || hipEventCreate(&ev1.e) != hipSuccess) throw OpError{BGV_E_DEVICE};
+    hipEvent_t e0 = ev0.e, e1 = ev1.e;
     const int saved = c->ntt_split;
+    struct Restore {
+      int& split;
+      int value;
+      ~Restore() { split = value; }
+    } restore{c->ntt_split, saved};
     int best = saved;
     float best_t = 1e30f;
     const int L = c->prm.L;
@@ -593,10 +607,8 @@ BGV_EXPORT bgv_status bgv_autotune_ntt(bgv_ctx* c, int32_t limbs, int32_t reps, 
         best = s;
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c->ntt_split = best >= 0 ? best : saved;
-    if (best_split) *best_split = c->ntt_split;
+    restore.value = best >= 0 ? best : saved;
+    if (best_split) *best_split = restore.value;
     if (best_us) *best_us = best_t;
     return BGV_OK;
   });

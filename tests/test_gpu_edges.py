@@ -107,3 +107,19 @@ def test_batch_limit():
     over = lib.concat([full, ga])
     assert _status(c, lib.mul_scalar, over, 3) == "E_ARG"
     assert _status(c, lib.mod_switch, over) == "E_ARG"
+
+
+def test_raw_ntt_and_autotune_limb_limit():
+    """The raw transform and the split autotuner take at most 65535 limbs per call (the grid's y
+    extent); beyond that they fail on the host with E_ARG instead of launching."""
+    import torch
+    c = pair_tiny17()
+    lib = c.lib
+    level = 5
+    n_polys = 65535 // level + 1
+    x = torch.zeros(n_polys * level * lib.N, dtype=torch.int64, device="cuda")
+    assert _status(c, lib.ntt, x, n_polys, level) == "E_ARG"
+    assert _status(c, lib.autotune_ntt, 65536, 1) == "E_ARG"
+    lib.ntt(x, n_polys - 1, level)  # 65535 limbs: accepted (zeros stay zeros)
+    torch.cuda.synchronize()
+    assert int(x.abs().sum()) == 0
