@@ -80,8 +80,9 @@ typedef struct {
   int32_t slots, d;                          /* ell slots of degree d = N/ell */
   int64_t t;                                 /* p^r                          */
   int32_t max_batch; /* largest n one call accepts: every launch of the call fits the
-                        grid limits (n * dnum * (L + K) <= 65535); larger batches are
-                        split by the caller, a call above it fails with BGV_E_ARG      */
+                        grid limits (n * max(dnum, 2) * (L + K) <= 65535); larger
+                        batches are split by the caller, a call above it fails with
+                        BGV_E_ARG                                                      */
   int32_t _pad;
 } bgv_info;
 

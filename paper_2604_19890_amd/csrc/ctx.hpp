@@ -81,10 +81,11 @@ struct bgv_ctx {
     return ((size_t)(level * dnum + j)) * (size_t)alpha * (1 + Ltot);
   }
   size_t modup_basis_off(int level, int j) const { return modup_inv_off(level, j) + alpha; }
-  // largest batch per call: the widest launch (the first NTT pass of the ModUp output)
-  // has n * dnum' * (level + K) <= n * dnum * Ltot block rows, and a grid's y extent is
-  // at most 65535
-  int max_batch() const { return 65535 / (dnum * Ltot); }
+  // largest batch per call: a grid's y extent is at most 65535, and the widest launches
+  // have n * dnum' * (level + K) <= n * dnum * Ltot block rows (the first NTT pass of the
+  // ModUp output) or at most n * 2 * Ltot (two polynomials' rows, e.g. the top and special
+  // rows of u with one digit)
+  int max_batch() const { return 65535 / ((dnum > 2 ? dnum : 2) * Ltot); }
 };
 
 struct bgv_keys {

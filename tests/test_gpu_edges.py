@@ -96,7 +96,7 @@ def test_batch_limit():
     limits); one more is rejected before anything is enqueued."""
     c = pair_tiny17()
     P, t, lib = c.P, c.P.t_full, c.lib
-    assert lib.max_batch == 65535 // (lib.dnum * (lib.L + lib.K))
+    assert lib.max_batch == 65535 // (max(lib.dnum, 2) * (lib.L + lib.K))
     g = np.random.default_rng(60)
     m = g.integers(0, t, size=(1, P.ell))
     ga, _ = c.enc_both(m)
