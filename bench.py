@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the forward NTT at the query shape and a copy of the same bytes (for counters)")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-basic-schedule", action="store_true",
+                    help="skip timing the query in the basic evaluation schedule")
     ap.add_argument("--no-ntt", action="store_true",
                     help="skip the standalone NTT timing (roofline null), e.g. to profile the query alone")
     ap.add_argument("--bits", type=int, default=16, choices=range(1, 17), metavar="1..16",
@@ -389,6 +391,18 @@ def main():
         assert all(int(v) == exp for v in got), (got[:4], exp)
         log(f"[bench] decrypted SUM = {exp} in every slot (matches the plaintext query)")
 
+    # the same query in the basic evaluation schedule (one product per outer Paterson-Stockmeyer
+    # term, dense split), for comparison with the default schedule timed above
+    basic_sched = None
+    if not args.no_basic_schedule:
+        ctx.set_schedule("basic")
+        el, out_p = time_batched(ctx, keys, cts, args.steps, 1)
+        ctx.set_schedule("fast")
+        if not args.no_check:
+            assert all(int(v) == expected_sum(cols, thr) for v in ctx.decrypt(s, out_p)[0])
+        basic_sched = {"ms_per_step": el / args.steps * 1e3, "rows_per_s": rows * args.steps / el}
+        log(f"[bench] basic schedule: {el / args.steps * 1e3:.1f} ms/step, {rows * args.steps / el:.1f} rows/s")
+
     t_graph = time_graph(ctx, keys, cts, args.steps) if args.graph else None
     if t_graph:
         log(f"[bench] graph replay: {t_graph * 1e3:.1f} ms/step, {rows / t_graph:.1f} rows/s")
@@ -418,6 +432,7 @@ def main():
         "plain_rows_per_s": plain_rows,
         "graph_rows_per_s": (rows / t_graph) if t_graph else None,
         "batched_over_plain": (value / plain_rows) if plain_rows else None,
+        "basic_schedule": basic_sched,
         "ntt_gb_per_s": ntt_gbs,
         "roofline": None if ntt_gbs is None else {
                      "bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",

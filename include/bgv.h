@@ -183,10 +183,26 @@ bgv_status bgv_mod_switch_to(bgv_ctx* ctx, const bgv_ct* in, int32_t level, bgv_
 
 /* ---- polynomial evaluation and space switching ----------------------------
  * bgv_eval_poly: sum_i coeffs[i] x^i (coefficients reduced mod p^t_exp) by the
- *   baby-step/giant-step Paterson-Stockmeyer form (Theorem 2) with the schedule
- *   documented in the library's design notes; every product is followed by one
- *   modulus switch.  The output level is input level minus the schedule depth;
- *   BGV_E_LEVEL if the chain is too short.
+ *   baby-step/giant-step Paterson-Stockmeyer form (Theorem 2), in the context's
+ *   schedule (bgv_set_schedule); every relinearisation is followed by one modulus
+ *   switch.  The output level is input level minus the schedule depth (the same in
+ *   both schedules); BGV_E_LEVEL if the chain is too short.
+ * bgv_set_schedule: the evaluation schedule of every polynomial of the context, the
+ *   space-switching operations included (the paper fixes only the Paterson-Stockmeyer
+ *   form).  Both form baby powers x^2..x^k and giant powers y^j, y = x^k, with
+ *   x^i = (x^(i/2))^2 for i a power of two, else x^h x^(i-h) (h the largest power of two
+ *   below i), each product aligning its operands by single-prime switches.
+ *   BGV_SCHED_FAST (0, the default): odd-structured polynomials (every even
+ *   coefficient strictly between the constant and the leading term zero) take k =
+ *   the smallest power of two with k^2 >= D + 1, others 2k^2 >= D + 1; inner sums
+ *   are formed at the level where the outer products meet (or lower); the products
+ *   I_j y^j are aligned to their lowest common level, their tensor products summed
+ *   and relinearised once, then switched once; then c_jk y^j for constant I_j in
+ *   increasing j, then I_0.
+ *   BGV_SCHED_BASIC (1): k = the smallest power of two with 2k^2 >= D + 1 for every
+ *   polynomial; inner sums at the lowest level among their powers; in increasing j,
+ *   I_j y^j as one product (align, relinearise, switch) or c_jk y^j, added to the
+ *   running sum at the lower level; then I_0.  BGV_E_ARG for other values.
  * bgv_space_reduce: Algorithm 3 on a value tagged t = p^e (1 <= e <= r): e - 1 rounds
  *   of digits[i] = G_{p,e-i}(b), b <- DivideByP(b - digits[i]) (b starts as `in`),
  *   and digits[e-1] = b, all tagged t = p (ChangeModToP); the digits are the
@@ -205,6 +221,9 @@ bgv_status bgv_mod_switch_to(bgv_ctx* ctx, const bgv_ct* in, int32_t level, bgv_
  *   1, 2, 4, .., ell/4 and the row swap; all those keys are needed).           */
 bgv_status bgv_eval_poly(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, const int64_t* coeffs,
                          int32_t degree, bgv_ct* out);
+#define BGV_SCHED_FAST 0
+#define BGV_SCHED_BASIC 1
+bgv_status bgv_set_schedule(bgv_ctx* ctx, int32_t schedule);
 bgv_status bgv_space_reduce(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, bgv_ct* digits);
 bgv_status bgv_compare(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* digits, int32_t r, int32_t op,
                        bgv_ct* out);

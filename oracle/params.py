@@ -98,6 +98,8 @@ class Params:
     r: int
     L: int
     K: int
+    # polynomial evaluation schedule ("fast" or "basic"; see space.eval_poly)
+    schedule: str = "fast"
     N: int = field(init=False)
     t_full: int = field(init=False)
     alpha: int = field(init=False)

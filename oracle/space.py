@@ -111,16 +111,22 @@ def power(P, keys, x, e, cnt=None):
 
 
 def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
-    """Evaluate sum_i coeffs[i] x^i (coefficients mod t = p^t_exp of x).  With parity
-    (the default) an odd-structured polynomial takes the odd split of bsgs_shape.  The outer
-    products I_j y^j are relinearised once, after their tensor products are summed; the
-    inner sums are formed at the level where those products meet."""
+    """Evaluate sum_i coeffs[i] x^i (coefficients mod t = p^t_exp of x) by Paterson-Stockmeyer
+    (Theorem 2) in the schedule P.schedule.
+
+    "fast": with parity (the default) an odd-structured polynomial takes the odd split of
+    bsgs_shape; the outer products I_j y^j are relinearised once, after their tensor products
+    are summed; the inner sums are formed at the level where those products meet.
+    "basic": the dense split for every polynomial; each inner sum at the lowest level among
+    its powers; in increasing j, I_j y^j as one product (_mul) or c_jk y^j, added to the
+    running sum at the lower level; then I_0."""
+    basic = P.schedule == "basic"
     t = P.t(x.t_exp)
     c = [int(v) % t for v in coeffs]
     D = len(c) - 1
     while D > 0 and c[D] == 0:
         D -= 1
-    k, g = bsgs_shape(D, parity and odd_structured(c, D))
+    k, g = bsgs_shape(D, (not basic) and parity and odd_structured(c, D))
     baby = {1: x}
     for i in range(2, k + 1):
         _power_rule(baby, i, P, keys, cnt)
@@ -136,7 +142,7 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
     used_all = [[i for i in range(1, k) if coef(j * k + i) != 0] for j in range(g)]
     own = [min(baby[i].level for i in u) if u else None for u in used_all]
     prods = [j for j in range(1, g) if used_all[j]]
-    meet = min(min(own[j], giant[j].level) for j in prods) if prods else None
+    meet = min(min(own[j], giant[j].level) for j in prods) if prods and not basic else None
     inner = []
     for j in range(g):
         used = used_all[j]
@@ -153,15 +159,28 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
             acc = B.add_const(P, acc, const)
         inner.append(("ct", acc))
 
-    # outer sum: the products I_j y^j, relinearised once together, then the scalar
-    # multiples c_jk y^j of constant inner sums in increasing j, then I_0
-    pairs = [(v, giant[j]) for j, (kind, v) in enumerate(inner) if j >= 1 and kind == "ct"]
-    result = _lazy_products(P, keys, pairs, cnt) if pairs else None
-    for j in range(1, g):
-        kind, v = inner[j]
-        if kind == "const" and v != 0:
-            term = B.mul_scalar(P, giant[j], v)
+    result = None
+    if basic:
+        # in increasing j: I_j y^j as one product, or c_jk y^j, added at the lower level
+        for j in range(1, g):
+            kind, v = inner[j]
+            if kind == "ct":
+                term = _mul(P, keys, v, giant[j], cnt)
+            elif v != 0:
+                term = B.mul_scalar(P, giant[j], v)
+            else:
+                continue
             result = term if result is None else _add(P, result, term)
+    else:
+        # the products I_j y^j, relinearised once together, then the scalar multiples
+        # c_jk y^j of constant inner sums in increasing j
+        pairs = [(v, giant[j]) for j, (kind, v) in enumerate(inner) if j >= 1 and kind == "ct"]
+        result = _lazy_products(P, keys, pairs, cnt) if pairs else None
+        for j in range(1, g):
+            kind, v = inner[j]
+            if kind == "const" and v != 0:
+                term = B.mul_scalar(P, giant[j], v)
+                result = term if result is None else _add(P, result, term)
     kind, v = inner[0]
     if kind == "const":
         if result is None:

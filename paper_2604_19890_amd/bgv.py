@@ -96,6 +96,7 @@ _sigs = {
     "bgv_set_ntt_chunk": [_vp, _i32],
     "bgv_trim": [_vp, _vp],
     "bgv_set_ntt_split": [_vp, _i32],
+    "bgv_set_schedule": [_vp, _i32],
     "bgv_autotune_ntt": [_vp, _i32, _i32, _vp, _vp],
     "bgv_capture_begin": [_vp],
     "bgv_capture_end": [_vp, _P(_vp)],
@@ -420,6 +421,12 @@ class Context:
 
     def set_ntt_split(self, first_pass_stages: int):
         self._check(_lib.bgv_set_ntt_split(self.handle, int(first_pass_stages)))
+
+    SCHEDULES = {"fast": 0, "basic": 1}
+
+    def set_schedule(self, name: str):
+        """Polynomial evaluation schedule of the context: "fast" (default) or "basic"."""
+        self._check(_lib.bgv_set_schedule(self.handle, self.SCHEDULES[name]))
 
     def autotune_ntt(self, limbs: int, reps: int = 10):
         """Pick the fastest NTT pass split for `limbs` limbs; returns (split, microseconds)."""

@@ -553,6 +553,13 @@ BGV_EXPORT void bgv_graph_destroy(bgv_graph* g) {
   delete g;
 }
 
+BGV_EXPORT bgv_status bgv_set_schedule(bgv_ctx* c, int32_t schedule) {
+  NEED_CTX(c);
+  if (schedule != BGV_SCHED_FAST && schedule != BGV_SCHED_BASIC) return fail(c, BGV_E_ARG, "unknown schedule");
+  c->schedule = schedule;
+  return BGV_OK;
+}
+
 BGV_EXPORT bgv_status bgv_set_ntt_split(bgv_ctx* c, int32_t s) {
   NEED_CTX(c);
   if (s != 0 && (s < 4 || s > 8 || c->logN - s < 4 || c->logN - s > 8 || c->logN <= 8))

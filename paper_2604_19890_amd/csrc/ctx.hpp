@@ -35,6 +35,7 @@ struct bgv_ctx {
   std::string err;
   int ntt_chunk = 0;  // limbs per chunk of a two-pass NTT (0: one launch pair for all limbs)
   int ntt_split = 0;  // stages in the first of two NTT passes (0: ceil(log N / 2))
+  int schedule = 0;   // polynomial evaluation schedule (BGV_SCHED_FAST / BGV_SCHED_BASIC)
   int graphs_alive = 0;  // executable graphs referring to pool buffers (trim keeps them then)
   bool capturing = false;
   hipStream_t cap_stream = nullptr;    // capture happens here (default priority, non-blocking)

@@ -633,6 +633,9 @@ static const double* coeff_table(bgv_ctx* c, int t_exp, const std::vector<int64_
 // common level, summed, relinearised once and switched down one prime; then the
 // scalar multiples c_jk y^j of constant inner sums in increasing j, then I_0.
 // Every other product aligns its operands, relinearises and switches down one prime.
+// The basic schedule (BGV_SCHED_BASIC) takes the dense split for every polynomial,
+// forms each inner sum at the lowest level among its powers, and adds the outer terms
+// in increasing j, each I_j y^j as one such product; then I_0.
 CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std::vector<int64_t>& coeffs,
                      std::vector<CipherP>* giant_out, int* giant_k) {
   const int64_t t = c->tpow[x->v.t_exp];
@@ -644,7 +647,10 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   // An odd-structured polynomial (every even coefficient strictly between the
   // constant and the leading term zero: G_{p,e} for odd p, F_LT) needs only the odd
   // baby powers, so its split moves to k = smallest power of two with k^2 >= D+1.
-  bool odd = D >= 3;
+  // The basic schedule keeps the dense split, own-level inner sums and one product
+  // per outer term.
+  const bool basic = c->schedule == BGV_SCHED_BASIC;
+  bool odd = !basic && D >= 3;
   for (int i = 2; i < D && odd; i += 2)
     if (cf[i] != 0) odd = false;
   int kk = 1;
@@ -721,7 +727,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
         used[j].push_back(i);
         own[j] = std::min(own[j], baby[i]->v.level);
       }
-    if (j >= 1 && !used[j].empty()) meet = std::min(meet, std::min(own[j], giant[j]->v.level));
+    if (!basic && j >= 1 && !used[j].empty()) meet = std::min(meet, std::min(own[j], giant[j]->v.level));
   }
   for (int j = 0; j < g; ++j) {
     if (used[j].empty()) {
@@ -786,18 +792,29 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   // the inner sums hold everything the outer sum needs from the baby steps
   aligned.clear();
   for (auto it = baby.begin(); it != baby.end();) it = (it->first != 1 && it->first != kk) ? baby.erase(it) : std::next(it);
-  // outer sum: the products I_j y^j, relinearised once together, then the scalar
-  // multiples c_jk y^j of constant inner sums in increasing j, then I_0
+  // outer sum: the products I_j y^j (relinearised once together in the fast schedule),
+  // the scalar multiples c_jk y^j of constant inner sums, then I_0
   CipherP result;
-  std::vector<std::pair<CipherP, CipherP>> pairs;
-  for (int j = 1; j < g; ++j)
-    if (!inner[j].is_const) pairs.push_back({inner[j].ct, giant[j]});
-  if (!pairs.empty()) result = ev_lazy_products(c, k, pairs);
-  pairs.clear();
-  for (int j = 1; j < g; ++j) {
-    if (!inner[j].is_const || inner[j].cst == 0) continue;
-    CipherP term = ev_scalar(c, giant[j], inner[j].cst);
-    result = result ? ev_add(c, result, term) : term;
+  if (basic) {
+    // in increasing j: I_j y^j as one product, or c_jk y^j, added at the lower level
+    for (int j = 1; j < g; ++j) {
+      CipherP term;
+      if (!inner[j].is_const) term = ev_mul(c, k, inner[j].ct, giant[j]);
+      else if (inner[j].cst != 0) term = ev_scalar(c, giant[j], inner[j].cst);
+      else continue;
+      result = result ? ev_add(c, result, term) : term;
+    }
+  } else {
+    std::vector<std::pair<CipherP, CipherP>> pairs;
+    for (int j = 1; j < g; ++j)
+      if (!inner[j].is_const) pairs.push_back({inner[j].ct, giant[j]});
+    if (!pairs.empty()) result = ev_lazy_products(c, k, pairs);
+    pairs.clear();
+    for (int j = 1; j < g; ++j) {
+      if (!inner[j].is_const || inner[j].cst == 0) continue;
+      CipherP term = ev_scalar(c, giant[j], inner[j].cst);
+      result = result ? ev_add(c, result, term) : term;
+    }
   }
   if (inner[0].is_const) {
     if (!result) throw OpError{BGV_E_ARG};

@@ -4,6 +4,7 @@ Both sides receive the same seeded secret key, key-switching randomness and
 encryption randomness from paper_2604_19890_amd.synth; neither side sees the
 other's outputs.  GPU ciphertexts are brought to coefficient form with the
 library's own inverse NTT before they are compared word by word."""
+import contextlib
 import functools
 import sys
 
@@ -76,6 +77,18 @@ class Pair:
             if not np.array_equal(w[b], o.c):
                 bad = np.argwhere(w[b] != o.c)
                 raise AssertionError(f"{what}: ct {b}: {len(bad)} words differ, first at {bad[0].tolist()}")
+
+
+@contextlib.contextmanager
+def schedule(c, name):
+    """Run a block with both sides of a pair in the named evaluation schedule."""
+    c.P.schedule = name
+    c.lib.set_schedule(name)
+    try:
+        yield c
+    finally:
+        c.P.schedule = "fast"
+        c.lib.set_schedule("fast")
 
 
 @functools.lru_cache(maxsize=None)

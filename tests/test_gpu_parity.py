@@ -8,7 +8,7 @@ from oracle import bgv as B
 from oracle import space as S
 from oracle.params import Params
 from tests.gpu_ctx import (Pair, log, pair_hybrid17, pair_r3_17, pair_r4_37, pair_tiny17, pair_tiny5, pair_tiny5_r3,
-                           pair_tiny5_r4)
+                           pair_tiny5_r4, schedule)
 
 pytestmark = pytest.mark.gpu
 
@@ -131,8 +131,9 @@ def test_rotate_matches(pf):
                        f"rotate {step}")
 
 
+@pytest.mark.parametrize("sched", ["fast", "basic"])
 @pytest.mark.parametrize("deg", [3, 16, 17, 30])
-def test_eval_poly_matches(deg):
+def test_eval_poly_matches(deg, sched):
     c = pair_tiny17()
     P, t = c.P, c.P.t_full
     g = np.random.default_rng(deg)
@@ -141,13 +142,20 @@ def test_eval_poly_matches(deg):
     if deg == 17:
         coeffs[0::2] = [0] * len(coeffs[0::2])  # an odd polynomial (sparse inner sums)
     ga, oa = c.enc_both(g.integers(0, t, size=(2, P.ell)))
-    out = c.lib.eval_poly(c.keys, ga, coeffs)
-    c.assert_equal(out, [S.eval_poly(P, c.okeys, x, coeffs) for x in oa], f"eval_poly deg {deg}")
+    with schedule(c, sched):
+        out = c.lib.eval_poly(c.keys, ga, coeffs)
+        c.assert_equal(out, [S.eval_poly(P, c.okeys, x, coeffs) for x in oa], f"eval_poly deg {deg} {sched}")
 
 
-@pytest.mark.parametrize("pf", [pair_tiny5, pair_tiny17, pair_tiny5_r3, pair_r3_17, pair_tiny5_r4])
-def test_space_switching_composites_match(pf):
-    c = pf()
+@pytest.mark.parametrize("pf,sched", [(pair_tiny5, "fast"), (pair_tiny17, "fast"), (pair_tiny5_r3, "fast"),
+                                      (pair_r3_17, "fast"), (pair_tiny5_r4, "fast"), (pair_tiny5, "basic"),
+                                      (pair_tiny17, "basic"), (pair_tiny5_r3, "basic")])
+def test_space_switching_composites_match(pf, sched):
+    with schedule(pf(), sched) as c:
+        _composites(c)
+
+
+def _composites(c):
     P, t = c.P, c.P.t_full
     rows = [[(i * 37 + b * 11) % t for i in range(P.ell)] for b in range(2)]
     ga, oa = c.enc_both(rows)

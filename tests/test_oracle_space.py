@@ -277,3 +277,63 @@ def test_relu_and_filter_sum_pipelines():
     total = S.rotate_and_sum(P, c.keys, prod)
     expect = sum(x * y for v, x, y in zip(a, b, cc) if v < thr) % t
     assert c.dec(total) == [expect] * P.ell
+
+
+def _basic_products(c, k, g):
+    """Products of the basic schedule: every baby power x^2..x^k, every giant power
+    y^2..y^(g-1), and one product per j >= 1 whose inner sum is not a constant."""
+    D = len(c) - 1
+    coef = lambda n: c[n] if n <= D else 0
+    outer = sum(1 for j in range(1, g) if any(coef(j * k + i) for i in range(1, k)))
+    return (k - 1) + (g - 2) + outer
+
+
+def test_basic_schedule_counts_horner_and_depth():
+    """The basic schedule (dense split, own-level inner sums, one product per outer term) on
+    encrypted inputs: Horner's values, the products counted by hand and the fast schedule's
+    depth.  G_{17,2} (D = 17, k = 4, g = 5): 3 baby + 3 giant + 4 outer = 10; a dense degree-16
+    polynomial: 3 + 3 + 3 = 9 (its I_4 is the constant c_16).  At p = 257 the same count gives
+    15 + 15 + 16 = 46 for G_{257,2} and 15 + 15 + 15 = 45 for F_LT (x^256 enters as a scalar
+    multiple of y^16)."""
+    c = tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(7)
+    G = [v % t for v in polys.g_poly(17, 2)]
+    dense16 = [int(v) for v in g.integers(1, t, size=17)]
+    xs = [int(x) for x in g.integers(0, t, size=P.ell)]
+    a = c.enc(xs)
+    try:
+        for poly, want in ((G, 10), (dense16, 9)):
+            P.schedule = "basic"
+            cnt = S.Counter()
+            out = S.eval_poly(P, c.keys, a, poly, cnt)
+            assert c.dec(out) == [polys.eval_mod(poly, x, t) for x in xs]
+            assert cnt.mul == want == _basic_products(poly, *S.bsgs_shape(len(poly) - 1))
+            P.schedule = "fast"
+            fast = S.eval_poly(P, c.keys, a, poly)
+            assert out.level == fast.level
+    finally:
+        P.schedule = "fast"
+    G257 = [v % 66049 for v in polys.g_poly(257, 2)]
+    F257 = [v % 257 for v in polys.f_lt(257)]
+    assert S.bsgs_shape(257) == (16, 17) and S.bsgs_shape(256) == (16, 17)
+    assert _basic_products(G257, 16, 17) == 46
+    assert _basic_products(F257, 16, 17) == 45
+
+
+def test_basic_schedule_space_switching_brute_force():
+    """reduce -> LT -> raise in the basic schedule over all of Z_25 (p = 5): the same plaintext
+    results as the fast schedule (centered x < 0)."""
+    c = tiny5()
+    P, t = c.P, c.P.t_full
+    vals = list(range(t))
+    try:
+        P.schedule = "basic"
+        got = []
+        for s0 in range(0, t, P.ell):
+            chunk = (vals[s0:s0 + P.ell] + [0] * P.ell)[:P.ell]
+            digits = S.space_reduce(P, c.keys, c.enc(chunk))
+            got += c.dec(S.space_raise(P, c.keys, S.compare(P, c.keys, digits, "lt")))[: len(vals[s0:s0 + P.ell])]
+    finally:
+        P.schedule = "fast"
+    assert got == [1 if v > (t - 1) // 2 else 0 for v in vals]
