@@ -198,7 +198,9 @@ bgv_status bgv_mod_switch_to(bgv_ctx* ctx, const bgv_ct* in, int32_t level, bgv_
  *   are formed at the level where the outer products meet (or lower); the products
  *   I_j y^j are aligned to their lowest common level, their tensor products summed
  *   and relinearised once, then switched once; then c_jk y^j for constant I_j in
- *   increasing j, then I_0.
+ *   increasing j, then I_0.  A power that is itself a product (x^i, i >= 2, and the
+ *   y^j) is aligned by removing its top limbs without rescaling, since its noise is
+ *   already at the floor the last switch left; every other operand is switched.
  *   BGV_SCHED_BASIC (1): k = the smallest power of two with 2k^2 >= D + 1 for every
  *   polynomial; inner sums at the lowest level among their powers; in increasing j,
  *   I_j y^j as one product (align, relinearise, switch) or c_jk y^j, added to the

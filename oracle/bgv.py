@@ -276,6 +276,15 @@ def mod_switch(P: Params, a: Ct) -> Ct:
     return Ct(out, lv - 1, a.t_exp)
 
 
+def drop(P: Params, a: Ct, level: int) -> Ct:
+    """The ciphertext modulo its first `level` primes, without rescaling: c0 + c1 s = m + t e
+    holds modulo every divisor of the modulus, and the primes are 1 mod t, so the limbs above
+    `level` are simply removed (the noise keeps its size)."""
+    if level > a.level or level < 1:
+        raise ValueError("cannot raise a level")
+    return Ct(a.c[:, :level, :].copy(), level, a.t_exp)
+
+
 def align(P: Params, a: Ct, level: int) -> Ct:
     """Sequential single-prime drops down to `level`."""
     if level > a.level:

@@ -38,23 +38,28 @@ class Counter:
         self.max_depth = 0
 
 
-def _mul(P, keys, a, b, cnt=None):
+def _mul(P, keys, a, b, cnt=None, da=False, db=False):
+    """a b relinearised and switched down one prime; each operand first brought to the lower
+    level by dropping limbs (da, db: a power that is itself a product, whose noise is at the
+    floor of the last switch) or by rescaling switches."""
     lv = min(a.level, b.level)
-    a = B.align(P, a, lv)
-    b = B.align(P, b, lv)
+    a = B.drop(P, a, lv) if da else B.align(P, a, lv)
+    b = B.drop(P, b, lv) if db else B.align(P, b, lv)
     r = B.mul_relin(P, keys.relin, a, b)
     if cnt is not None:
         cnt.mul += 1
     return B.mod_switch(P, r)
 
 
-def _lazy_products(P, keys, pairs, cnt=None):
+def _lazy_products(P, keys, pairs, cnt=None, drop_second=False):
     """sum_j a_j b_j relinearised once: every operand aligned to the lowest level among the
-    pairs, the tensor products summed, one key switch of the summed d2, one modulus switch."""
+    pairs (b_j by dropping limbs with drop_second), the tensor products summed, one key switch
+    of the summed d2, one modulus switch."""
     lv = min(min(a.level, b.level) for a, b in pairs)
     acc = None
     for a, b in pairs:
-        d = B.tensor(P, B.align(P, a, lv), B.align(P, b, lv))
+        bb = B.drop(P, b, lv) if drop_second else B.align(P, b, lv)
+        d = B.tensor(P, B.align(P, a, lv), bb)
         acc = d if acc is None else B.add_tensor(P, acc, d, lv)
         if cnt is not None:
             cnt.mul += 1
@@ -91,16 +96,21 @@ def bsgs_shape(D: int, odd: bool = False):
     return k, g
 
 
-def _power_rule(table, i, P, keys, cnt):
+def _power_rule(table, i, P, keys, cnt, unit=1):
+    """x^i = x^(i/2) x^(i/2) for i a power of two, else x^h x^(i-h) (h the largest power of two
+    below i).  table[1] is x^unit of the underlying input; in the fast schedule an operand that is
+    itself a product (exponent times unit >= 2) is aligned by dropping limbs."""
     if i in table:
         return table[i]
     h = 1 << (i.bit_length() - 1)
     if i == h:
-        half = _power_rule(table, i // 2, P, keys, cnt)
+        half = _power_rule(table, i // 2, P, keys, cnt, unit)
         table[i] = _mul(P, keys, half, half, cnt)
     else:
-        table[i] = _mul(P, keys, _power_rule(table, h, P, keys, cnt),
-                        _power_rule(table, i - h, P, keys, cnt), cnt)
+        fast = P.schedule == "fast"
+        table[i] = _mul(P, keys, _power_rule(table, h, P, keys, cnt, unit),
+                        _power_rule(table, i - h, P, keys, cnt, unit), cnt,
+                        da=fast and h * unit >= 2, db=fast and (i - h) * unit >= 2)
     return table[i]
 
 
@@ -116,7 +126,8 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
 
     "fast": with parity (the default) an odd-structured polynomial takes the odd split of
     bsgs_shape; the outer products I_j y^j are relinearised once, after their tensor products
-    are summed; the inner sums are formed at the level where those products meet.
+    are summed; the inner sums are formed at the level where those products meet; a power that
+    is itself a product is aligned by dropping limbs (drop), every other operand by rescaling.
     "basic": the dense split for every polynomial; each inner sum at the lowest level among
     its powers; in increasing j, I_j y^j as one product (_mul) or c_jk y^j, added to the
     running sum at the lower level; then I_0."""
@@ -132,7 +143,7 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
         _power_rule(baby, i, P, keys, cnt)
     giant = {1: baby[k]}
     for j in range(2, g):
-        _power_rule(giant, j, P, keys, cnt)
+        _power_rule(giant, j, P, keys, cnt, unit=k)
 
     def coef(n):
         return c[n] if n <= D else 0
@@ -153,7 +164,9 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
         lv = own[j] if meet is None else min(own[j], meet)
         acc = None
         for i in used:
-            term = B.mul_scalar(P, B.align(P, baby[i], lv), coef(j * k + i))
+            # a baby power that is a product (i >= 2) drops limbs in the fast schedule
+            xi = B.drop(P, baby[i], lv) if (not basic and i >= 2) else B.align(P, baby[i], lv)
+            term = B.mul_scalar(P, xi, coef(j * k + i))
             acc = term if acc is None else B.add(P, acc, term)
         if const != 0:
             acc = B.add_const(P, acc, const)
@@ -175,7 +188,7 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
         # the products I_j y^j, relinearised once together, then the scalar multiples
         # c_jk y^j of constant inner sums in increasing j
         pairs = [(v, giant[j]) for j, (kind, v) in enumerate(inner) if j >= 1 and kind == "ct"]
-        result = _lazy_products(P, keys, pairs, cnt) if pairs else None
+        result = _lazy_products(P, keys, pairs, cnt, drop_second=k >= 2) if pairs else None
         for j in range(1, g):
             kind, v = inner[j]
             if kind == "const" and v != 0:

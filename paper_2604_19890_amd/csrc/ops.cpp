@@ -189,9 +189,13 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   relin_ms(c, keys, D, X, n, lv, a.t_exp, out);
 }
 
+static CipherP ev_drop(bgv_ctx* c, const CipherP& x, int level);
+
 // sum_j a_j b_j relinearised once: every operand aligned to the lowest level among the
-// pairs, the tensor products accumulated, one key switch and one modulus switch.
-static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector<std::pair<CipherP, CipherP>>& pairs) {
+// pairs (b_j by dropping limbs when drop_second), the tensor products accumulated, one key
+// switch and one modulus switch.
+static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector<std::pair<CipherP, CipherP>>& pairs,
+                                bool drop_second) {
   int lv = 1 << 30, n = 1;
   for (const auto& pr : pairs) {
     lv = std::min(lv, std::min(pr.first->v.level, pr.second->v.level));
@@ -208,7 +212,8 @@ static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector
     std::vector<CipherP> keep;
     lk::TensorPairs tp{};
     for (int t = 0; t < np; ++t) {
-      CipherP a = ev_align(c, pairs[s0 + t].first, lv), b = ev_align(c, pairs[s0 + t].second, lv);
+      CipherP a = ev_align(c, pairs[s0 + t].first, lv);
+      CipherP b = drop_second ? ev_drop(c, pairs[s0 + t].second, lv) : ev_align(c, pairs[s0 + t].second, lv);
       if (a->v.n == 1 && n > 1) std::swap(a, b);
       tp.a[t] = a->v.d;
       tp.b[t] = b->v.d;
@@ -531,6 +536,38 @@ static CipherP with_t(const CipherP& x, int t_exp) {
   return r;
 }
 
+// The ciphertext reduced modulo its first `level` primes: the top limbs are dropped
+// without rescaling (the decryption relation holds modulo every divisor of the
+// modulus, and the primes are 1 mod t, so the message is unchanged).  The noise
+// keeps its size, which equals what a rescaling switch leaves for a ciphertext whose
+// noise is already at the floor of the last switch: a power that is itself a product.
+static CipherP ev_drop(bgv_ctx* c, const CipherP& x, int level) {
+  if (x->v.level == level) return x;
+  if (level > x->v.level || level < 1) throw OpError{BGV_E_LEVEL};
+  CipherP r = new_cipher(c, x->v.n, level, x->v.t_exp);
+  const size_t N = c->N;
+  check_hip(c,
+            hipMemcpy2DAsync(r->v.d, (size_t)level * N * 8, x->v.d, (size_t)x->v.level * N * 8,
+                             (size_t)level * N * 8, (size_t)x->v.n * 2, hipMemcpyDeviceToDevice, c->stream),
+            "drop limbs");
+  return r;
+}
+
+// a * b with each operand brought to the lower level by dropping limbs (da, db) or by
+// rescaling switches
+static CipherP ev_mul_pw(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& b, bool da, bool db) {
+  const int lv = std::min(a->v.level, b->v.level);
+  if (lv < 2) throw OpError{BGV_E_LEVEL};
+  if (a->v.t_exp != b->v.t_exp) throw OpError{BGV_E_PTXT_MOD};
+  CipherP a2 = da ? ev_drop(c, a, lv) : ev_align(c, a, lv);
+  CipherP b2 = db ? ev_drop(c, b, lv) : ev_align(c, b, lv);
+  const int n = std::max(a->v.n, b->v.n);
+  CipherP r = new_cipher(c, n, lv - 1, a->v.t_exp);
+  if (a2->v.n == 1 && n > 1) op_mul_ms(c, k, b2->v, a2->v, r->v);
+  else op_mul_ms(c, k, a2->v, b2->v, r->v);
+  return r;
+}
+
 CipherP ev_mul(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& b) {
   const int lv = std::min(a->v.level, b->v.level);
   if (lv < 2) throw OpError{BGV_E_LEVEL};
@@ -572,20 +609,23 @@ static CipherP ev_neg(bgv_ctx* c, const CipherP& x) {
   return r;
 }
 
-// x^i by the power rule: h = 2^floor(log2 i); x^i = x^(i/2) x^(i/2) if i = h, else x^h x^(i-h)
-static const CipherP& power(bgv_ctx* c, const bgv_keys* k, std::map<int, CipherP>& tab, int i) {
+// x^i by the power rule: h = 2^floor(log2 i); x^i = x^(i/2) x^(i/2) if i = h, else x^h x^(i-h).
+// tab[1] is x^unit of the underlying input; in the fast schedule an operand that is
+// itself a product (exponent h unit >= 2) is aligned by dropping limbs.
+static const CipherP& power(bgv_ctx* c, const bgv_keys* k, std::map<int, CipherP>& tab, int i, int unit = 1) {
   auto it = tab.find(i);
   if (it != tab.end()) return it->second;
   int h = 1;
   while (2 * h <= i) h *= 2;
   CipherP r;
   if (i == h) {
-    const CipherP& half = power(c, k, tab, i / 2);
+    const CipherP& half = power(c, k, tab, i / 2, unit);
     r = ev_mul(c, k, half, half);
   } else {
-    const CipherP& a = power(c, k, tab, h);
-    const CipherP& b = power(c, k, tab, i - h);
-    r = ev_mul(c, k, a, b);
+    const CipherP& a = power(c, k, tab, h, unit);
+    const CipherP& b = power(c, k, tab, i - h, unit);
+    const bool drop = c->schedule == BGV_SCHED_FAST;
+    r = ev_mul_pw(c, k, a, b, drop && h * unit >= 2, drop && (i - h) * unit >= 2);
   }
   return tab[i] = r;
 }
@@ -694,14 +734,15 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   std::map<int, CipherP> giant;
   giant[1] = baby[kk];
   for (int j = 2; j < g; ++j)
-    if (need_g[j]) power(c, k, giant, j);
+    if (need_g[j]) power(c, k, giant, j, kk);
 
   std::map<std::pair<int, int>, CipherP> aligned;
   auto aligned_power = [&](int i, int lv) -> CipherP {
     auto key = std::make_pair(i, lv);
     auto it = aligned.find(key);
     if (it != aligned.end()) return it->second;
-    CipherP r = ev_align(c, baby[i], lv);
+    // a baby power that is a product (i >= 2) drops limbs in the fast schedule
+    CipherP r = (!basic && i >= 2) ? ev_drop(c, baby[i], lv) : ev_align(c, baby[i], lv);
     aligned[key] = r;
     return r;
   };
@@ -808,7 +849,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
     std::vector<std::pair<CipherP, CipherP>> pairs;
     for (int j = 1; j < g; ++j)
       if (!inner[j].is_const) pairs.push_back({inner[j].ct, giant[j]});
-    if (!pairs.empty()) result = ev_lazy_products(c, k, pairs);
+    if (!pairs.empty()) result = ev_lazy_products(c, k, pairs, kk >= 2);  // y^j = x^(j kk) are products
     pairs.clear();
     for (int j = 1; j < g; ++j) {
       if (!inner[j].is_const || inner[j].cst == 0) continue;

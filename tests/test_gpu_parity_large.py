@@ -1,11 +1,13 @@
 """GPU parity on rings with the two-pass NTT (and the fused key-switching pass), the tiny
 workload end to end at N = 4096, and sampled checks at the real sizes N = 2^15 and 2^16."""
+import math
+
 import numpy as np
 import pytest
 
 from oracle import bgv as B
 from oracle import space as S
-from tests.gpu_ctx import Pair, log, pair_two_pass
+from tests.gpu_ctx import Pair, log, pair_two_pass, schedule
 
 pytestmark = pytest.mark.gpu
 
@@ -128,3 +130,44 @@ def test_full_size_batch_in_the_bench_launch_shape():
     got = c.lib.decrypt(c.s, prod)
     for pos in range(32):
         assert np.array_equal(got[pos], (ta[pos % 2].astype(object) * tb[pos % 2].astype(object)) % t)
+
+
+def _noise_bits(c, ct):
+    """log2 of the largest |c0 + c1 s| (centered mod q_0) over the coefficients of a level-1
+    ciphertext: the plaintext (|m| <= t/2) plus t times the noise."""
+    from oracle import _ring as R
+    q0 = c.P.q[0]
+    w = c.coeff_words(ct)[0]  # [2][level][N]
+    s = np.mod(np.asarray(c.s, dtype=np.int64), q0).astype(np.uint64)
+    phase = (w[0, 0].astype(object) + R.negacyclic_dot(w[1, 0], s, q0).astype(object)) % q0
+    big = max(abs(int(v) - q0 if int(v) > q0 // 2 else int(v)) for v in phase)
+    return math.log2(max(big, 1)), math.log2(q0 / 2)
+
+
+def test_noise_margin_of_the_query_at_full_size():
+    """The filter+SUM query at N = 2^16, L = 30, K = 6 with the dense ternary secret of the
+    benchmark: its result decrypts to the plaintext query in both evaluation schedules, and the
+    largest |c0 + c1 s| of the final ciphertext stays well below q_0 / 2.  The fast schedule
+    aligns powers by dropping limbs; the margin shows what that leaves."""
+    log("[noise] N=2^16 L=30 K=6, dense ternary secret, 2 ciphertexts per column")
+    c = Pair(16, 257, 2, 30, 6, steps=(1, 2, 4, 8, 16, 32), conj=True, oracle_keys=False)
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(77)
+    cols = {k: g.integers(0, 1 << 16, size=(2, P.ell)) for k in "abc"}
+    thr = int(g.integers(0, 1 << 16))
+    A, Bc, C = (c.enc_both(cols[k], oracle=False)[0] for k in "abc")
+    T = c.enc_both(np.full((1, P.ell), thr), oracle=False)[0]
+    a, b, cc = (cols[k].astype(np.int64) for k in "abc")
+    want = int((b * cc * (((a - thr) % t) > (t - 1) // 2)).sum() % t)
+    margins = {}
+    for sched in ("fast", "basic"):
+        with schedule(c, sched):
+            out = c.lib.filter_sum(c.keys, A, T, Bc, C)
+        assert out.level >= 1
+        assert all(int(v) == want for v in c.lib.decrypt(c.s, out)[0]), sched
+        if out.level > 1:
+            out = c.lib.mod_switch_to(out, 1)
+        bits, half = _noise_bits(c, out)
+        margins[sched] = half - bits
+        log(f"[noise] {sched}: largest |c0 + c1 s| = 2^{bits:.1f}, q_0 / 2 = 2^{half:.1f}")
+    assert min(margins.values()) >= 8, margins
