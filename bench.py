@@ -275,7 +275,7 @@ def limb_products_per_query_ct():
 
     saved = {k: getattr(OB, k) for k in ("mul_relin", "mod_switch", "add", "sub", "neg", "mul_scalar",
                                         "add_const", "divide_by_p", "change_mod_to_p", "raise_tag", "rotate",
-                                        "tensor", "relin", "add_tensor")}
+                                        "tensor", "relin", "add_tensor", "drop")}
     try:
         OB.mul_relin = mul_relin
         OB.tensor = tensor
@@ -283,6 +283,7 @@ def limb_products_per_query_ct():
         OB.add_tensor = lambda P_, d, e, level: d
         OB.rotate = rotate
         OB.mod_switch = lambda P_, a: Fake(a.level - 1, a.t_exp)
+        OB.drop = lambda P_, a, level: Fake(level, a.t_exp)
         OB.add = lambda P_, a, b: Fake(a.level, a.t_exp)
         OB.sub = lambda P_, a, b: Fake(a.level, a.t_exp)
         OB.neg = lambda P_, a: Fake(a.level, a.t_exp)

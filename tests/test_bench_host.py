@@ -42,3 +42,14 @@ def test_fifteen_bit_values_always_agree_and_sixteen_bit_do_not():
     bad = sum((1.0 - bench.sql_agreement(_cols(a16), int(thr))["rows_agree"]) for thr in range(0, 1 << 16, 64))
     share = bad / len(range(0, 1 << 16, 64))
     assert abs(share - ((65536 - 33025) / 65536) ** 2) < 2e-3
+
+
+def test_cpu_baseline_schedule_replay_runs_and_restores_the_oracle():
+    """The CPU baseline scales one oracle product by the limb products of the oracle's own
+    schedule, replayed on level-only stand-ins; the replay must cover every oracle function the
+    schedule calls and put them all back."""
+    import oracle.bgv as OB
+    before = {k: getattr(OB, k) for k in ("mul_relin", "mod_switch", "drop", "tensor", "relin", "align")}
+    per_ct, tail = bench.limb_products_per_query_ct()
+    assert per_ct > 0 and tail > 0
+    assert all(getattr(OB, k) is v for k, v in before.items())
