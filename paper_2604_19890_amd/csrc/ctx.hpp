@@ -140,14 +140,17 @@ void mul_scalar(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, 
 // add s_i to every word of component 0
 void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);
 // tensor: d01 [n][2][level][N] (d0, d1) and d2 [n][level][N] from a, b [n][2][level][N]
+// (sa, sb: limbs per polynomial of a and b in memory when above level; 0: level)
 void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d01, uint64_t* d2, int n, int level,
-            bool b_bcast);
+            bool b_bcast, int sa = 0, int sb = 0);
 // Pairs of one multi-pair tensor sum (at most TS_MAX per launch).
 constexpr int TS_MAX = 16;
 struct TensorPairs {
   const uint64_t* a[TS_MAX];
   const uint64_t* b[TS_MAX];
   int bb[TS_MAX];  // b is one ciphertext broadcast over the batch
+  int sa[TS_MAX];  // limbs per polynomial of a and b in memory (at least the level; 0: the level)
+  int sb[TS_MAX];
 };
 // d01, d2 = sum over the np pairs of their tensor products (added to what they hold with acc)
 void tensor_sum(bgv_ctx* c, const TensorPairs& tp, int np, uint64_t* d01, uint64_t* d2, int n, int level, bool acc);
@@ -180,6 +183,7 @@ constexpr int LC_MAXT = 16;
 constexpr int LC_MAXO = 24;
 struct LinMulti {
   const uint64_t* x[LC_MAXT];
+  int xs[LC_MAXT];  // limbs per polynomial of term t in memory (at least the level; 0: the level)
   uint64_t* out[LC_MAXO];
   int row[LC_MAXO][LC_MAXT];  // coefficient row of term t in sum o; -1: absent
   int cst_row[LC_MAXO];       // row of the constant of sum o; -1: none

@@ -68,18 +68,20 @@ __global__ void k_add_const(const uint64_t* __restrict__ a, uint64_t* __restrict
 // d01[b][0] = a0 b0, d01[b][1] = a0 b1 + a1 b0, d2[b] = a1 b1
 // Tensor product (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1).
 __global__ void k_tensor(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b, uint64_t* __restrict__ d,
-                         uint64_t* __restrict__ d2, int level, int N, int b_bcast, const PrimeD* __restrict__ pc) {
+                         uint64_t* __restrict__ d2, int level, int N, int b_bcast, int sa, int sb,
+                         const PrimeD* __restrict__ pc) {
   const int ct = blockIdx.y / level;
   const int i = blockIdx.y % level;
   const double q = pc[i].q, qinv = pc[i].qinv;
   const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t L2 = (size_t)level * N;
-  const uint64_t* A = a + (size_t)ct * 2 * L2 + (size_t)i * N + n0;
-  const uint64_t* B = b + (size_t)(b_bcast ? 0 : ct) * 2 * L2 + (size_t)i * N + n0;
+  const size_t LA = (size_t)sa * N, LB = (size_t)sb * N;  // polynomial strides of the operands
+  const uint64_t* A = a + (size_t)ct * 2 * LA + (size_t)i * N + n0;
+  const uint64_t* B = b + (size_t)(b_bcast ? 0 : ct) * 2 * LB + (size_t)i * N + n0;
   uint64_t* D = d + (size_t)ct * 2 * L2 + (size_t)i * N + n0;
   // a is read once; a broadcast b is shared by every ciphertext and stays cached
-  const double a0 = u2d(ld_once(A)), a1 = u2d(ld_once(A + L2));
-  const double b0 = u2d(b_bcast ? B[0] : ld_once(B)), b1 = u2d(b_bcast ? B[L2] : ld_once(B + L2));
+  const double a0 = u2d(ld_once(A)), a1 = u2d(ld_once(A + LA));
+  const double b0 = u2d(b_bcast ? B[0] : ld_once(B)), b1 = u2d(b_bcast ? B[LB] : ld_once(B + LB));
   uint64_t* E = d2 + (size_t)ct * L2 + (size_t)i * N + n0;
   const double v0 = mul_lazy(a0, b0, q, qinv);
   const double v1 = mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv);
@@ -102,10 +104,12 @@ __global__ void k_tensor_sum(lk::TensorPairs tp, int np, uint64_t* __restrict__ 
   const size_t off = (size_t)i * N + n0;
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
   for (int t = 0; t < np; ++t) {
-    const uint64_t* A = tp.a[t] + (size_t)ct * 2 * L2 + off;
-    const uint64_t* B = tp.b[t] + (size_t)(tp.bb[t] ? 0 : ct) * 2 * L2 + off;
-    const double a0 = u2d(ld_once(A)), a1 = u2d(ld_once(A + L2));
-    const double b0 = u2d(tp.bb[t] ? B[0] : ld_once(B)), b1 = u2d(tp.bb[t] ? B[L2] : ld_once(B + L2));
+    const size_t LA = (size_t)(tp.sa[t] ? tp.sa[t] : level) * N;  // polynomial strides (0: level)
+    const size_t LB = (size_t)(tp.sb[t] ? tp.sb[t] : level) * N;
+    const uint64_t* A = tp.a[t] + (size_t)ct * 2 * LA + off;
+    const uint64_t* B = tp.b[t] + (size_t)(tp.bb[t] ? 0 : ct) * 2 * LB + off;
+    const double a0 = u2d(ld_once(A)), a1 = u2d(ld_once(A + LA));
+    const double b0 = u2d(tp.bb[t] ? B[0] : ld_once(B)), b1 = u2d(tp.bb[t] ? B[LB] : ld_once(B + LB));
     v0 = red(v0 + mul_lazy(a0, b0, q, qinv), q, qinv);
     v1 = red(v1 + mul_lazy(a0, b1, q, qinv) + mul_lazy(a1, b0, q, qinv), q, qinv);
     v2 = red(v2 + mul_lazy(a1, b1, q, qinv), q, qinv);
@@ -405,12 +409,16 @@ __global__ void k_lincomb_multi(lk::LinMulti m, int nt, int no, const double* __
   }
   __syncthreads();
   const double q = pc[i].q, qinv = pc[i].qinv;
-  const size_t off = (size_t)limb * N + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t pos = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t off = (size_t)limb * N + pos;
+  const int poly = limb / level;  // ciphertext * 2 + component
+  // term t's word: its polynomial stride is xs[t] limbs (at least the level; 0: the level)
+  auto xoff = [&](int t) { return ((size_t)poly * (m.xs[t] ? m.xs[t] : level) + i) * N + pos; };
   if constexpr (SPLIT) {
     double xh[T], xl[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      const uint64_t v = t < nt ? ld_once(m.x[t] + off) : 0;
+      const uint64_t v = t < nt ? ld_once(m.x[t] + xoff(t)) : 0;
       xh[t] = u2d(v >> 25);
       xl[t] = u2d(v & 0x1FFFFFFull);
     }
@@ -431,7 +439,7 @@ __global__ void k_lincomb_multi(lk::LinMulti m, int nt, int no, const double* __
   } else {
     double x[T];
 #pragma unroll
-    for (int t = 0; t < T; ++t) x[t] = t < nt ? u2d(ld_once(m.x[t] + off)) : 0.0;
+    for (int t = 0; t < T; ++t) x[t] = t < nt ? u2d(ld_once(m.x[t] + xoff(t))) : 0.0;
     for (int o = 0; o < no; ++o) {
       double acc = 0.0;
 #pragma unroll
@@ -628,9 +636,10 @@ void add_const(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, c
                      c->N, t, c->d_prime);
 }
 
-void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, uint64_t* d2, int n, int level, bool bb) {
+void tensor(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* d, uint64_t* d2, int n, int level, bool bb,
+            int sa, int sb) {
   hipLaunchKernelGGL(k_tensor, grid_for(c->N, n * level), dim3(block_for(c->N)), 0, c->stream, a, b, d, d2, level,
-                     c->N, bb ? 1 : 0, c->d_prime);
+                     c->N, bb ? 1 : 0, sa ? sa : level, sb ? sb : level, c->d_prime);
 }
 
 void tensor_sum(bgv_ctx* c, const TensorPairs& tp, int np, uint64_t* d, uint64_t* d2, int n, int level, bool acc) {

@@ -185,7 +185,7 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   const int n = a.n, lv = a.level, N = c->N;
   if (lv < 2) throw OpError{BGV_E_LEVEL};
   Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
-  lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1);
+  lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1, lstride(a), lstride(b));
   relin_ms(c, keys, D, X, n, lv, a.t_exp, out);
 }
 
@@ -217,6 +217,8 @@ static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector
       if (a->v.n == 1 && n > 1) std::swap(a, b);
       tp.a[t] = a->v.d;
       tp.b[t] = b->v.d;
+      tp.sa[t] = lstride(a->v);
+      tp.sb[t] = lstride(b->v);
       tp.bb[t] = b->v.n == 1 && n > 1;
       keep.push_back(a);
       keep.push_back(b);
@@ -541,15 +543,28 @@ static CipherP with_t(const CipherP& x, int t_exp) {
 // modulus, and the primes are 1 mod t, so the message is unchanged).  The noise
 // keeps its size, which equals what a rescaling switch leaves for a ciphertext whose
 // noise is already at the floor of the last switch: a power that is itself a product.
+// The result is a view of x's lower limbs (no copy, polynomial stride x's); only the
+// tensor kernels and the inner sums read views, and ev_materialize copies one.
 static CipherP ev_drop(bgv_ctx* c, const CipherP& x, int level) {
   if (x->v.level == level) return x;
   if (level > x->v.level || level < 1) throw OpError{BGV_E_LEVEL};
-  CipherP r = new_cipher(c, x->v.n, level, x->v.t_exp);
+  (void)c;
+  auto r = std::make_shared<Cipher>();
+  r->buf = x->buf;
+  r->v = x->v;
+  r->v.level = level;
+  r->v.stride = lstride(x->v);
+  return r;
+}
+
+static CipherP ev_materialize(bgv_ctx* c, const CipherP& x) {
+  if (lstride(x->v) == x->v.level) return x;
+  CipherP r = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
   const size_t N = c->N;
   check_hip(c,
-            hipMemcpy2DAsync(r->v.d, (size_t)level * N * 8, x->v.d, (size_t)x->v.level * N * 8,
-                             (size_t)level * N * 8, (size_t)x->v.n * 2, hipMemcpyDeviceToDevice, c->stream),
-            "drop limbs");
+            hipMemcpy2DAsync(r->v.d, (size_t)x->v.level * N * 8, x->v.d, (size_t)lstride(x->v) * N * 8,
+                             (size_t)x->v.level * N * 8, (size_t)x->v.n * 2, hipMemcpyDeviceToDevice, c->stream),
+            "copy the kept limbs");
   return r;
 }
 
@@ -790,6 +805,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
       for (size_t t = 0; t < terms.size(); ++t) {
         keep.push_back(aligned_power(terms[t], lv));
         m.x[t] = keep.back()->v.d;
+        m.xs[t] = lstride(keep.back()->v);
       }
       for (size_t s0 = 0; s0 < js.size(); s0 += lk::LC_MAXO) {
         const int no = (int)std::min<size_t>(lk::LC_MAXO, js.size() - s0);
@@ -815,7 +831,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
       std::vector<const uint64_t*> xs;
       std::vector<int> rws;
       for (int i : used[j]) {
-        keep.push_back(aligned_power(i, lv));
+        keep.push_back(ev_materialize(c, aligned_power(i, lv)));  // the single-sum kernel reads no views
         xs.push_back(keep.back()->v.d);
         rws.push_back(j * kk + i);
       }

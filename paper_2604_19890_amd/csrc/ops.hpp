@@ -14,7 +14,11 @@ bool build_encoder(bgv_ctx* c);
 struct CtV {
   uint64_t* d = nullptr;
   int n = 0, level = 0, t_exp = 0;
+  // limbs per polynomial in memory when the batch is a view of the lower `level` limbs of a
+  // deeper one (0: level).  Only the tensor kernels and the inner sums read views.
+  int stride = 0;
 };
+inline int lstride(const CtV& v) { return v.stride ? v.stride : v.level; }
 
 // Device scratch from the context pool, returned on destruction.
 struct Scratch {
