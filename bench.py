@@ -363,7 +363,7 @@ def main():
                          "comparison equals the integer one on every row)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a design note only",
+        print(json.dumps({"error": "this benchmark runs on one GPU; sharding over several GPUs is a design note only",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

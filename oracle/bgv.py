@@ -8,7 +8,7 @@ q_0..q_{level-1}, together with the current plaintext-modulus exponent t_exp
 (t = p^t_exp; DivideByP lowers it by one, ChangeModToP sets it to 1, modulus
 raising sets it back to r -- Method, reduction and raising subsections).
 
-Readings of what the paper leaves open (each is also listed in the design doc):
+Readings of what the paper leaves open:
   * encryption is the symmetric Algorithm 1 with c1 uniform per prime and e from
     the seeded clipped Gaussian; every plaintext and constant is lifted to the
     centered range [-(t-1)/2, (t-1)/2] before it is reduced mod q_i;
