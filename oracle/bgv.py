@@ -20,7 +20,9 @@ Readings of what the paper leaves open:
     w = [u_P t^-1] in [0, p_k), converts it to the q-primes by the same formula and
     subtracts t*w before multiplying by P^-1;
   * modulus switching drops the top prime with w = centered([c_top t^-1]_{q_top}),
-    c_i <- (c_i - t w) q_top^-1; a multi-level drop is that step repeated.
+    c_i <- (c_i - t w) q_top^-1; a multi-level drop is that step repeated (align);
+    drop removes top limbs without rescaling, for operands whose noise is already
+    at the floor a switch leaves (the evaluator's powers in the fast schedule).
 """
 from __future__ import annotations
 
