@@ -32,3 +32,19 @@ def test_null_arguments_are_rejected_on_the_host():
     assert lib.bgv_ctx_create(None, None, None) == 1  # BGV_E_ARG
     assert lib.bgv_sync(None) == 1
     assert lib.bgv_ct_words(None, 3) == 0
+    assert lib.bgv_set_schedule(None, 0) == 1
+    assert lib.bgv_set_ntt_split(None, 8) == 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asked for more it exits with status 2 and says so on its
+    JSON line (before it touches the GPU)."""
+    import json
+    import subprocess
+    import sys
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]

@@ -123,3 +123,11 @@ def test_raw_ntt_and_autotune_limb_limit():
     lib.ntt(x, n_polys - 1, level)  # 65535 limbs: accepted (zeros stay zeros)
     torch.cuda.synchronize()
     assert int(x.abs().sum()) == 0
+
+
+def test_unknown_schedule_is_rejected():
+    c = pair_tiny17()
+    assert c.G._lib.bgv_set_schedule(c.lib.handle, 7) == 1  # BGV_E_ARG
+    with pytest.raises(KeyError):
+        c.lib.set_schedule("fastest")
+    c.lib.set_schedule("fast")
