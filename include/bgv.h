@@ -55,13 +55,13 @@ typedef enum {
   BGV_E_NOKEY = 5,       /* no Galois key for the requested rotation             */
   BGV_E_OOM = 6,         /* device or host allocation failed                     */
   BGV_E_DEVICE = 7,      /* a HIP runtime call failed                            */
-  BGV_E_UNSUPPORTED = 8  /* a case the library does not build (e.g. r >= 3)      */
+  BGV_E_UNSUPPORTED = 8  /* no G_{p,e} table for the ciphertext's exponent e     */
 } bgv_status;
 
 typedef struct {
   int32_t log_n; /* N = 2^log_n, 4 <= log_n <= 16                                 */
   int32_t p;     /* plaintext prime, p = 1 mod 4                                  */
-  int32_t r;     /* plaintext exponent, t = p^r (r = 2 is the built reduction)    */
+  int32_t r;     /* plaintext exponent, t = p^r: 1 <= r <= 4, p^r < 2^31          */
   int32_t L;     /* ciphertext primes                                             */
   int32_t K;     /* special primes for hybrid key switching; digit size alpha = K */
 } bgv_params;
@@ -291,6 +291,24 @@ int32_t bgv_get_ntt_chunk(const bgv_ctx* ctx);
  *   are identical for every split.  BGV_E_ARG for limbs above 65535.               */
 bgv_status bgv_set_ntt_split(bgv_ctx* ctx, int32_t first_pass_stages);
 bgv_status bgv_autotune_ntt(bgv_ctx* ctx, int32_t limbs, int32_t reps, int32_t* best_split, float* best_us);
+
+/* ---- launch statistics -----------------------------------------------------
+ * Host-side counters of the work a context has enqueued since its creation or the
+ * last bgv_reset_stats (they are updated when work is enqueued and never wait for
+ * the device).  A batch call counts once.  Tests use them to confirm which launch
+ * shapes a computation reached; they have no effect on results.                 */
+typedef struct {
+  int64_t key_switches;      /* relinearisations and rotations                             */
+  int64_t rescale_drops;     /* single-prime modulus switches (a switch by k primes adds k) */
+  int64_t limb_drops;        /* alignments that remove top limbs without rescaling         */
+  int64_t odd_splits;        /* polynomial evaluations that took the odd baby-step split    */
+  int32_t max_baby_k;        /* largest baby-step count k of an evaluated polynomial        */
+  int32_t max_inner_terms;   /* most baby powers read by one multi-output inner-sum launch  */
+  int32_t max_inner_outputs; /* most inner sums written by one such launch                  */
+  int32_t max_tensor_pairs;  /* most ciphertext pairs summed by one tensor-sum launch       */
+} bgv_stats;
+bgv_status bgv_get_stats(const bgv_ctx* ctx, bgv_stats* out);
+bgv_status bgv_reset_stats(bgv_ctx* ctx);
 
 /* ---- raw NTT access (the transform on its own, for tests and bandwidth runs)
  * bgv_ntt: in place on a DEVICE array holding n_polys polynomials of `level` limbs

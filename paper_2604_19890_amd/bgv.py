@@ -52,6 +52,12 @@ class _Info(ctypes.Structure):
                [("t", ctypes.c_int64), ("max_batch", ctypes.c_int32), ("_pad", ctypes.c_int32)]
 
 
+class _Stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("key_switches", "rescale_drops", "limb_drops", "odd_splits")] + \
+               [(f, ctypes.c_int32) for f in ("max_baby_k", "max_inner_terms", "max_inner_outputs",
+                                              "max_tensor_pairs")]
+
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -103,6 +109,8 @@ _sigs = {
     "bgv_graph_launch": [_vp, _vp],
     "bgv_graph_destroy": [_vp],
     "bgv_get_ntt_chunk": [_vp],
+    "bgv_get_stats": [_vp, _P(_Stats)],
+    "bgv_reset_stats": [_vp],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -249,6 +257,15 @@ class Context:
         h = ctypes.c_void_p()
         self._check(_lib.bgv_capture_end(self.handle, ctypes.byref(h)))
         return Graph(self, h)
+
+    def stats(self) -> dict:
+        """Host-side counters of the enqueued work (see bgv_get_stats)."""
+        st = _Stats()
+        self._check(_lib.bgv_get_stats(self.handle, ctypes.byref(st)))
+        return {f: int(getattr(st, f)) for f, _ in _Stats._fields_}
+
+    def reset_stats(self):
+        self._check(_lib.bgv_reset_stats(self.handle))
 
     def trim(self) -> int:
         """Free the library's cached scratch; returns the bytes still in use."""

@@ -620,3 +620,22 @@ BGV_EXPORT bgv_status bgv_autotune_ntt(bgv_ctx* c, int32_t limbs, int32_t reps, 
     return BGV_OK;
   });
 }
+
+BGV_EXPORT bgv_status bgv_get_stats(const bgv_ctx* c, bgv_stats* o) {
+  if (!c || !o) return BGV_E_ARG;
+  o->key_switches = c->stats.key_switches;
+  o->rescale_drops = c->stats.rescale_drops;
+  o->limb_drops = c->stats.limb_drops;
+  o->odd_splits = c->stats.odd_splits;
+  o->max_baby_k = c->stats.max_baby_k;
+  o->max_inner_terms = c->stats.max_inner_terms;
+  o->max_inner_outputs = c->stats.max_inner_outputs;
+  o->max_tensor_pairs = c->stats.max_tensor_pairs;
+  return BGV_OK;
+}
+
+BGV_EXPORT bgv_status bgv_reset_stats(bgv_ctx* c) {
+  NEED_CTX(c);
+  c->stats = Stats{};
+  return BGV_OK;
+}

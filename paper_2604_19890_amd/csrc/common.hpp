@@ -1,21 +1,12 @@
-// Shared device-side definitions of the gfx950 kernels.
-//
-// Residues are stored in HBM as uint64 in [0, q) with q < 2^50.  Inside the
-// kernels they are carried as IEEE binary64 values, because on CDNA4 the fp64
-// FMA issues at the full VALU rate while a 64x64-bit integer product has to be
-// assembled from quarter-rate 32-bit multiplies.  A modular product is a Barrett
-// reduction whose quotient estimate is taken in floating point and whose
-// remainder is computed exactly with FMAs:
-//     h = a*b (rounded), l = fma(a, b, -h) (exact: a*b = h + l),
-//     k = rint(h * (1/q)),  r = fma(-k, q, h) + l.
-// For |a|, |b| <= q < 2^50 the estimate k is within 0.875 of a*b/q, so the
-// exact integer r = a*b - k q satisfies |r| < q and every intermediate fits the
-// 53-bit significand.  Values between stages are kept signed in (-q, q) and
-// brought to [0, q) only when written back.  All kernels must be compiled with
-// -ffp-contract=off so that the compiler neither fuses nor reorders these steps.
+// Shared device-side definitions of the gfx950 kernels: per-prime constants, the limb
+// maps of batched launches and cache hints.  The modular arithmetic itself (residues
+// below 2^50 as binary64, Barrett products with an exact FMA remainder) is in
+// modarith.hpp.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "modarith.hpp"
 
 struct PrimeD {
   double q;     // the prime as a double (exact)
@@ -76,31 +67,3 @@ __device__ __forceinline__ bool limb_skipped(const LimbMap& lm, int l) {
 // the non-temporal hint keeps it from displacing data that is reused from the caches.
 __device__ __forceinline__ uint64_t ld_once(const uint64_t* p) { return __builtin_nontemporal_load(p); }
 
-// exact conversions for integers in [0, 2^52)
-__device__ __forceinline__ double u2d(uint64_t x) {
-  return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 4503599627370496.0;
-}
-__device__ __forceinline__ uint64_t d2u(double v) {
-  return (uint64_t)__double_as_longlong(v + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
-}
-
-// a*b mod q as a signed value with |r| < q; requires |a|, |b| <= q.
-__device__ __forceinline__ double mul_lazy(double a, double b, double q, double qinv) {
-  double h = a * b;
-  double l = __builtin_fma(a, b, -h);
-  double k = __builtin_rint(h * qinv);
-  return __builtin_fma(-k, q, h) + l;
-}
-
-// x mod q as a signed value with |r| <= q/2 + 1; requires |x| < 2^52.
-__device__ __forceinline__ double red(double x, double q, double qinv) {
-  return __builtin_fma(-__builtin_rint(x * qinv), q, x);
-}
-
-// [0, q) representative of a signed value with |x| < q.
-__device__ __forceinline__ double canon(double x, double q) { return x < 0.0 ? x + q : x; }
-
-// canonical residue of a signed value with |x| < 2^52
-__device__ __forceinline__ uint64_t to_u(double x, double q, double qinv) {
-  return d2u(canon(red(x, q, qinv), q));
-}

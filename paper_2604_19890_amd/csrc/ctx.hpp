@@ -24,6 +24,18 @@ struct DevPool {
   void release();
 };
 
+// Host-side counters of what a context has enqueued (bgv_get_stats).
+struct Stats {
+  int64_t key_switches = 0;   // relinearisations and rotations, one per batch call
+  int64_t rescale_drops = 0;  // single-prime modulus switches (k primes at once count k)
+  int64_t limb_drops = 0;     // alignments by removing top limbs without rescaling
+  int64_t odd_splits = 0;     // polynomial evaluations in the odd baby-step split
+  int32_t max_baby_k = 0;
+  int32_t max_inner_terms = 0;
+  int32_t max_inner_outputs = 0;
+  int32_t max_tensor_pairs = 0;
+};
+
 struct bgv_ctx {
   bgv_params prm;
   int N = 0, logN = 0, ell = 0, dslot = 0, alpha = 0, dnum = 0, Ltot = 0;
@@ -41,6 +53,7 @@ struct bgv_ctx {
   hipStream_t cap_stream = nullptr;    // capture happens here (default priority, non-blocking)
   hipStream_t saved_stream = nullptr;  // the context stream while capturing
   DevPool pool;
+  Stats stats;
 
   // device tables
   PrimeD* d_prime = nullptr;  // [Ltot]

@@ -419,8 +419,8 @@ __global__ void k_lincomb_multi(lk::LinMulti m, int nt, int no, const double* __
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const uint64_t v = t < nt ? ld_once(m.x[t] + xoff(t)) : 0;
-      xh[t] = u2d(v >> 25);
-      xl[t] = u2d(v & 0x1FFFFFFull);
+      xh[t] = split_hi(v);
+      xl[t] = split_lo(v);
     }
     for (int o = 0; o < no; ++o) {
       double hi = 0.0, lo = 0.0;
@@ -432,7 +432,7 @@ __global__ void k_lincomb_multi(lk::LinMulti m, int nt, int no, const double* __
           lo = __builtin_fma(c, xl[t], lo);
         }
       }
-      double acc = mul_lazy(red(hi, q, qinv), 33554432.0, q, qinv) + red(lo, q, qinv);
+      double acc = split_combine(hi, lo, q, qinv);
       if (comp == 0 && m.cst_row[o] >= 0) acc += sc[(size_t)m.cst_row[o] * sc_stride + i];
       __builtin_nontemporal_store(to_u(acc, q, qinv), m.out[o] + off);
     }

@@ -28,6 +28,7 @@
 // value below 4 q and every multiplicand below 8 q.  Each step ends with one
 // reduction of its 16 values.
 #include "ctx.hpp"
+#include "ntt_stages.hpp"
 
 namespace {
 
@@ -54,52 +55,6 @@ __device__ __forceinline__ void pass_sync(bool wave_local) {
     wave_lds_sync();
   else
     __syncthreads();
-}
-
-// Cooley-Tukey stages at register distances DMAX, DMAX/2, .., 1 on 16 registers
-// holding global indices g0 + i * 2^gs_log.  The butterflies of group g at
-// distance dd share twiddle number ((N + g0) >> log2(2 dd 2^gs_log)) + g.
-template <int DMAX>
-__device__ __forceinline__ void ct_stages(double* v, const double* __restrict__ w, int N, int g0, int gs_log,
-                                          double q, double qinv) {
-#pragma unroll
-  for (int dd = DMAX; dd >= 1; dd >>= 1) {
-    const double* wp = w + ((N + g0) >> (__builtin_ctz(2 * dd) + gs_log));
-#pragma unroll
-    for (int g = 0; g < 16 / (2 * dd); ++g) {
-      const double wt = wp[g];
-#pragma unroll
-      for (int i = g * 2 * dd; i < g * 2 * dd + dd; ++i) {
-        const double r = mul_lazy(v[i + dd], wt, q, qinv);
-        const double a = v[i];
-        v[i] = a + r;
-        v[i + dd] = a - r;
-      }
-    }
-  }
-}
-
-// Gentleman-Sande stages at register distances 1, 2, .., DMAX.
-template <int DMAX>
-__device__ __forceinline__ void gs_stages(double* v, const double* __restrict__ w, int N, int g0, int gs_log,
-                                          double q, double qinv) {
-  int stage = 0;
-#pragma unroll
-  for (int dd = 1; dd <= DMAX; dd <<= 1) {
-    ++stage;
-    const double* wp = w + ((N + g0) >> (__builtin_ctz(2 * dd) + gs_log));
-#pragma unroll
-    for (int g = 0; g < 16 / (2 * dd); ++g) {
-      const double wt = wp[g];
-#pragma unroll
-      for (int i = g * 2 * dd; i < g * 2 * dd + dd; ++i) {
-        const double a = v[i], b = v[i + dd];
-        const double s = a + b;
-        v[i] = (stage & 1) ? s : red(s, q, qinv);
-        v[i + dd] = mul_lazy(a - b, wt, q, qinv);
-      }
-    }
-  }
 }
 
 // One pass over data; the pass reads from src (data itself when src is null,

@@ -100,6 +100,7 @@ void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out) {
 static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const Scratch& X, int n, int level) {
   const int N = c->N, K = c->prm.K, L = c->prm.L, A = c->alpha;
   const int dn = (level + A - 1) / A, rows = level + K;
+  c->stats.key_switches += 1;
   Scratch Y(c, (size_t)n * dn * rows * N);
   Scratch Xc(c, (size_t)n * level * N);
   const bool fused = lk::ntt_fused_inner_ok(c);
@@ -223,6 +224,7 @@ static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector
       keep.push_back(a);
       keep.push_back(b);
     }
+    c->stats.max_tensor_pairs = std::max(c->stats.max_tensor_pairs, np);
     lk::tensor_sum(c, tp, np, D.d, X.d, n, lv, s0 > 0);
   }
   CipherP r = new_cipher(c, n, lv - 1, t_exp);
@@ -259,6 +261,7 @@ void op_rotate(bgv_ctx* c, const bgv_keys* keys, const CtV& in, int g, const CtV
 void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out) {
   const int n = in.n, lv = in.level, N = c->N;
   if (lv < 2) throw OpError{BGV_E_LEVEL};
+  c->stats.rescale_drops += 1;
   Scratch T(c, (size_t)n * 2 * N);
   check_hip(c,
             hipMemcpy2DAsync(T.d, (size_t)N * 8, in.d + (size_t)(lv - 1) * N, (size_t)lv * N * 8, (size_t)N * 8,
@@ -293,6 +296,7 @@ void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out) {
     op_mod_switch(c, in, out);
     return;
   }
+  c->stats.rescale_drops += lv - to;
   // At most 16 drops per step.  A step brings only the dropped limbs to coefficient
   // form, forms the combined correction e for the kept ones, and finishes in the epilogue
   // of e's forward NTT: out_i = (c_i - e_i) prod q_dropped^-1 with c in evaluation form.
@@ -548,7 +552,7 @@ static CipherP with_t(const CipherP& x, int t_exp) {
 static CipherP ev_drop(bgv_ctx* c, const CipherP& x, int level) {
   if (x->v.level == level) return x;
   if (level > x->v.level || level < 1) throw OpError{BGV_E_LEVEL};
-  (void)c;
+  c->stats.limb_drops += 1;
   auto r = std::make_shared<Cipher>();
   r->buf = x->buf;
   r->v = x->v;
@@ -712,6 +716,8 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   while ((odd ? 1 : 2) * kk * kk < D + 1) kk *= 2;
   const int g = (D + kk) / kk;
   auto coef = [&](int n) -> int64_t { return n <= D ? cf[n] : 0; };
+  c->stats.max_baby_k = std::max(c->stats.max_baby_k, kk);
+  if (odd) c->stats.odd_splits += 1;
 
   const double* tab = coeff_table(c, x->v.t_exp, cf);
   // the centered coefficients follow the residue rows; they serve the exact split
@@ -818,6 +824,8 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
           m.cst_row[o] = coef(j * kk) != 0 ? j * kk : -1;
           inner[j] = Inner{false, 0, acc};
         }
+        c->stats.max_inner_terms = std::max(c->stats.max_inner_terms, (int)terms.size());
+        c->stats.max_inner_outputs = std::max(c->stats.max_inner_outputs, no);
         lk::lincomb_multi(c, m, (int)terms.size(), no, tab, c->prm.L, scs, x->v.n, lv);
       }
       continue;

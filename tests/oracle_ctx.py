@@ -64,3 +64,10 @@ def tiny17():
 def hybrid17():
     """Digits of two primes (alpha = K = 2) to exercise multi-prime base conversion."""
     return Ctx(5, 17, 2, 7, 2, steps=(1,), conj=True)
+
+
+@functools.lru_cache(maxsize=None)
+def p257():
+    """The benchmark's plaintext modulus 257^2 with its chain (30 + 6 primes) on the smallest
+    ring that holds all 128 slots (N = 2^8, two coefficients per slot)."""
+    return Ctx(8, 257, 2, 30, 6)

@@ -8,7 +8,7 @@ import pytest
 from oracle import bgv as B
 from oracle import polys
 from oracle import space as S
-from tests.oracle_ctx import tiny5, tiny5_r3, tiny5_r4, tiny17, tiny37_r4
+from tests.oracle_ctx import p257, tiny5, tiny5_r3, tiny5_r4, tiny17, tiny37_r4
 
 
 def _balanced_digits(v, p):
@@ -337,3 +337,41 @@ def test_basic_schedule_space_switching_brute_force():
     finally:
         P.schedule = "fast"
     assert got == [1 if v > (t - 1) // 2 else 0 for v in vals]
+
+
+def _p257_edges(t, p):
+    h, d = (t - 1) // 2, (p - 1) // 2
+    v = [0, 1, t - 1, 2, t - 2, h, h + 1, h - 1, h + 2, d, t - d, d + 1, t - d - 1, p, t - p, p - 1, p + 1,
+         d * p, t - d * p, d * p + d, d * p - d, (d + 1) * p, d * p + d + 1, (d - 1) * p - d]
+    return [x % t for x in v]
+
+
+@pytest.mark.parametrize("sched", ["fast", "basic"])
+def test_space_switching_at_p257_encrypted(sched):
+    """The benchmark's modulus 257^2 (30 + 6 primes, N = 2^8): one ciphertext whose 128 slots
+    hold the edges of the method (0, +-1, +-(t-1)/2, digits at +-(p-1)/2, carries between the
+    digits) and random values.  The decrypted digits are the balanced base-p digits (Lemma 3),
+    LT is [centered value < 0], EQ is [value = 0], and the raise is the 0/1 lift (plain
+    definitions, not the circuit)."""
+    c = p257()
+    P, t, p = c.P, c.P.t_full, c.P.p
+    vals = _p257_edges(t, p)
+    vals += [int(x) for x in np.random.default_rng(257).integers(0, t, size=P.ell - len(vals))]
+    P.schedule = sched
+    try:
+        dg = S.space_reduce(P, c.keys, c.enc(vals))
+        lt = S.compare(P, c.keys, dg, "lt")
+        eq = S.compare(P, c.keys, dg, "eq")
+        rs = S.space_raise(P, c.keys, lt)
+    finally:
+        P.schedule = "fast"
+    assert [d.t_exp for d in dg] == [1, 1] and rs.t_exp == 2
+    got0, got1 = c.dec(dg[0]), c.dec(dg[1])
+    want = [_balanced_digits(v, p) for v in vals]
+    assert got0 == [z0 % p for z0, _ in want]
+    assert got1 == [z1 % p for _, z1 in want]
+    assert all(z0 + p * z1 == _centered(v, t) for v, (z0, z1) in zip(vals, want))
+    lt_want = [1 if _centered(v, t) < 0 else 0 for v in vals]
+    assert c.dec(lt) == lt_want
+    assert c.dec(eq) == [1 if v == 0 else 0 for v in vals]
+    assert c.dec(rs) == lt_want
