@@ -292,6 +292,21 @@ int32_t bgv_get_ntt_chunk(const bgv_ctx* ctx);
 bgv_status bgv_set_ntt_split(bgv_ctx* ctx, int32_t first_pass_stages);
 bgv_status bgv_autotune_ntt(bgv_ctx* ctx, int32_t limbs, int32_t reps, int32_t* best_split, float* best_us);
 
+/* ---- allocation-free variant ------------------------------------------------
+ * For callers that cannot allocate device memory during a call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).
+ * bgv_mod_switch_noalloc: the same result as bgv_mod_switch (bit for bit), but every
+ *   temporary lives in a scratch array of BGV_NOALLOC_SCRATCH_WORDS uint64 words (32 MiB)
+ *   that the library holds on each GPU it runs on until the process ends; the call performs
+ *   no device allocation or free.  The caller passes the input and the output (out may
+ *   alias in).  The switch of n ciphertexts at level l needs 2 n l N words of scratch; a
+ *   larger call returns BGV_E_ARG before anything is enqueued.  All calls on one GPU share
+ *   the array (contexts and streams included): calls whose execution overlaps on one GPU
+ *   race on it, so callers serialise them (one stream, or events between streams).
+ *   BGV_E_DEVICE if the array's address could not be resolved on this device.          */
+#define BGV_NOALLOC_SCRATCH_WORDS (4 * 1024 * 1024)
+bgv_status bgv_mod_switch_noalloc(bgv_ctx* ctx, const bgv_ct* in, bgv_ct* out);
+
 /* ---- launch statistics -----------------------------------------------------
  * Host-side counters of the work a context has enqueued since its creation or the
  * last bgv_reset_stats (they are updated when work is enqueued and never wait for

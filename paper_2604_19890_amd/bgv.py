@@ -20,6 +20,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 ROW_SWAP = -1
+NOALLOC_SCRATCH_WORDS = 4 * 1024 * 1024  # BGV_NOALLOC_SCRATCH_WORDS
 OP_LT = 0
 OP_EQ = 1
 OP_GT = 2
@@ -110,6 +111,7 @@ _sigs = {
     "bgv_graph_destroy": [_vp],
     "bgv_get_ntt_chunk": [_vp],
     "bgv_get_stats": [_vp, _P(_Stats)],
+    "bgv_mod_switch_noalloc": [_vp, _P(_Ct), _P(_Ct)],
     "bgv_reset_stats": [_vp],
 }
 for _name, _args in _sigs.items():
@@ -362,6 +364,14 @@ class Context:
 
     def mod_switch(self, a, out=None):
         return self._un(_lib.bgv_mod_switch, a, out=out, level=a.level - 1)
+
+    def mod_switch_noalloc(self, a, out):
+        """bgv_mod_switch_noalloc: the single switch with the library's fixed scratch (no device
+        allocation in the call); the caller provides the output batch."""
+        sa, so = a._struct(), out._struct()
+        self._check(_lib.bgv_mod_switch_noalloc(self.handle, ctypes.byref(sa), ctypes.byref(so)))
+        out._update(so)
+        return out
 
     def mod_switch_to(self, a, level: int, out=None):
         return self._un(_lib.bgv_mod_switch_to, a, ctypes.c_int32(level), out=out, level=level)

@@ -313,6 +313,22 @@ BGV_EXPORT bgv_status bgv_mod_switch(bgv_ctx* c, const bgv_ct* in, bgv_ct* out) 
   return unary(c, in, out, in->level - 1, in->t_exp, [&](const CtV& x, const CtV& o) { op_mod_switch(c, x, o); });
 }
 
+BGV_EXPORT bgv_status bgv_mod_switch_noalloc(bgv_ctx* c, const bgv_ct* in, bgv_ct* out) {
+  NEED_CTX(c);
+  CHECK(check_in(c, in, "null input"));
+  if (in->level < 2) return fail(c, BGV_E_LEVEL, "no prime left to drop");
+  if (!c->noalloc_scratch) return fail(c, BGV_E_DEVICE, "the allocation-free scratch is not available on this device");
+  // T [n][2][N] and W [n][2][level-1][N]
+  const int64_t t_words = (int64_t)in->n * 2 * c->N;
+  const int64_t need = t_words + (int64_t)in->n * 2 * (in->level - 1) * c->N;
+  if (need > BGV_NOALLOC_SCRATCH_WORDS)
+    return fail(c, BGV_E_ARG, "the switch needs more scratch than the allocation-free variant holds");
+  uint64_t* T = c->noalloc_scratch;
+  uint64_t* W = T + t_words;
+  return unary(c, in, out, in->level - 1, in->t_exp,
+               [&](const CtV& x, const CtV& o) { op_mod_switch_with(c, x, o, T, W); });
+}
+
 BGV_EXPORT bgv_status bgv_mod_switch_to(bgv_ctx* c, const bgv_ct* in, int32_t level, bgv_ct* out) {
   NEED_CTX(c);
   CHECK(check_in(c, in, "null input"));

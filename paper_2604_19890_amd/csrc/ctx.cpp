@@ -424,6 +424,8 @@ bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream) {
       !upload(c, &c->d_mswpi, mswpi) || !upload(c, &c->d_tconst, tc) || !upload(c, &c->d_mdfold, mdfold))
     return BGV_E_DEVICE;
   if (!build_encoder(c)) { c->err = "slot encoder construction failed"; return BGV_E_PARAM; }
+  // the allocation-free variant's scratch on this device (looked up once per device)
+  c->noalloc_scratch = noalloc_scratch_ptr(&c->device);
   return BGV_OK;
 }
 

@@ -54,6 +54,10 @@ struct bgv_ctx {
   hipStream_t saved_stream = nullptr;  // the context stream while capturing
   DevPool pool;
   Stats stats;
+  // device address of the allocation-free variant's scratch on this context's device
+  // (looked up once per device at context creation; null if the lookup failed)
+  uint64_t* noalloc_scratch = nullptr;
+  int device = -1;
 
   // device tables
   PrimeD* d_prime = nullptr;  // [Ltot]
@@ -231,3 +235,8 @@ void key_combine(bgv_ctx* c, const uint64_t* A, const uint64_t* S, const uint64_
 }  // namespace lk
 
 bool hip_ok(bgv_ctx* c, hipError_t e, const char* what);
+
+// The allocation-free variant's scratch: the device address of a file-scope device array of
+// BGV_NOALLOC_SCRATCH_WORDS words on the current device, looked up once per device and kept
+// (kernels.hip).  Returns null if the runtime cannot resolve it.
+uint64_t* noalloc_scratch_ptr(int* device);

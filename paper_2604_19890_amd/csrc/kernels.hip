@@ -4,6 +4,8 @@
 // component uses prime q_i.  Evaluation-form kernels work word by word; the
 // base-conversion kernels (ModUp, ModDown, modulus switching) work on
 // coefficient-form limbs produced by the INTT, one coefficient per thread.
+#include <mutex>
+
 #include "ctx.hpp"
 
 namespace {
@@ -777,3 +779,28 @@ void key_combine(bgv_ctx* c, const uint64_t* A, const uint64_t* S, const uint64_
 }
 
 }  // namespace lk
+
+// ------------------------------------------------------------------ allocation-free scratch
+namespace {
+// Scratch of the allocation-free entry points: BGV_NOALLOC_SCRATCH_WORDS words on every GPU
+// the library runs on, held by the loaded code object until the process ends and shared by
+// every call on that GPU.  In host code this name is only a host-side stand-in: the device
+// address comes from hipGetSymbolAddress, once per device, and only that address is used.
+__device__ __align__(256) uint64_t scratch[BGV_NOALLOC_SCRATCH_WORDS];
+std::mutex g_scratch_mu;
+constexpr int MAX_DEVICES = 64;
+uint64_t* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+uint64_t* noalloc_scratch_ptr(int* device) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  if (device) *device = dev;
+  std::lock_guard<std::mutex> guard(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = (uint64_t*)p;
+  }
+  return g_scratch_ptr[dev];
+}

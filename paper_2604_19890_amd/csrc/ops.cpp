@@ -258,18 +258,19 @@ void op_rotate(bgv_ctx* c, const bgv_keys* keys, const CtV& in, int g, const CtV
   key_switch(c, it->second, X, n, lv, in.t_exp, R.d, (int64_t)lv * N, 1, out.d);
 }
 
-void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out) {
+// Single modulus switch with caller-provided scratch: T [n][2][N] receives the top limbs
+// (coefficient form), W [n][2][level-1][N] the correction w and, for an in-place call, the
+// result before it is copied back.  Every word of T and W is written before it is read.
+void op_mod_switch_with(bgv_ctx* c, const CtV& in, const CtV& out, uint64_t* T, uint64_t* W) {
   const int n = in.n, lv = in.level, N = c->N;
   if (lv < 2) throw OpError{BGV_E_LEVEL};
   c->stats.rescale_drops += 1;
-  Scratch T(c, (size_t)n * 2 * N);
   check_hip(c,
-            hipMemcpy2DAsync(T.d, (size_t)N * 8, in.d + (size_t)(lv - 1) * N, (size_t)lv * N * 8, (size_t)N * 8,
+            hipMemcpy2DAsync(T, (size_t)N * 8, in.d + (size_t)(lv - 1) * N, (size_t)lv * N * 8, (size_t)N * 8,
                              (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
             "gather top");
-  lk::ntt(c, T.d, n * 2, LimbMap{1, 1, c->prm.L, 0, 1, lv - 1, 0}, true);
-  Scratch W(c, (size_t)n * 2 * (lv - 1) * N);
-  lk::msw_w(c, T.d, W.d, n, lv, in.t_exp);
+  lk::ntt(c, T, n * 2, LimbMap{1, 1, c->prm.L, 0, 1, lv - 1, 0}, true);
+  lk::msw_w(c, T, W, n, lv, in.t_exp);
   // forward NTT of w with the final step in its last pass:
   // out_i = (x_i - t w_i) q_top^-1 for i < level-1
   lk::NttEpi ep{};
@@ -277,12 +278,20 @@ void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out) {
   ep.a_cc = (int64_t)lv * N;
   ep.sv = c->d_tconst + ((size_t)2 * in.t_exp + 1) * c->Ltot;  // t mod q_i
   ep.qt = c->d_msw + (size_t)(lv - 1) * c->prm.L;              // q_top^-1 mod q_i
-  ep.out = out.d == in.d ? W.d : out.d;  // in place: the result goes through w
+  ep.out = out.d == in.d ? W : out.d;  // in place: the result goes through w
   ep.rows = lv - 1;
-  lk::ntt(c, W.d, n * 2 * (lv - 1), lm_chain(c, lv - 1), false, nullptr, &ep);
+  lk::ntt(c, W, n * 2 * (lv - 1), lm_chain(c, lv - 1), false, nullptr, &ep);
   if (out.d == in.d)
-    check_hip(c, hipMemcpyAsync(out.d, W.d, (size_t)n * 2 * (lv - 1) * N * 8, hipMemcpyDeviceToDevice, c->stream),
+    check_hip(c, hipMemcpyAsync(out.d, W, (size_t)n * 2 * (lv - 1) * N * 8, hipMemcpyDeviceToDevice, c->stream),
               "copy");
+}
+
+void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out) {
+  const int n = in.n, lv = in.level, N = c->N;
+  if (lv < 2) throw OpError{BGV_E_LEVEL};
+  Scratch T(c, (size_t)n * 2 * N);
+  Scratch W(c, (size_t)n * 2 * (lv - 1) * N);
+  op_mod_switch_with(c, in, out, T.d, W.d);
 }
 
 void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out) {

@@ -58,6 +58,8 @@ void op_mul_relin(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, 
 void op_rotate(bgv_ctx* c, const bgv_keys* keys, const CtV& in, int g, const CtV& out);
 void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out);  // product + one switch
 void op_mod_switch(bgv_ctx* c, const CtV& in, const CtV& out);         // one prime
+// the same with caller-provided scratch T [n][2][N] and W [n][2][level-1][N] (no allocation)
+void op_mod_switch_with(bgv_ctx* c, const CtV& in, const CtV& out, uint64_t* T, uint64_t* W);
 void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out);  // repeated
 void op_copy(bgv_ctx* c, const CtV& in, const CtV& out);
 int galois_elt(const bgv_ctx* c, int step);
