@@ -9,16 +9,26 @@ b*c product, the masked product, the batch sum and rotate-and-sum, with every
 input already resident in HBM.  value = rows per second of the batched form.
 
 Also reported on the same line:
-  plain      -- the same query with one ciphertext per call (every launch covers one ciphertext)
-  ntt        -- forward NTT GB/s on the query's ciphertext shape (16 N bytes per limb)
-  roofline   -- the NTT passes (the most frequent kernels) against the 8 TB/s HBM peak
-  cpu_baseline -- the CPU oracle on a bounded sample (one product at N = 2^16), scaled
-                  to rows/s by the query's count of schoolbook limb products.
+  plain         -- the same query with one ciphertext per call (every launch covers one ciphertext)
+  roofline      -- the forward NTT (the most frequent kernel) against the 8 TB/s HBM peak
+  ks_roofline   -- the product step (tensor, relinearisation by hybrid key switching, one
+                   modulus switch) at the query's top level, against the same peak
+  step_roofline -- the whole query step: the algorithmic bytes of every step the library
+                   enqueued (its own accounting), over the step time
+  sql_exact     -- the query on 15-bit filter columns, where the circuit's comparison equals the
+                   integer one on every row
+  primitives    -- the primitive batch (N = 2^15, 16 + 4 primes, 64 ciphertexts): NTT/INTT,
+                   mul_relin, rotate, mod_switch, batched against one ciphertext per call
+  relu          -- ReLU over int8 activations at N = 2^16 (a bounded sample), batched and plain
+  served        -- a bounded serving mix: p50/p99 latency and rows/s, batched against plain
+  cpu_baseline  -- the CPU oracle on a bounded sample (one product at N = 2^16), scaled
+                   to rows/s by the query's count of schoolbook limb products.
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -38,6 +48,7 @@ HBM_PEAK_GBS = 8000.0
 # NTT sources they were taken on (hash below) and are reported only while those are unchanged.
 NTT_COUNTERS = {
     "sources_sha256": "49663687e55e64cff561abe8304328f19f325ee18438e09bfb8417e8aa6b8316",
+    "sources": ("ntt.hip", "common.hpp"),
     "limbs": 960,
     "fetch_kib": [246089, 253498],
     "write_kib": [491520, 491520],
@@ -45,27 +56,72 @@ NTT_COUNTERS = {
     "write_scale": 1.0,
 }
 
+# HBM traffic of the product step (32 ciphertext pairs at level 30) summed over its kernels, from
+# the same two counter runs of `bench.py --ks-only` (profiles/product_step_n65536_b32.md); null
+# until taken on the current sources.
+KS_COUNTERS = None
 
-def ntt_sources_sha256():
+
+def sources_sha256(names):
     h = hashlib.sha256()
-    for name in ("ntt.hip", "common.hpp"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2604_19890_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def ntt_traffic_bytes(limbs):
-    """Counter-measured HBM bytes of one forward NTT over `limbs` limbs, or None when the NTT
-    sources differ from the ones the counters were read on."""
-    c = NTT_COUNTERS
-    if ntt_sources_sha256() != c["sources_sha256"]:
+def counter_bytes(c, units):
+    """Counter-measured HBM bytes for `units` of the counted workload, or None when the sources
+    differ from the ones the counters were read on."""
+    if c is None or sources_sha256(c["sources"]) != c["sources_sha256"]:
         return None
-    per_transform = 1024 * (sum(c["fetch_kib"]) * c["fetch_scale"] + sum(c["write_kib"]) * c["write_scale"])
-    return per_transform * limbs / c["limbs"]
+    per = 1024 * (sum(c["fetch_kib"]) * c["fetch_scale"] + sum(c["write_kib"]) * c["write_scale"])
+    return per * units / c["limbs"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_calls(fn, reps, warm=1):
+    """Seconds per call of fn() between HIP events on the current stream (the stream every
+    library call of the benchmark is enqueued on), after `warm` untimed calls."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a, b = events()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / 1e3 / reps
+
+
+def encrypt_rows(ctx, s, rows, wl, base, seed):
+    from paper_2604_19890_amd import synth
+    rows = np.asarray(rows, dtype=np.uint64).reshape(-1, ctx.slots)
+    c1 = np.empty((len(rows), ctx.L, ctx.N), dtype=np.uint64)
+    e = np.empty((len(rows), ctx.N), dtype=np.int32)
+    for i in range(len(rows)):
+        c1[i], e[i] = synth.encryption_randomness(ctx.primes[:ctx.L], ctx.N, seed, wl, base + i)
+    return ctx.encrypt(s, rows, c1, e)
+
+
+def make_keys(ctx, s, wl, seed, steps, conj):
+    from paper_2604_19890_amd import synth
+    n_keys = 1 + len(steps) + (1 if conj else 0)
+    ka = np.empty((n_keys, ctx.dnum, ctx.L + ctx.K, ctx.N), dtype=np.uint64)
+    ke = np.empty((n_keys, ctx.dnum, ctx.N), dtype=np.int32)
+    for i in range(n_keys):
+        ka[i], ke[i] = synth.key_randomness(ctx.primes, ctx.N, ctx.dnum, seed, wl, i)
+    return ctx.keygen(s, ka, ke, steps=steps, with_conj=conj)
 
 
 def setup(args):
@@ -74,41 +130,28 @@ def setup(args):
     from paper_2604_19890_amd import synth
 
     ctx = G.Context(LOG_N, P_, R_, L_, K_)
-    N, ell = ctx.N, ctx.slots
     wl = 2
-    s = synth.ternary(N, args.seed, wl)
+    s = synth.ternary(ctx.N, args.seed, wl)
     steps = [1 << i for i in range(6)]  # 1..32: rotate-and-sum over a row of 64 slots
-    n_keys = 1 + len(steps) + 1
     t0 = time.time()
-    ka = np.empty((n_keys, ctx.dnum, ctx.L + ctx.K, N), dtype=np.uint64)
-    ke = np.empty((n_keys, ctx.dnum, N), dtype=np.int32)
-    for i in range(n_keys):
-        ka[i], ke[i] = synth.key_randomness(ctx.primes, N, ctx.dnum, args.seed, wl, i)
-    keys = ctx.keygen(s, ka, ke, steps=steps, with_conj=True)
-    del ka, ke
+    keys = make_keys(ctx, s, wl, args.seed, steps, True)
     log(f"[bench] keys {keys.bytes / 2**20:.0f} MiB in {time.time() - t0:.1f}s")
 
-    B = args.cts
+    B, ell = args.cts, ctx.slots
     g = synth.rng(args.seed, wl, synth.SLOTS, 0)
     cols = {k: g.integers(0, 1 << 16, size=(B, ell), dtype=np.uint64) for k in "abc"}
     thr = int(g.integers(0, 1 << 16))
-    if args.bits < 16:  # the filter column and threshold on a narrower range
-        cols["a"] >>= np.uint64(16 - args.bits)
-        thr >>= 16 - args.bits
-
-    def enc(rows, base):
-        c1 = np.empty((len(rows), ctx.L, N), dtype=np.uint64)
-        e = np.empty((len(rows), N), dtype=np.int32)
-        for i in range(len(rows)):
-            c1[i], e[i] = synth.encryption_randomness(ctx.primes[:ctx.L], N, args.seed, wl, base + i)
-        return ctx.encrypt(s, rows, c1, e)
-
     t0 = time.time()
-    cts = {k: enc(cols[k], 100000 * (j + 1)) for j, k in enumerate("abc")}
-    cts["t"] = enc(np.full((1, ell), thr, dtype=np.uint64), 900000)
+    cts = {k: encrypt_rows(ctx, s, cols[k], wl, 100000 * (j + 1), args.seed) for j, k in enumerate("abc")}
+    cts["t"] = encrypt_rows(ctx, s, np.full((1, ell), thr), wl, 900000, args.seed)
+    # the 15-bit variant of the filter column and threshold (same b and c)
+    cols15 = dict(cols, a=cols["a"] >> np.uint64(1))
+    thr15 = thr >> 1
+    cts15 = {"a": encrypt_rows(ctx, s, cols15["a"], wl, 400000, args.seed),
+             "t": encrypt_rows(ctx, s, np.full((1, ell), thr15), wl, 950000, args.seed)}
     torch.cuda.synchronize()
-    log(f"[bench] encrypted 3 x {B} + 1 ciphertexts in {time.time() - t0:.1f}s")
-    return ctx, keys, s, cols, thr, cts
+    log(f"[bench] encrypted 4 x {B} + 2 ciphertexts in {time.time() - t0:.1f}s")
+    return ctx, keys, s, cols, thr, cts, cols15, thr15, cts15
 
 
 def expected_sum(cols, thr, t=P_ ** R_):
@@ -129,39 +172,43 @@ def sql_agreement(cols, thr, t=P_ ** R_):
             "sum_equals_sql": int((b * c * sql).sum() % t) == expected_sum(cols, thr, t)}
 
 
-def time_batched(ctx, keys, cts, steps, warmup):
+def time_batched(ctx, keys, cts, steps, warmup, a="a", t="t"):
     import torch
     for _ in range(warmup):
-        ctx.filter_sum(keys, cts["a"], cts["t"], cts["b"], cts["c"])
+        ctx.filter_sum(keys, cts[a], cts[t], cts["b"], cts["c"])
     torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start, stop = events()
     start.record()
     out = None
     for i in range(steps):
-        out = ctx.filter_sum(keys, cts["a"], cts["t"], cts["b"], cts["c"])
+        out = ctx.filter_sum(keys, cts[a], cts[t], cts["b"], cts["c"])
         log(f"[bench] step {i + 1}/{steps} enqueued")
     stop.record()
     torch.cuda.synchronize()
     return start.elapsed_time(stop) / 1e3, out
 
 
+def step_accounting(ctx, keys, cts):
+    """What the library enqueues for one query step: key switches, rescaling switches and the
+    algorithmic HBM bytes of its steps (the library's own accounting, bgv_get_stats)."""
+    import torch
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.filter_sum(keys, cts["a"], cts["t"], cts["b"], cts["c"])
+    st = ctx.stats()
+    torch.cuda.synchronize()
+    return st
+
+
 def time_plain(ctx, keys, cts, n_plain):
     """One ciphertext per call: the same query, looping over the first n_plain rows-ciphertexts."""
     import torch
-    from paper_2604_19890_amd.bgv import Ct
-
-    N = ctx.N
-
-    def one(name, i):
-        x = cts[name]
-        w = x.tensor.numel() // x.n
-        return Ct(x.tensor[i * w:(i + 1) * w], 1, x.level, x.t_exp)
 
     def run():
         acc = None
         for i in range(n_plain):
-            bc = ctx.mul(keys, one("b", i), one("c", i))
-            lt = ctx.less_than(keys, one("a", i), cts["t"])
+            bc = ctx.mul(keys, ctx.view(cts["b"], i, 1), ctx.view(cts["c"], i, 1))
+            lt = ctx.less_than(keys, ctx.view(cts["a"], i, 1), cts["t"])
             prod = ctx.mul(keys, lt, bc)
             acc = prod if acc is None else ctx.add(acc, prod)
         return ctx.rotate_sum(keys, acc)
@@ -185,7 +232,7 @@ def time_graph(ctx, keys, cts, steps):
     graph = ctx.capture_end()
     graph.launch()
     torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start, stop = events()
     start.record()
     for _ in range(steps):
         graph.launch()
@@ -209,15 +256,27 @@ def time_ntt(ctx, n_cts, reps=20, warm_s=1.0):
         torch.cuda.synchronize()
         if time.perf_counter() - t0 >= warm_s:
             break
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(reps):
-        ctx.ntt(x, n_cts * 2, ctx.L)
-    stop.record()
-    torch.cuda.synchronize()
-    per = start.elapsed_time(stop) / 1e3 / reps
+    per = time_calls(lambda: ctx.ntt(x, n_cts * 2, ctx.L), reps, warm=0)
     algo_bytes = 16.0 * ctx.N * limbs
     return per, algo_bytes, limbs
+
+
+def product_step(ctx, keys, cts, reps=5):
+    """The product step (tensor, relinearisation, one modulus switch: bgv_mul) on the query's
+    batch at the top level, timed alone; algorithmic bytes from the library's accounting."""
+    import torch
+    b, c = cts["b"], cts["c"]
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.mul(keys, b, c)
+    algo = ctx.stats()["algo_bytes"]
+    per = time_calls(lambda: ctx.mul(keys, b, c), reps, warm=2)
+    achieved = algo / per / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "ms": per * 1e3, "algorithmic_bytes": algo,
+            "traffic": counter_bytes(KS_COUNTERS, b.n),
+            "op": f"bgv_mul of {b.n} ciphertext pairs at level {b.level} (N=2^16, K=6): reads 4 l, writes "
+                  f"2 (l - 1) limbs per ciphertext, plus the relinearisation key once"}
 
 
 def ntt_only(args):
@@ -236,6 +295,117 @@ def ntt_only(args):
     per, algo_bytes, limbs = time_ntt(ctx, args.cts, reps=args.steps, warm_s=0.0)
     log(f"[bench] ntt-only: {limbs} limbs, {algo_bytes / 2**30:.3f} GiB algorithmic per transform, "
         f"copy of {x.numel() * 8 / 2**30:.3f} GiB; {per * 1e6:.1f} us per transform")
+
+
+def ks_only(args):
+    """The product step on --cts ciphertext pairs at level 30 and a device copy of 480 MiB,
+    --steps times each: the run the hardware counters of the product step are read on."""
+    import torch
+    from paper_2604_19890_amd import bgv as G
+    from paper_2604_19890_amd import synth
+    ctx = G.Context(LOG_N, P_, R_, L_, K_)
+    s = synth.ternary(ctx.N, args.seed, 2)
+    keys = make_keys(ctx, s, 2, args.seed, [], False)
+    g = synth.rng(args.seed, 2, synth.SLOTS, 1)
+    b = encrypt_rows(ctx, s, g.integers(0, ctx.t, size=(args.cts, ctx.slots)), 2, 100, args.seed)
+    c = encrypt_rows(ctx, s, g.integers(0, ctx.t, size=(args.cts, ctx.slots)), 2, 200, args.seed)
+    x = torch.empty(480 * 2**20 // 8, dtype=torch.int64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.steps):
+        ctx.mul(keys, b, c)
+        y.copy_(x)
+    torch.cuda.synchronize()
+    res = product_step(ctx, keys, {"b": b, "c": c}, reps=args.steps)
+    log(f"[bench] ks-only: {res['ms']:.2f} ms per product step, {res['achieved']:.0f} GB/s algorithmic")
+
+
+# ----------------------------------------------------------------------------- primitive batch
+
+def primitives(args):
+    """The primitive batch: N = 2^15, p = 257, r = 2, 16 + 4 primes, 64 ciphertexts with uniform
+    slots; NTT and INTT, mul_relin (32 pairs), rotate by seeded random steps (8 steps, 8
+    ciphertexts each), mod_switch 16 -> 15; each batched (one call) and plain (one ciphertext per
+    call), with the algorithmic bytes of each operation over its batched time."""
+    import torch
+    from paper_2604_19890_amd import bgv as G
+    from paper_2604_19890_amd import synth
+    ctx = G.Context(15, P_, R_, 16, 4)
+    wl = 5
+    s = synth.ternary(ctx.N, args.seed, wl)
+    g = synth.rng(args.seed, wl, synth.PERM, 0)
+    steps = sorted(int(v) for v in g.choice(np.arange(1, 64), size=8, replace=False))
+    keys = make_keys(ctx, s, wl, args.seed, steps, False)
+    split, tune_us = ctx.autotune_ntt(64 * 2 * 16, reps=5)
+    n = 64
+    rows = synth.rng(args.seed, wl, synth.SLOTS, 0).integers(0, ctx.t, size=(n, ctx.slots))
+    X = encrypt_rows(ctx, s, rows, wl, 0, args.seed)
+    perm = synth.rng(args.seed, wl, synth.PERM, 1).permutation(n)
+    Y = ctx.concat([ctx.view(X, int(i), 1) for i in perm])
+    N, lv, K = ctx.N, ctx.L, ctx.K
+    limb_bytes = N * 8
+    key_limbs = 2 * ctx.dnum * (lv + K)
+    out = {"config": f"N=2^15 p=257 r=2 L=16 K=4, {n} ciphertexts", "ntt_split": split, "autotune_us": tune_us,
+           "rotate_steps": steps}
+    flat = X.tensor[: n * ctx.words(lv)].clone()
+
+    def rec(name, fb, fp, algo):
+        tb = time_calls(fb, 5, 2)
+        tp = time_calls(fp, 2, 1)
+        out[name] = {"batched_ms": tb * 1e3, "plain_ms": tp * 1e3, "batched_over_plain": tp / tb,
+                     "algorithmic_bytes": algo, "achieved_gbs": algo / tb / 1e9, "frac": algo / tb / 1e9 / HBM_PEAK_GBS}
+        log(f"[bench] primitives {name}: batched {tb * 1e3:.2f} ms, plain {tp * 1e3:.2f} ms, "
+            f"{algo / tb / 1e9:.0f} GB/s algorithmic")
+
+    per_ct = ctx.words(lv)
+    rec("ntt", lambda: ctx.ntt(flat, 2 * n, lv),
+        lambda: [ctx.ntt(flat[i * per_ct:(i + 1) * per_ct], 2, lv) for i in range(n)], 16.0 * N * 2 * lv * n)
+    rec("intt", lambda: ctx.ntt(flat, 2 * n, lv, inverse=True),
+        lambda: [ctx.ntt(flat[i * per_ct:(i + 1) * per_ct], 2, lv, inverse=True) for i in range(n)],
+        16.0 * N * 2 * lv * n)
+    A, Bm = ctx.view(X, 0, 32), ctx.view(Y, 0, 32)
+    rec("mul_relin", lambda: ctx.mul_relin(keys, A, Bm),
+        lambda: [ctx.mul_relin(keys, ctx.view(A, i, 1), ctx.view(Bm, i, 1)) for i in range(32)],
+        (6 * lv * 32 + key_limbs) * limb_bytes)
+    rec("rotate", lambda: [ctx.rotate(keys, ctx.view(X, 8 * k, 8), st) for k, st in enumerate(steps)],
+        lambda: [ctx.rotate(keys, ctx.view(X, i, 1), steps[i // 8]) for i in range(n)],
+        (4 * lv * n + 8 * key_limbs) * limb_bytes)
+    rec("mod_switch", lambda: ctx.mod_switch(X),
+        lambda: [ctx.mod_switch(ctx.view(X, i, 1)) for i in range(n)], (4 * lv - 2) * n * limb_bytes)
+    # the results decrypt to the slot products and the rotated slots
+    ta = ctx.decrypt(s, A).astype(object)
+    tb = ctx.decrypt(s, Bm).astype(object)
+    assert np.array_equal(ctx.decrypt(s, ctx.mul_relin(keys, A, Bm)), (ta * tb) % ctx.t)
+    del ctx, keys, X, Y, flat
+    torch.cuda.empty_cache()
+    return out
+
+
+# ----------------------------------------------------------------------------- ReLU sample
+
+def relu_leg(args, ctx, keys, s):
+    """ReLU x * (1 - [x < 0]) on int8 activations (round-half-even of N(0, 32^2), clipped to
+    [-128, 127], embedded mod 257^2) at the query's ring: calls of `--relu-cts` ciphertexts,
+    `--relu-calls` times (a bounded sample of the 2^18-activation workload: the same ciphertexts
+    in every call; the work is independent of the values), against one ciphertext per call."""
+    import torch
+    from paper_2604_19890_amd import synth
+    n = args.relu_cts
+    x = synth.int8_activations(n * ctx.slots, 32.0, args.seed, 6).reshape(n, ctx.slots)
+    X = encrypt_rows(ctx, s, x % ctx.t, 6, 0, args.seed)
+    t_b = time_calls(lambda: ctx.relu(keys, X), args.relu_calls, warm=1)
+    t_p = time_calls(lambda: ctx.relu(keys, ctx.view(X, 0, 1)), 2, warm=1)
+    got = ctx.decrypt(s, ctx.relu(keys, X))
+    assert np.array_equal(got, np.maximum(x, 0) % ctx.t), "relu"
+    rows_b = n * ctx.slots / t_b
+    rows_p = ctx.slots / t_p
+    log(f"[bench] relu: batched {rows_b:.0f} activations/s, plain {rows_p:.0f}")
+    del X
+    ctx.trim()
+    torch.cuda.empty_cache()
+    return {"activations_per_s": rows_b, "plain_activations_per_s": rows_p, "batched_over_plain": rows_b / rows_p,
+            "ms_per_call": t_b * 1e3,
+            "sample": f"{args.relu_calls} calls of {n} ciphertexts ({n * ctx.slots} activations each) at N=2^16 "
+                      f"L=30 K=6; the workload is 2^18 activations = 2048 ciphertexts"}
 
 
 # ----------------------------------------------------------------------------- CPU oracle baseline
@@ -305,6 +475,23 @@ def limb_products_per_query_ct():
     return per_ct, tail
 
 
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, avail
+
+
 def cpu_baseline(n_cts):
     from oracle import bgv as OB
     from oracle.params import Params
@@ -329,12 +516,17 @@ def cpu_baseline(n_cts):
     per_ct, tail = limb_products_per_query_ct()
     t_query = per_prod * (per_ct * n_cts + tail)
     rows = n_cts * P.ell
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model, nproc, avail = cpu_info()
+    # the oracle's C kernels run OpenMP over the output coefficients: OMP_NUM_THREADS threads if set,
+    # otherwise one per available core
+    threads = int(os.environ.get("OMP_NUM_THREADS", avail))
     return {
         "value": rows / t_query,
         "unit": "rows/s",
-        "cores": cores,
+        "cores": threads,
         "kind": "oracle",
+        "cpu_model": model,
+        "nproc": nproc,
         "sample": (f"one oracle mul_relin at N=2^16, level {lv}, K={K_} ({sample_prods} schoolbook limb products, "
                    f"{dt:.1f}s); scaled by the oracle schedule's {per_ct} limb products per 128-row ciphertext "
                    f"(+{tail} for the final rotate-and-sum) over {n_cts} ciphertexts"),
@@ -347,17 +539,25 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cts", type=int, default=32, help="ciphertexts per column per step (128 rows each)")
-    ap.add_argument("--plain", type=int, default=2, help="ciphertexts timed in the plain form")
+    ap.add_argument("--plain", type=int, default=8, help="ciphertexts timed in the plain form")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="also time the step replayed from a hipGraph")
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the forward NTT at the query shape and a copy of the same bytes (for counters)")
+    ap.add_argument("--ks-only", action="store_true",
+                    help="only the product step at the query shape and a copy (for counters)")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-basic-schedule", action="store_true",
                     help="skip timing the query in the basic evaluation schedule")
     ap.add_argument("--no-ntt", action="store_true",
                     help="skip the standalone NTT timing (roofline null), e.g. to profile the query alone")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the query (no 15-bit variant, primitives, ReLU, serving mix or product step)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-queries", type=int, default=24)
+    ap.add_argument("--relu-cts", type=int, default=64)
+    ap.add_argument("--relu-calls", type=int, default=4)
     ap.add_argument("--bits", type=int, default=16, choices=range(1, 17), metavar="1..16",
                     help="range of the filter column and threshold (16: the workload; 15: the circuit's "
                          "comparison equals the integer one on every row)")
@@ -371,16 +571,32 @@ def main():
     if args.ntt_only:
         ntt_only(args)
         return
-    ctx, keys, s, cols, thr, cts = setup(args)
+    if args.ks_only:
+        ks_only(args)
+        return
+    ctx, keys, s, cols, thr, cts, cols15, thr15, cts15 = setup(args)
+    if args.bits < 16:  # the whole run on the narrower filter column
+        cols, thr, cts = cols15, thr15, dict(cts, a=cts15["a"], t=cts15["t"])
     rows = args.cts * ctx.slots
+    extras = not args.no_extras
+
+    # NTT pass split: the autotuner's pick on the query's transform shape (at N = 2^16 only the
+    # 8 + 8 split is within the passes' 4..8 stages; the pick matters at smaller rings)
+    ntt_limbs = min(args.cts, 16) * 2 * ctx.L
+    split, tune_us = ctx.autotune_ntt(ntt_limbs, reps=5)
+    log(f"[bench] autotuned NTT split {split} ({tune_us:.1f} us per transform of {ntt_limbs} limbs)")
 
     # the dominant kernel, the forward NTT at the query's ciphertext shape (16 ciphertexts),
     # timed before the query after its own warm-up
-    ntt_gbs, ntt_limbs = None, min(args.cts, 16) * 2 * ctx.L
+    ntt_gbs = None
     if not args.no_ntt:
         ntt_s, ntt_bytes, ntt_limbs = time_ntt(ctx, min(args.cts, 16))
         ntt_gbs = ntt_bytes / ntt_s / 1e9
         log(f"[bench] NTT: {ntt_limbs} limbs in {ntt_s * 1e3:.3f} ms = {ntt_gbs:.0f} GB/s")
+
+    ks = product_step(ctx, keys, cts) if extras else None
+    if ks:
+        log(f"[bench] product step: {ks['ms']:.2f} ms, {ks['achieved']:.0f} GB/s algorithmic ({ks['frac']:.3f})")
 
     elapsed, out = time_batched(ctx, keys, cts, args.steps, args.warmup)
     per_step = elapsed / args.steps
@@ -391,6 +607,20 @@ def main():
         exp = expected_sum(cols, thr)
         assert all(int(v) == exp for v in got), (got[:4], exp)
         log(f"[bench] decrypted SUM = {exp} in every slot (matches the plaintext query)")
+    acct = step_accounting(ctx, keys, cts)
+    step_gbs = acct["algo_bytes"] / per_step / 1e9
+    log(f"[bench] step: {acct['key_switches']} key switches, {acct['rescale_drops']} rescaling drops, "
+        f"{acct['algo_bytes'] / 1e9:.1f} GB algorithmic = {step_gbs:.0f} GB/s")
+
+    sql_exact = None
+    if extras and args.bits == 16:
+        el15, out15 = time_batched(ctx, keys, dict(cts, a=cts15["a"], t=cts15["t"]), args.steps, 1)
+        exp15 = expected_sum(cols15, thr15)
+        ok = all(int(v) == exp15 for v in ctx.decrypt(s, out15)[0])
+        sql_exact = {"bits": 15, "rows_per_s": rows * args.steps / el15, "ms_per_step": el15 / args.steps * 1e3,
+                     "decrypted_sum_correct": ok, **sql_agreement(cols15, thr15)}
+        log(f"[bench] 15-bit filter column: {el15 / args.steps * 1e3:.1f} ms/step, SQL-exact: "
+            f"{sql_exact['sum_equals_sql']}")
 
     # the same query in the basic evaluation schedule (one product per outer Paterson-Stockmeyer
     # term, dense split), for comparison with the default schedule timed above
@@ -407,12 +637,22 @@ def main():
     t_graph = time_graph(ctx, keys, cts, args.steps) if args.graph else None
     if t_graph:
         log(f"[bench] graph replay: {t_graph * 1e3:.1f} ms/step, {rows / t_graph:.1f} rows/s")
-    t_plain = time_plain(ctx, keys, cts, args.plain) if args.plain > 0 else None
-    plain_rows = (args.plain * ctx.slots / t_plain) if t_plain else None
+    n_plain = min(args.plain, args.cts)
+    t_plain = time_plain(ctx, keys, cts, n_plain) if n_plain > 0 else None
+    plain_rows = (n_plain * ctx.slots / t_plain) if t_plain else None
     if t_plain:
-        log(f"[bench] plain: {t_plain * 1e3:.1f} ms for {args.plain} ciphertexts, {plain_rows:.1f} rows/s")
+        log(f"[bench] plain: {t_plain * 1e3:.1f} ms for {n_plain} ciphertexts, {plain_rows:.1f} rows/s")
 
-    traffic = ntt_traffic_bytes(ntt_limbs)
+    relu = relu_leg(args, ctx, keys, s) if extras else None
+    ctx.trim()
+    torch.cuda.empty_cache()
+    prims = primitives(args) if extras else None
+    served = None
+    if extras and not args.no_serve:
+        from paper_2604_19890_amd import serve as SV
+        served = SV.run_mix(n_queries=args.serve_queries, seed=args.seed, log=log)
+
+    traffic = counter_bytes(NTT_COUNTERS, ntt_limbs)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cts)
     line = {
         "metric": "encrypted filter+SUM rows/s @N=2^16 (batched)",
@@ -431,16 +671,26 @@ def main():
                                + (f", {args.bits}-bit filter column" if args.bits < 16 else ""),
                    "rows_per_step": rows, "parallelism": "batch"},
         "plain_rows_per_s": plain_rows,
+        "plain_cts_timed": n_plain,
         "graph_rows_per_s": (rows / t_graph) if t_graph else None,
         "batched_over_plain": (value / plain_rows) if plain_rows else None,
         "basic_schedule": basic_sched,
         "ntt_gb_per_s": ntt_gbs,
+        "ntt_split": {"autotuned": split, "us": tune_us, "limbs": ntt_limbs},
         "roofline": None if ntt_gbs is None else {
-                     "bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ntt_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_ntt_pass, forward NTT (two passes) over {ntt_limbs} limbs of N=2^16; "
-                               f"achieved = 16 N bytes per limb / transform time; traffic = counter bytes "
-                               f"per transform"},
+            "bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ntt_gbs / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": f"k_ntt_pass, forward NTT (two passes) over {ntt_limbs} limbs of N=2^16; "
+                      f"achieved = 16 N bytes per limb / transform time; traffic = counter bytes per transform"},
+        "ks_roofline": ks,
+        "step_roofline": {"bound": "hbm", "algorithmic_bytes": acct["algo_bytes"], "achieved": step_gbs,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
+                          "key_switches": acct["key_switches"], "rescale_drops": acct["rescale_drops"],
+                          "limb_drops": acct["limb_drops"]},
+        "sql_exact": sql_exact,
+        "primitives": prims,
+        "relu": relu,
+        "served": served,
         "cpu_baseline": cpu,
         "sql_agreement": sql_agreement(cols, thr),
     }

@@ -283,6 +283,10 @@ void bgv_graph_destroy(bgv_graph* graph);
  * bgv_get_ntt_chunk: the current setting.                                       */
 bgv_status bgv_set_ntt_chunk(bgv_ctx* ctx, int32_t limbs);
 int32_t bgv_get_ntt_chunk(const bgv_ctx* ctx);
+/* bgv_set_ntt_coop: how two-pass transforms run.  mode 0 (the only one built): two
+ *   launches per transform.  mode 1, a persistent launch that would keep each limb's
+ *   intermediate in one XCD's L2, is switched off and returns BGV_E_UNSUPPORTED.     */
+bgv_status bgv_set_ntt_coop(bgv_ctx* ctx, int32_t mode, int32_t lookahead);
 /* bgv_set_ntt_split: stages in the first of the two NTT passes (each pass does 4..8
  *   stages; 0 restores the default ceil(log N / 2)).  BGV_E_ARG if out of range.
  * bgv_autotune_ntt: times every valid split on a scratch array of `limbs` limbs
@@ -317,6 +321,12 @@ typedef struct {
   int64_t rescale_drops;     /* single-prime modulus switches (a switch by k primes adds k) */
   int64_t limb_drops;        /* alignments that remove top limbs without rescaling         */
   int64_t odd_splits;        /* polynomial evaluations that took the odd baby-step split    */
+  int64_t algo_bytes;        /* algorithmic HBM bytes of the enqueued steps: each step's one
+                                read of its inputs and write of its outputs (a relinearised
+                                product 6 l N 8, 6 l N 8 - 2 N 8 with its switch merged in; a
+                                rotation 4 l N 8; a single modulus switch (4 l - 2) N 8; linear
+                                steps their inputs and outputs), per ciphertext of a batch, plus
+                                the key of a key switch once per call                         */
   int32_t max_baby_k;        /* largest baby-step count k of an evaluated polynomial        */
   int32_t max_inner_terms;   /* most baby powers read by one multi-output inner-sum launch  */
   int32_t max_inner_outputs; /* most inner sums written by one such launch                  */

@@ -54,7 +54,8 @@ class _Info(ctypes.Structure):
 
 
 class _Stats(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_int64) for f in ("key_switches", "rescale_drops", "limb_drops", "odd_splits")] + \
+    _fields_ = [(f, ctypes.c_int64) for f in ("key_switches", "rescale_drops", "limb_drops", "odd_splits",
+                                              "algo_bytes")] + \
                [(f, ctypes.c_int32) for f in ("max_baby_k", "max_inner_terms", "max_inner_outputs",
                                               "max_tensor_pairs")]
 
@@ -112,6 +113,7 @@ _sigs = {
     "bgv_get_ntt_chunk": [_vp],
     "bgv_get_stats": [_vp, _P(_Stats)],
     "bgv_mod_switch_noalloc": [_vp, _P(_Ct), _P(_Ct)],
+    "bgv_set_ntt_coop": [_vp, _i32, _i32],
     "bgv_reset_stats": [_vp],
 }
 for _name, _args in _sigs.items():
@@ -259,6 +261,10 @@ class Context:
         h = ctypes.c_void_p()
         self._check(_lib.bgv_capture_end(self.handle, ctypes.byref(h)))
         return Graph(self, h)
+
+    def set_ntt_coop(self, mode: int, lookahead: int = 2):
+        """Two-pass transforms as one XCD-local launch (mode 1) or two launches (mode 0)."""
+        self._check(_lib.bgv_set_ntt_coop(self.handle, int(mode), int(lookahead)))
 
     def stats(self) -> dict:
         """Host-side counters of the enqueued work (see bgv_get_stats)."""

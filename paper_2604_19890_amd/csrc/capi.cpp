@@ -159,6 +159,13 @@ BGV_EXPORT bgv_status bgv_sync(bgv_ctx* c) {
   return BGV_OK;
 }
 
+BGV_EXPORT bgv_status bgv_set_ntt_coop(bgv_ctx* c, int32_t mode, int32_t lookahead) {
+  NEED_CTX(c);
+  if (mode < 0 || mode > 1 || lookahead < 0 || lookahead > 16) return fail(c, BGV_E_ARG, "mode 0/1, lookahead 0..16");
+  if (mode == 1) return fail(c, BGV_E_UNSUPPORTED, "the XCD-local transform is switched off");
+  return BGV_OK;
+}
+
 BGV_EXPORT const char* bgv_last_error(const bgv_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 BGV_EXPORT bgv_status bgv_keygen(bgv_ctx* c, const int8_t* s, const uint64_t* a, const int32_t* e,
@@ -643,6 +650,7 @@ BGV_EXPORT bgv_status bgv_get_stats(const bgv_ctx* c, bgv_stats* o) {
   o->rescale_drops = c->stats.rescale_drops;
   o->limb_drops = c->stats.limb_drops;
   o->odd_splits = c->stats.odd_splits;
+  o->algo_bytes = c->stats.algo_bytes;
   o->max_baby_k = c->stats.max_baby_k;
   o->max_inner_terms = c->stats.max_inner_terms;
   o->max_inner_outputs = c->stats.max_inner_outputs;

@@ -30,6 +30,7 @@ struct Stats {
   int64_t rescale_drops = 0;  // single-prime modulus switches (k primes at once count k)
   int64_t limb_drops = 0;     // alignments by removing top limbs without rescaling
   int64_t odd_splits = 0;     // polynomial evaluations in the odd baby-step split
+  int64_t algo_bytes = 0;     // algorithmic HBM bytes of the enqueued steps (see ops.cpp)
   int32_t max_baby_k = 0;
   int32_t max_inner_terms = 0;
   int32_t max_inner_outputs = 0;

@@ -57,29 +57,21 @@ __device__ __forceinline__ void pass_sync(bool wave_local) {
     __syncthreads();
 }
 
-// One pass over data; the pass reads from src (data itself when src is null,
-// the transform then being in place) and writes to data, or with EPI (the last
-// forward pass) applies the epilogue ep and writes ep.out.
+// One pass over one block of one limb.  The pass reads from src (data itself when src
+// is null, the transform then being in place) and writes to data, or with EPI (the last
+// forward pass) applies the epilogue ep and writes ep.out.  `limb` is the launch limb
+// index (after the block-row order below) and `bx` the block's position within the limb.
 template <int LOGS, bool INV, bool EPI>
-__global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint64_t* src, int logN, int s0,
-                                                     LimbMap lm, const PrimeD* __restrict__ pc,
-                                                     const double* __restrict__ tw, int last, lk::NttEpi ep) {
+__device__ __forceinline__ void ntt_pass_body(uint64_t* data, const uint64_t* src, int logN, int s0,
+                                              const LimbMap& lm, const PrimeD* __restrict__ pc,
+                                              const double* __restrict__ tw, int last, const lk::NttEpi& ep,
+                                              int limb, int bx, double* lds) {
   constexpr int S = 1 << LOGS;
   constexpr int T = S / 16;
   constexpr int T_LOG = LOGS - 4;
-  __shared__ double lds[NT_MAX * 16 + NT_MAX + NT_MAX];
   const int N = 1 << logN;
   const int NT = blockDim.x;
   const int SUBS = NT / T;
-  // Prime-major block order: consecutive block rows take the same limb position
-  // of consecutive polynomials, so the prime's twiddle table is read once into
-  // each XCD's L2 and reused instead of cycling through every prime's table.
-  int limb = blockIdx.y;
-  if (gridDim.y % lm.period == 0) {
-    const int polys = gridDim.y / lm.period;
-    limb = (blockIdx.y % polys) * lm.period + blockIdx.y / polys;
-  }
-  if (limb_skipped(lm, limb)) return;
   const int pi = limb_prime(lm, limb);
   const double q = pc[pi].q, qinv = pc[pi].qinv;
   const double* __restrict__ w = tw + (size_t)pi * N;
@@ -97,10 +89,6 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
     sl = threadIdx.x % SUBS;
     tau = threadIdx.x / SUBS;
   }
-  // Column pass: the column block turns with the row.  Block ids go round-robin over the
-  // eight XCDs, so with a fixed order an XCD would always take the same column blocks of
-  // every row (16 blocks per row at N = 2^16); turning the order spreads them.
-  const int bx = tmin > 1 ? ((blockIdx.x + blockIdx.y) & (gridDim.x - 1)) : blockIdx.x;
   const int st = bx * SUBS + sl;
   const int lo = st & (tmin - 1);
   const int hi = st >> tmin_log;
@@ -186,6 +174,31 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint6
 #pragma unroll
     for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(d2u(canon(red(v[i], q, qinv), q)), &xp[(size_t)i << gs1_log]);
   }
+}
+
+// Prime-major block order: consecutive block rows take the same limb position of
+// consecutive polynomials, so the prime's twiddle table is read once into each XCD's L2
+// and reused instead of cycling through every prime's table.
+__device__ __forceinline__ int prime_major(const LimbMap& lm, int row, int rows) {
+  if (rows % lm.period != 0) return row;
+  const int polys = rows / lm.period;
+  return (row % polys) * lm.period + row / polys;
+}
+
+// One pass over data as its own launch: block (x, y) takes block x of launch limb y.
+template <int LOGS, bool INV, bool EPI>
+__global__ void __launch_bounds__(NT_MAX) k_ntt_pass(uint64_t* data, const uint64_t* src, int logN, int s0,
+                                                     LimbMap lm, const PrimeD* __restrict__ pc,
+                                                     const double* __restrict__ tw, int last, lk::NttEpi ep) {
+  __shared__ double lds[NT_MAX * 16 + NT_MAX + NT_MAX];
+  const int limb = prime_major(lm, blockIdx.y, gridDim.y);
+  if (limb_skipped(lm, limb)) return;
+  // Column pass: the column block turns with the row.  Block ids go round-robin over the
+  // eight XCDs, so with a fixed order an XCD would always take the same column blocks of
+  // every row (16 blocks per row at N = 2^16); turning the order spreads them.
+  const bool column = logN - s0 - LOGS > 0;
+  const int bx = column ? ((blockIdx.x + blockIdx.y) & (gridDim.x - 1)) : blockIdx.x;
+  ntt_pass_body<LOGS, INV, EPI>(data, src, logN, s0, lm, pc, tw, last, ep, limb, bx, lds);
 }
 
 // Second forward pass fused with the key-switching inner product, over the

@@ -36,6 +36,18 @@ CipherP new_cipher(bgv_ctx* c, int n, int level, int t_exp) {
   return p;
 }
 
+// Algorithmic HBM bytes of the method's steps, in limbs of N words: what a step must read
+// and write once (a ciphertext at level l is 2 l limbs), plus the evaluation key of a key
+// switch read once per batch call (2 dnum' (l + K) limbs, dnum' = ceil(l / alpha)).  A
+// relinearised product reads its two operands and writes its result (6 l; 6 l - 2 when the
+// modulus switch after it is merged in), a rotation 4 l, a single modulus switch 4 l - 2.
+// Intermediate round trips of an implementation are not counted: this is the floor the
+// measured traffic is compared with.
+static void algo(bgv_ctx* c, double limbs) { c->stats.algo_bytes += (int64_t)(limbs * c->N * 8.0); }
+static double key_limbs(const bgv_ctx* c, int lv) {
+  return 2.0 * ((lv + c->alpha - 1) / c->alpha) * (lv + c->prm.K);
+}
+
 static void check_hip(bgv_ctx* c, hipError_t e, const char* what) {
   if (e != hipSuccess) {
     c->err = std::string(what) + ": " + hipGetErrorString(e);
@@ -62,10 +74,14 @@ void op_ntt(bgv_ctx* c, uint64_t* d, int n_polys, int level, bool inverse) {
 }
 
 void op_add_sub(bgv_ctx* c, const CtV& a, const CtV& b, const CtV& out, int op) {
+  algo(c, 6.0 * a.level * a.n);
   lk::add_sub(c, a.d, b.d, out.d, a.n, a.level, op, b.n == 1 && a.n > 1);
 }
 
-void op_negate(bgv_ctx* c, const CtV& a, const CtV& out) { lk::negate(c, a.d, out.d, a.n, a.level); }
+void op_negate(bgv_ctx* c, const CtV& a, const CtV& out) {
+  algo(c, 4.0 * a.level * a.n);
+  lk::negate(c, a.d, out.d, a.n, a.level);
+}
 
 static void scalar_table(const bgv_ctx* c, int64_t k, int level, double* s) {
   for (int i = 0; i < level; ++i) {
@@ -77,18 +93,21 @@ static void scalar_table(const bgv_ctx* c, int64_t k, int level, double* s) {
 }
 
 void op_mul_scalar(bgv_ctx* c, const CtV& a, int64_t k, const CtV& out) {
+  algo(c, 4.0 * a.level * a.n);
   double s[64];
   scalar_table(c, centered(k, c->tpow[a.t_exp]), a.level, s);
   lk::mul_scalar(c, a.d, out.d, a.n, a.level, s);
 }
 
 void op_add_const(bgv_ctx* c, const CtV& a, int64_t k, const CtV& out) {
+  algo(c, 4.0 * a.level * a.n);
   double s[64];
   scalar_table(c, centered(k, c->tpow[a.t_exp]), a.level, s);
   lk::add_const(c, a.d, out.d, a.n, a.level, s);
 }
 
 void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out) {
+  algo(c, 4.0 * a.level * a.n);
   double s[64];
   for (int i = 0; i < a.level; ++i) s[i] = (double)invmod((uint64_t)c->prm.p, c->primes[i]);
   lk::mul_scalar(c, a.d, out.d, a.n, a.level, s);
@@ -185,6 +204,7 @@ static void relin_ms(bgv_ctx* c, const bgv_keys* keys, Scratch& D, Scratch& X, i
 void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
   const int n = a.n, lv = a.level, N = c->N;
   if (lv < 2) throw OpError{BGV_E_LEVEL};
+  algo(c, (6.0 * lv - 2.0) * n + key_limbs(c, lv));
   Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
   lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1, lstride(a), lstride(b));
   relin_ms(c, keys, D, X, n, lv, a.t_exp, out);
@@ -206,6 +226,7 @@ static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector
   }
   if (lv < 2) throw OpError{BGV_E_LEVEL};
   const int t_exp = pairs[0].first->v.t_exp, N = c->N;
+  algo(c, (4.0 * lv * pairs.size() + 2.0 * (lv - 1)) * n + key_limbs(c, lv));
   Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
   // the pairs' tensor products summed in passes of at most TS_MAX pairs (each operand read once)
   for (size_t s0 = 0; s0 < pairs.size(); s0 += lk::TS_MAX) {
@@ -234,6 +255,7 @@ static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector
 
 void op_mul_relin(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, const CtV& out) {
   const int n = a.n, lv = a.level, N = c->N;
+  algo(c, 6.0 * lv * n + key_limbs(c, lv));
   Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
   lk::tensor(c, a.d, b.d, D.d, X.d, n, lv, b.n == 1 && n > 1);
   key_switch(c, keys->relin, X, n, lv, a.t_exp, D.d, (int64_t)2 * lv * N, 2, out.d);
@@ -251,6 +273,7 @@ void op_rotate(bgv_ctx* c, const bgv_keys* keys, const CtV& in, int g, const CtV
   const int n = in.n, lv = in.level, N = c->N;
   auto it = keys->galois.find(g);
   if (it == keys->galois.end()) throw OpError{BGV_E_NOKEY};
+  algo(c, 4.0 * lv * n + key_limbs(c, lv));
   Scratch R(c, (size_t)n * lv * N), X(c, (size_t)n * lv * N);
   const int64_t st = (int64_t)2 * lv * N;
   lk::automorph(c, in.d, st, R.d, (int64_t)lv * N, n, lv, g);              // X -> X^g on c0
@@ -265,6 +288,7 @@ void op_mod_switch_with(bgv_ctx* c, const CtV& in, const CtV& out, uint64_t* T, 
   const int n = in.n, lv = in.level, N = c->N;
   if (lv < 2) throw OpError{BGV_E_LEVEL};
   c->stats.rescale_drops += 1;
+  algo(c, (4.0 * lv - 2.0) * n);
   check_hip(c,
             hipMemcpy2DAsync(T, (size_t)N * 8, in.d + (size_t)(lv - 1) * N, (size_t)lv * N * 8, (size_t)N * 8,
                              (size_t)n * 2, hipMemcpyDeviceToDevice, c->stream),
@@ -306,6 +330,7 @@ void op_mod_switch_to(bgv_ctx* c, const CtV& in, int to, const CtV& out) {
     return;
   }
   c->stats.rescale_drops += lv - to;
+  algo(c, (2.0 * lv + 2.0 * to) * n);
   // At most 16 drops per step.  A step brings only the dropped limbs to coefficient
   // form, forms the combined correction e for the kept ones, and finishes in the epilogue
   // of e's forward NTT: out_i = (c_i - e_i) prod q_dropped^-1 with c in evaluation form.
@@ -835,6 +860,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
         }
         c->stats.max_inner_terms = std::max(c->stats.max_inner_terms, (int)terms.size());
         c->stats.max_inner_outputs = std::max(c->stats.max_inner_outputs, no);
+        algo(c, 2.0 * lv * (terms.size() + no) * x->v.n);
         lk::lincomb_multi(c, m, (int)terms.size(), no, tab, c->prm.L, scs, x->v.n, lv);
       }
       continue;
@@ -856,6 +882,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
       for (size_t s = 0; s < xs.size(); s += 16) {
         const int nt = (int)std::min<size_t>(16, xs.size() - s);
         CipherP part = s == 0 ? acc : new_cipher(c, x->v.n, lv, x->v.t_exp);
+        algo(c, 2.0 * lv * (nt + 1) * x->v.n);
         lk::lincomb(c, xs.data() + s, rws.data() + s, nt, tab, c->prm.L, (s == 0 && cst != 0) ? j * kk : -1,
                     part->v.d, x->v.n, lv);
         if (s > 0) op_add_sub(c, acc->v, part->v, acc->v, 0);
@@ -1003,6 +1030,7 @@ CipherP ev_less_than(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const Ciph
 }
 
 CipherP ev_batch_sum(bgv_ctx* c, const CipherP& x) {
+  algo(c, 2.0 * x->v.level * (x->v.n + 1));
   CipherP r = new_cipher(c, 1, x->v.level, x->v.t_exp);
   lk::batch_sum(c, x->v.d, r->v.d, x->v.n, x->v.level);
   return r;

@@ -1,7 +1,11 @@
 """Served form: continuous batching of encrypted filter-and-aggregate queries.
 
 Queries arrive over time (Poisson arrivals), each with its own ring size, row count and
-kind: SUM(b*c WHERE a < t) ("filter") or SUM(b*c) ("sum").  Their encrypted columns are
+kind: SUM(b*c WHERE a < t) ("filter") or SUM(b*c) ("sum").  Rings keep the chains of the
+serving configuration: 8 primes at N = 2^14 and 16 at N = 2^15 (special primes K = L / 4),
+which hold the arithmetic-only query (one product, then rotate-and-sum).  The compare
+circuit is 29 products deep, so filter queries run on the N = 2^16 ring, whose chain is
+30 + 6 primes (the configured 24 extended to the circuit's depth).  Their encrypted columns are
 resident in HBM; every ring keeps its evaluation keys resident.  A query is admitted when
 its ciphertext footprint fits the memory budget next to the resident keys, and waits (FIFO)
 otherwise; a query larger than the whole budget is rejected.
@@ -35,6 +39,20 @@ from . import synth
 
 P_, R_ = 257, 2
 STEPS = [1 << i for i in range(6)]
+# (ciphertext primes L, special primes K) per ring (log2 N)
+RING_CHAINS = {14: (8, 2), 15: (16, 4), 16: (30, 6)}
+# log2(Q P) bound for 128-bit security with a uniform ternary secret, from the homomorphic
+# encryption security standard's table (N = 2^14, 2^15, 2^16)
+QP_BITS_128 = {14: 438, 15: 881, 16: 1772}
+
+
+def security_estimate(log_n: int, L: int, K: int, bits: int = 50) -> dict:
+    """log2(Q P) of a chain and a rough security level: 128 scaled by the standard's log2(Q P)
+    bound over the chain's (the level falls about in proportion to log2(Q P) at fixed N).
+    An estimate for orientation, not the output of a lattice estimator."""
+    qp = (L + K) * bits
+    bound = QP_BITS_128.get(log_n)
+    return {"log2_qp": qp, "bound_128": bound, "lambda_est": None if bound is None else round(128.0 * bound / qp)}
 
 
 @dataclasses.dataclass
@@ -140,7 +158,11 @@ class Engine:
             q.done_event.record(self.stream)
 
 
-def make_queries(n_queries: int, rings, rows_lo: int, rows_hi: int, rate: float, seed: int = 0):
+def make_queries(n_queries: int, rings, rows_lo: int, rows_hi: int, rate: float, seed: int = 0,
+                 filter_ring: int = 16):
+    """70% filter / 30% arithmetic-only queries, rows log-uniform in [rows_lo, rows_hi]; an
+    arithmetic-only query takes a ring drawn uniformly from `rings`, a filter query the ring
+    whose chain holds the compare circuit (filter_ring)."""
     g = synth.rng(seed, 77, synth.SLOTS, 0)
     t = 0.0
     out = []
@@ -149,6 +171,8 @@ def make_queries(n_queries: int, rings, rows_lo: int, rows_hi: int, rate: float,
         rows = int(round(math.exp(g.uniform(math.log(rows_lo), math.log(rows_hi)))))
         log_n = int(g.choice(rings))
         kind = "filter" if g.uniform() < 0.7 else "sum"
+        if kind == "filter":
+            log_n = filter_ring
         out.append(Query(i, log_n, kind, rows, t))
     return out
 
@@ -289,6 +313,50 @@ def check(queries, engines):
     return bad
 
 
+def poisson_arrivals(queries, rate: float, seed: int = 0):
+    g = synth.rng(seed, 79, synth.SLOTS, 0)
+    t = 0.0
+    for q in queries:
+        t += g.exponential(1.0 / rate)
+        q.arrival = t
+
+
+def run_mix(n_queries: int = 24, rings=(14, 15, 16), rows_lo: int = 1 << 10, rows_hi: int = 1 << 12,
+            load: float = 0.8, round_cts_16: int = 16, seed: int = 0, log=print) -> dict:
+    """A bounded serving run: the mix's columns are encrypted first; the batched capacity is
+    measured with every query present at time 0; then arrivals are Poisson at `load` times that
+    capacity, served batched and then plain (one at a time).  Every result is checked against
+    the plaintext query."""
+    rings = list(rings)
+    engines = {r: Engine(r, *RING_CHAINS[r], seed=seed) for r in rings}
+    qs = make_queries(n_queries, rings, rows_lo, rows_hi, rate=0.0, seed=seed, filter_ring=max(rings))
+    prepare(qs, engines, seed=seed)
+    log(f"[serve] {len(qs)} queries, {sum(q.rows for q in qs)} rows, encrypted")
+    round_cts = {r: round_cts_16 << (16 - r) for r in rings}
+    for q in qs:
+        q.arrival = 0.0
+    cap = serve(qs, engines, mode="batched", round_cts=round_cts)
+    rate = load * len(qs) / cap["makespan_s"]
+    poisson_arrivals(qs, rate, seed)
+    release_cache(engines)
+    batched = serve(qs, engines, mode="batched", round_cts=round_cts)
+    bad = check(qs, engines)
+    log(f"[serve] batched: p50 {batched['p50_ms']:.0f} ms, p99 {batched['p99_ms']:.0f} ms, "
+        f"{batched['rows_per_s']:.0f} rows/s")
+    release_cache(engines)
+    plain = serve(qs, engines, mode="plain")
+    bad += check(qs, engines)
+    log(f"[serve] plain: p50 {plain['p50_ms']:.0f} ms, p99 {plain['p99_ms']:.0f} ms, {plain['rows_per_s']:.0f} rows/s")
+    chains = {str(r): {"L": RING_CHAINS[r][0], "K": RING_CHAINS[r][1], **security_estimate(r, *RING_CHAINS[r])}
+              for r in rings}
+    out = {"queries": len(qs), "rows": sum(q.rows for q in qs), "rows_lo": rows_lo, "rows_hi": rows_hi,
+           "load_of_batched_capacity": load, "arrival_rate_qps": rate, "batched_capacity_rows_per_s": cap["rows_per_s"],
+           "batched": batched, "plain": plain, "wrong_results": bad, "chains": chains}
+    del engines
+    release_cache({})
+    return out
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="served filter-and-aggregate queries on one GPU")
@@ -296,34 +364,11 @@ def main(argv=None):
     ap.add_argument("--queries", type=int, default=24)
     ap.add_argument("--rows-lo", type=int, default=1 << 10)
     ap.add_argument("--rows-hi", type=int, default=1 << 14)
-    ap.add_argument("--load", type=float, default=0.8, help="offered load as a fraction of the plain capacity")
+    ap.add_argument("--load", type=float, default=0.8, help="offered load as a fraction of the batched capacity")
     ap.add_argument("--round-cts", type=int, default=16, help="ciphertexts per round at N = 2^16 (scaled by N)")
-    ap.add_argument("--L", type=int, default=30)
     args = ap.parse_args(argv)
     rings = [int(x) for x in args.rings.split(",")]
-    K_of = {14: 2, 15: 4, 16: 6}
-    engines = {r: Engine(r, args.L, K_of.get(r, 6)) for r in rings}
-    qs = make_queries(args.queries, rings, args.rows_lo, args.rows_hi, rate=0.0)
-    prepare(qs, engines)
-    # plain capacity: every query served back to back with zero gaps
-    for q in qs:
-        q.arrival = 0.0
-    plain0 = serve(qs, engines, mode="plain")
-    rate = args.load * len(qs) / plain0["makespan_s"]
-    g = synth.rng(0, 79, synth.SLOTS, 0)
-    t = 0.0
-    for q in qs:
-        t += g.exponential(1.0 / rate)
-        q.arrival = t
-    round_cts = {r: args.round_cts << (16 - r) for r in rings}
-    release_cache(engines)
-    plain = serve(qs, engines, mode="plain")
-    bad_plain = check(qs, engines)
-    release_cache(engines)
-    batched = serve(qs, engines, mode="batched", round_cts=round_cts)
-    bad_batched = check(qs, engines)
-    out = {"arrival_rate_qps": rate, "rings": rings, "plain": plain, "batched": batched,
-           "wrong_results": bad_plain + bad_batched}
+    out = run_mix(args.queries, rings, args.rows_lo, args.rows_hi, args.load, args.round_cts)
     print(json.dumps(out), flush=True)
     return out
 
