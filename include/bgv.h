@@ -283,6 +283,13 @@ void bgv_graph_destroy(bgv_graph* graph);
  * bgv_get_ntt_chunk: the current setting.                                       */
 bgv_status bgv_set_ntt_chunk(bgv_ctx* ctx, int32_t limbs);
 int32_t bgv_get_ntt_chunk(const bgv_ctx* ctx);
+/* bgv_set_modup_fused: key switching with ModUp fused into the transform passes around
+ *   it (1, the default, for rings with two-pass transforms whose first pass has 5..8
+ *   stages and digits of 1, 2, 4 or 6 primes: x's last inverse pass, ModUp and the first
+ *   forward pass of every ModUp row run in one kernel, so neither x's coefficient form nor
+ *   the untransformed ModUp rows are stored) or ModUp between full transforms (0).
+ *   Results are identical either way.                                                 */
+bgv_status bgv_set_modup_fused(bgv_ctx* ctx, int32_t on);
 /* bgv_set_ntt_coop: how two-pass transforms run.  mode 0 (the only one built): two
  *   launches per transform.  mode 1, a persistent launch that would keep each limb's
  *   intermediate in one XCD's L2, is switched off and returns BGV_E_UNSUPPORTED.     */

@@ -114,6 +114,7 @@ _sigs = {
     "bgv_get_stats": [_vp, _P(_Stats)],
     "bgv_mod_switch_noalloc": [_vp, _P(_Ct), _P(_Ct)],
     "bgv_set_ntt_coop": [_vp, _i32, _i32],
+    "bgv_set_modup_fused": [_vp, _i32],
     "bgv_reset_stats": [_vp],
 }
 for _name, _args in _sigs.items():
@@ -261,6 +262,10 @@ class Context:
         h = ctypes.c_void_p()
         self._check(_lib.bgv_capture_end(self.handle, ctypes.byref(h)))
         return Graph(self, h)
+
+    def set_modup_fused(self, on: bool):
+        """Key switching with the fused ModUp pass (True, the default) or ModUp between full transforms."""
+        self._check(_lib.bgv_set_modup_fused(self.handle, 1 if on else 0))
 
     def set_ntt_coop(self, mode: int, lookahead: int = 2):
         """Two-pass transforms as one XCD-local launch (mode 1) or two launches (mode 0)."""

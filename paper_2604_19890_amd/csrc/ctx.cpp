@@ -356,6 +356,15 @@ bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream) {
       }
     }
   }
+  // the fused ModUp's scales: N^-1 Qhat_i^-1 mod q_i (the inverse transform's factor folded in)
+  std::vector<double> mus((size_t)(L + 1) * c->dnum * A, 0.0);
+  for (int lv = 1; lv <= L; ++lv)
+    for (int j = 0; j * A < lv; ++j)
+      for (int a = 0; a < std::min(A, lv - j * A); ++a) {
+        const uint64_t qi = c->primes[j * A + a];
+        const uint64_t inv = (uint64_t)mu[c->modup_inv_off(lv, j) + a];
+        mus[((size_t)lv * c->dnum + j) * A + a] = (double)mulmod(inv, invmod((uint64_t)N, qi), qi);
+      }
   // ModDown tables: phat_inv [K], phat_mod [K][L], pinv_q [L], pmod_q [L]
   std::vector<double> md((size_t)K + (size_t)K * L + 2 * (size_t)L, 0.0);
   for (int k = 0; k < K; ++k) {
@@ -421,7 +430,8 @@ bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream) {
       }
   if (!upload(c, &c->d_prime, pd) || !upload(c, &c->d_tw, tw) || !upload(c, &c->d_itw, itw) ||
       !upload(c, &c->d_modup, mu) || !upload(c, &c->d_moddown, md) || !upload(c, &c->d_msw, msw) ||
-      !upload(c, &c->d_mswpi, mswpi) || !upload(c, &c->d_tconst, tc) || !upload(c, &c->d_mdfold, mdfold))
+      !upload(c, &c->d_mswpi, mswpi) || !upload(c, &c->d_tconst, tc) || !upload(c, &c->d_mdfold, mdfold) ||
+      !upload(c, &c->d_modup_scale, mus))
     return BGV_E_DEVICE;
   if (!build_encoder(c)) { c->err = "slot encoder construction failed"; return BGV_E_PARAM; }
   // the allocation-free variant's scratch on this device (looked up once per device)
@@ -435,7 +445,8 @@ void ctx_free(bgv_ctx* c) {
   c->pool.release();
   for (auto& kv : c->coeff_tabs) (void)hipFree(kv.second);
   c->coeff_tabs.clear();
-  void* ptrs[] = {c->d_prime, c->d_tw, c->d_itw, c->d_modup, c->d_moddown, c->d_msw, c->d_mswpi, c->d_tconst, c->d_mdfold};
+  void* ptrs[] = {c->d_prime,   c->d_tw,     c->d_itw,    c->d_modup,  c->d_moddown,
+                  c->d_msw,     c->d_mswpi,  c->d_tconst, c->d_mdfold, c->d_modup_scale};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

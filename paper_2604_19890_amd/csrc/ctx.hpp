@@ -49,6 +49,7 @@ struct bgv_ctx {
   int ntt_chunk = 0;  // limbs per chunk of a two-pass NTT (0: one launch pair for all limbs)
   int ntt_split = 0;  // stages in the first of two NTT passes (0: ceil(log N / 2))
   int schedule = 0;   // polynomial evaluation schedule (BGV_SCHED_FAST / BGV_SCHED_BASIC)
+  int modup_fused = 1;  // key switching with the fused ModUp pass (1) or ModUp between full transforms (0)
   int graphs_alive = 0;  // executable graphs referring to pool buffers (trim keeps them then)
   bool capturing = false;
   hipStream_t cap_stream = nullptr;    // capture happens here (default priority, non-blocking)
@@ -67,6 +68,8 @@ struct bgv_ctx {
   // ModUp: for level l in [1, L] and digit j: inverse table [alpha] and
   // basis table [alpha][Ltot] (Qhat_i mod prime m), at offset modup_off(l, j)
   double* d_modup = nullptr;
+  // ModUp operand scales N^-1 Qhat_i^-1 mod q_i per (level, digit, source) [L+1][dnum][alpha]
+  double* d_modup_scale = nullptr;
   // ModDown: phat_inv [K], phat_mod [K][L], pinv_q [L]
   double* d_moddown = nullptr;
   // modulus switching: qinv_tab [L][L] (q_top^-1 mod q_i at [top][i])
@@ -126,7 +129,16 @@ bool ntt_fused_inner_ok(const bgv_ctx* c);
 // -> u [n][2][level+K][N].  The own-digit rows are the rows of x, the switched
 // polynomial in evaluation form ([n][level][N] at ciphertext stride x_ct_stride).
 void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,
-                         uint64_t* u, int n, int level);
+                         uint64_t* u, int n, int level, bool pass1_done = false);
+// true when the fused ModUp below applies (two-pass transforms whose first pass has 5..8
+// stages, digits of 1, 2, 4 or 6 primes)
+bool modup_cols_ok(const bgv_ctx* c);
+// From xh [n][level][N] -- x after the first pass of its inverse transform -- the ModUp output
+// y [n][dn][level+K][N] with the first forward pass done on every non-own row (as ModUp and
+// that pass would leave it); x's own-digit rows are not written
+void modup_cols(bgv_ctx* c, const uint64_t* xh, uint64_t* y, int n, int level);
+// the first pass of the inverse transform alone, from src into d
+void ntt_inverse_first_pass(bgv_ctx* c, uint64_t* d, const uint64_t* src, int n_limbs, LimbMap lm);
 // NTT over n_limbs limbs of length N at d (limb l uses the prime given by lm).
 // Epilogue of the last forward pass over rows (cc, i), i < rows, of the
 // transformed data: with e the transformed value,

@@ -123,14 +123,22 @@ static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const 
   Scratch Y(c, (size_t)n * dn * rows * N);
   Scratch Xc(c, (size_t)n * level * N);
   const bool fused = lk::ntt_fused_inner_ok(c);
+  const bool mu_fused = fused && lk::modup_cols_ok(c);
   // a digit's own rows are x as it is: the fused pass reads them from X, the
   // unfused path from a copy in Y
   if (!fused) lk::mod_up_copy_own(c, X.d, (int64_t)level * N, Y.d, n, level);
-  lk::ntt(c, Xc.d, n * level, lm_chain(c, level), true, X.d);  // coefficient form of x, out of place
-  lk::mod_up(c, Xc.d, Y.d, n, level);
+  if (mu_fused) {
+    // x's inverse transform up to its last pass (out of place), then ModUp fused with that
+    // last pass and with the first forward pass of every ModUp row
+    lk::ntt_inverse_first_pass(c, Xc.d, X.d, n * level, lm_chain(c, level));
+    lk::modup_cols(c, Xc.d, Y.d, n, level);
+  } else {
+    lk::ntt(c, Xc.d, n * level, lm_chain(c, level), true, X.d);  // coefficient form of x, out of place
+    lk::mod_up(c, Xc.d, Y.d, n, level);
+  }
   std::unique_ptr<Scratch> U(new Scratch(c, (size_t)n * 2 * rows * N));
   if (fused) {
-    lk::ntt_pass1_key_inner(c, Y.d, X.d, (int64_t)level * N, key, U->d, n, level);
+    lk::ntt_pass1_key_inner(c, Y.d, X.d, (int64_t)level * N, key, U->d, n, level, mu_fused);
   } else {
     lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0}, false);
     lk::key_inner(c, Y.d, key, U->d, n, level);
