@@ -45,21 +45,29 @@ HBM_PEAK_GBS = 8000.0
 # --steps 3` (profiles/ntt_n65536_960limbs.md).  In the same runs a 480 MiB device
 # copy reads FETCH_SIZE = 245782 KiB and WRITE_SIZE = 491520 KiB, so FETCH_SIZE counts half
 # the bytes moved (scale 2.0) and WRITE_SIZE all of them (1.0).  The figures belong to the
-# NTT sources they were taken on (hash below) and are reported only while those are unchanged.
+# sources they were taken on (hash below) and are reported only while those are unchanged.
 NTT_COUNTERS = {
-    "sources_sha256": "49663687e55e64cff561abe8304328f19f325ee18438e09bfb8417e8aa6b8316",
-    "sources": ("ntt.hip", "common.hpp"),
-    "limbs": 960,
-    "fetch_kib": [246089, 253498],
+    "sources_sha256": "055d7f862e4d7a68effcbb066e46e228860ce7ef86dfed9d67f3cbf9deb91215",
+    "sources": ('ntt.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp'),
+    "units": 960,  # limbs
+    "fetch_kib": [246089, 253499],
     "write_kib": [491520, 491520],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
 
-# HBM traffic of the product step (32 ciphertext pairs at level 30) summed over its kernels, from
-# the same two counter runs of `bench.py --ks-only` (profiles/product_step_n65536_b32.md); null
-# until taken on the current sources.
-KS_COUNTERS = None
+# HBM traffic of the product step (bgv_mul, 32 ciphertext pairs at level 30: its 11 dispatches
+# summed) from the same two counter runs of `bench.py --ks-only --cts 32 --steps 3`, with the
+# copy-derived scales (profiles/product_step_n65536_b32.md).
+KS_COUNTERS = {
+    "sources_sha256": "cc6f92503d18fd93b5bf473365d5982ddd50c81a6264d34ab27c0546928af9a4",
+    "sources": ('ntt.hip', 'keyswitch.hip', 'kernels.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp', 'ops.cpp'),
+    "units": 32,  # ciphertext pairs
+    "fetch_kib": [5365438],
+    "write_kib": [8982786],
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+}
 
 
 def sources_sha256(names):
@@ -76,7 +84,7 @@ def counter_bytes(c, units):
     if c is None or sources_sha256(c["sources"]) != c["sources_sha256"]:
         return None
     per = 1024 * (sum(c["fetch_kib"]) * c["fetch_scale"] + sum(c["write_kib"]) * c["write_scale"])
-    return per * units / c["limbs"]
+    return per * units / c["units"]
 
 
 def log(*a):

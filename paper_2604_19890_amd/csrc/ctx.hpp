@@ -139,6 +139,8 @@ bool modup_cols_ok(const bgv_ctx* c);
 void modup_cols(bgv_ctx* c, const uint64_t* xh, uint64_t* y, int n, int level);
 // the first pass of the inverse transform alone, from src into d
 void ntt_inverse_first_pass(bgv_ctx* c, uint64_t* d, const uint64_t* src, int n_limbs, LimbMap lm);
+// the first pass of the forward transform alone, in place
+void ntt_forward_first_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm);
 // NTT over n_limbs limbs of length N at d (limb l uses the prime given by lm).
 // Epilogue of the last forward pass over rows (cc, i), i < rows, of the
 // transformed data: with e the transformed value,

@@ -1,0 +1,338 @@
+// Key-switching kernels built on the transform's passes (gfx950): the ModUp fused with the
+// passes around it, and the second forward pass fused with the key inner product.
+#include "ctx.hpp"
+#include "ntt_layout.hpp"
+#include "ntt_stages.hpp"
+
+namespace {
+
+using namespace nttl;
+
+// Second forward pass fused with the key-switching inner product, over the
+// ModUp output y [n][dn][rows][N] whose first pass is done.  The rows of a
+// digit's own primes are not in y: they are the input x itself (evaluation form,
+// [n][level][N] at ciphertext stride xs) and are used as they are.  A block
+// handles one (row block, target row m, ciphertext): for every digit j it
+// finishes the transform of y[ct][j][m] in registers and LDS, multiplies it by
+// key[j][comp][prime(m)] and accumulates; u[ct][comp][m] receives the sums.
+// Block order: workgroups are dispatched round-robin over the eight XCDs, so the
+// blocks of one (row block, m) group -- which read the same key rows -- are given
+// ids with the same residue mod 8 and consecutive positions on that XCD; the key
+// rows are then read once into that XCD's L2 and shared by all ciphertexts.
+template <int LOGS>
+__global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __restrict__ y,
+                                                           const uint64_t* __restrict__ xown, int64_t xs,
+                                                           const uint64_t* __restrict__ key,
+                                                           uint64_t* __restrict__ u, int logN, int s0, int level,
+                                                           int dn, int K, int alpha, int Lfull, int Ltot, int n_ct,
+                                                           const PrimeD* __restrict__ pc,
+                                                           const double* __restrict__ tw) {
+  constexpr int S = 1 << LOGS;
+  constexpr int T = S / 16;
+  constexpr int T_LOG = LOGS - 4;
+  __shared__ double lds[NT_MAX * 16 + NT_MAX + NT_MAX];
+  const int N = 1 << logN;
+  const int NT = blockDim.x;
+  const int SUBS = NT / T;
+  const int rows = level + K;
+  const int RB = (N / S) / SUBS;  // row blocks per limb
+  const int G = RB * rows;         // (row block, m) groups
+  const int wid = blockIdx.x;
+  int g, ct;
+  if ((G & 7) == 0) {
+    const int k = wid >> 3;
+    g = (wid & 7) + 8 * (k / n_ct);
+    ct = k % n_ct;
+  } else {
+    g = wid / n_ct;
+    ct = wid % n_ct;
+  }
+  const int rb = g % RB;
+  const int m = g / RB;
+  const int pm = m < level ? m : Lfull + (m - level);
+  const double q = pc[pm].q, qinv = pc[pm].qinv;
+  const double* __restrict__ w = tw + (size_t)pm * N;
+  const int tmax_log = logN - s0 - 1;  // tmin = 1 in the second pass
+  const int tau = threadIdx.x % T;
+  const int sl = threadIdx.x / T;
+  const int st = rb * SUBS + sl;
+  const int base = st << (tmax_log + 1);
+  const int g1 = base + tau;
+  const int gs1_log = T_LOG;
+  const int g2 = base + 16 * tau;
+  double acc0[16], acc1[16], v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = 0.0;
+  // Digit j + 1's y row is requested at the start of digit j, in the same batch
+  // as digit j's twiddle loads: loads complete in issue order, so the transform
+  // waits for both, and each digit costs one round trip to memory for its data
+  // and twiddles instead of two.
+  const uint64_t* __restrict__ yrow = y + ((size_t)ct * dn * rows + m) * N + g1;
+  const size_t ystep = (size_t)rows * N;
+  const int own_j = m < level ? m / alpha : -1;  // the digit whose own prime m is
+  const uint64_t* __restrict__ xrow = xown + (size_t)ct * xs + (size_t)m * N + g1;
+  uint64_t yn[16];
+  {
+    const uint64_t* __restrict__ yp = own_j == 0 ? xrow : yrow;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) yn[i] = __builtin_nontemporal_load(&yp[(size_t)i << gs1_log]);
+  }
+  for (int j = 0; j < dn; ++j) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = u2d(yn[i]);
+    if (j + 1 < dn) {
+      const uint64_t* __restrict__ yp = own_j == j + 1 ? xrow : yrow + (size_t)(j + 1) * ystep;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) yn[i] = __builtin_nontemporal_load(&yp[(size_t)i << gs1_log]);
+    }
+    if (j != own_j) {
+      ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
+      if (T > 1) {  // with T = 1 the four register stages were all of the pass
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+        ct_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, 0, q, qinv);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
+        wave_lds_sync();  // the next digit writes the same LDS rows
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = red(v[i], q, qinv);
+    }
+    const uint64_t* __restrict__ kb = key + (((size_t)j * 2 + 0) * Ltot + pm) * N + g1;
+    const uint64_t* __restrict__ ka = key + (((size_t)j * 2 + 1) * Ltot + pm) * N + g1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      acc0[i] += mul_lazy(v[i], u2d(kb[(size_t)i << gs1_log]), q, qinv);
+      acc1[i] += mul_lazy(v[i], u2d(ka[(size_t)i << gs1_log]), q, qinv);
+    }
+    if ((j & 3) == 3) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        acc0[i] = red(acc0[i], q, qinv);
+        acc1[i] = red(acc1[i], q, qinv);
+      }
+    }
+  }
+  uint64_t* __restrict__ u0 = u + ((size_t)ct * 2 * rows + m) * N + g1;
+  uint64_t* __restrict__ u1 = u0 + (size_t)rows * N;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    u0[(size_t)i << gs1_log] = to_u(acc0[i], q, qinv);
+    u1[(size_t)i << gs1_log] = to_u(acc1[i], q, qinv);
+  }
+}
+
+// ModUp fused with the transform passes around it.  The key switch of x (evaluation form,
+// [n][level][N]) needs x in coefficient form, the ModUp of each digit to the other primes, and
+// the forward transform of every ModUp row.  After the first (contiguous) pass of x's inverse
+// transform, written to xh, a block takes one column block of one digit j of one ciphertext:
+//  * it finishes the inverse transform of the digit's source rows there (the column pass) and
+//    scales them by N^-1 Qhat_i^-1 (one folded constant per row), which gives the ModUp
+//    operands v_i = [x_i Qhat_i^-1]_{q_i} in [0, q_i); they stay in registers;
+//  * for every target row m outside the digit it forms sum_i v_i (Qhat_i mod q_m) and runs the
+//    first (column) pass of the forward transform under q_m on it, and writes y[ct][j][m].
+// y then holds what the separate ModUp and first forward pass would have written (canonical
+// residues of the same exact values), while x's coefficient form and the untransformed ModUp
+// rows are never stored.  The second pass, fused with the key inner product, follows.
+// With ALPHA = 6 the operands of the last source row are kept in LDS (each thread reads back
+// only its own words, so no barrier is needed for them): the other five rows and the working
+// registers then fit two waves per SIMD.
+template <int LOGS, int ALPHA>
+__global__ void __launch_bounds__(NT_MAX, 2) k_modup_cols(const uint64_t* __restrict__ xh, uint64_t* __restrict__ y,
+                                                       int logN, int level, int dn, int dnum, int alpha, int K,
+                                                       int Lfull, int Ltot, const double* __restrict__ mu_scale,
+                                                       const double* __restrict__ modup,
+                                                       const PrimeD* __restrict__ pc, const double* __restrict__ tw,
+                                                       const double* __restrict__ itw) {
+  constexpr int S = 1 << LOGS;
+  constexpr int T = S / 16;
+  constexpr int T_LOG = LOGS - 4;
+  __shared__ double lds[NT_MAX * 16 + NT_MAX + NT_MAX];
+  const int N = 1 << logN;
+  const int NT = blockDim.x;
+  const int SUBS = NT / T;
+  const int ct = blockIdx.y / dn;
+  const int j = blockIdx.y % dn;
+  const int lo = j * alpha;
+  const int na = min(lo + alpha, level) - lo;
+  const int rows = level + K;
+  // column pass geometry (first forward / last inverse pass: stages 0 .. LOGS-1)
+  const int tmax_log = logN - 1;
+  const int tmin_log = logN - LOGS;
+  const int sl = threadIdx.x % SUBS;
+  const int tau = threadIdx.x / SUBS;
+  const int bx = (blockIdx.x + blockIdx.y) & (gridDim.x - 1);
+  const int st = bx * SUBS + sl;
+  const int lo_c = st & ((1 << tmin_log) - 1);
+  const int hi_c = st >> tmin_log;
+  const int base = (hi_c << (tmax_log + 1)) + lo_c;
+  const int g1 = base + (tau << tmin_log);
+  const int gs1_log = T_LOG + tmin_log;
+  const int g2 = base + ((16 * tau) << tmin_log);
+  constexpr int LSRC = ALPHA == 6 ? 1 : 0;  // source rows held in LDS
+  constexpr int RSRC = ALPHA - LSRC;          // source rows held in registers
+  __shared__ double lsrc[LSRC > 0 ? LSRC * 16 * NT_MAX : 1];
+  double src[RSRC][16];
+  // tables of (level, digit): the folded scales [alpha] and ModUp's Qhat_i mod prime [alpha][Ltot]
+  const size_t tab = (size_t)level * dnum + j;
+  // ---- the digit's source rows: last inverse pass, scaled to the ModUp operands
+#pragma unroll
+  for (int a = 0; a < ALPHA; ++a) {
+    if (a < na) {
+      const int pi = lo + a;
+      const double q = pc[pi].q, qinv = pc[pi].qinv;
+      const double* __restrict__ w = itw + (size_t)pi * N;
+      const uint64_t* xp = xh + ((size_t)ct * level + pi) * N + g1;
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = u2d(__builtin_nontemporal_load(&xp[(size_t)i << gs1_log]));
+      if (T > 1) {
+        __syncthreads();  // the previous pass's last LDS reads are done
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+        gs_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, tmin_log, q, qinv);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
+      }
+      gs_stages<8>(v, w, N, g1, gs1_log, q, qinv);
+      const double sc = mu_scale[tab * alpha + a];  // N^-1 Qhat_i^-1 mod q_i
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const double o = canon(red(mul_lazy(red(v[i], q, qinv), sc, q, qinv), q, qinv), q);
+        if (a < RSRC) src[a < RSRC ? a : 0][i] = o;
+        else lsrc[((a - RSRC) * 16 + i) * NT_MAX + threadIdx.x] = o;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (a < RSRC) src[a < RSRC ? a : 0][i] = 0.0;
+        else lsrc[((a - RSRC) * 16 + i) * NT_MAX + threadIdx.x] = 0.0;
+      }
+    }
+  }
+  // ---- every target row outside the digit: ModUp value, first forward pass, store
+  const double* __restrict__ basis = modup + tab * (size_t)alpha * (1 + Ltot) + alpha;
+  uint64_t* __restrict__ yb = y + ((size_t)ct * dn + j) * rows * N + g1;
+  for (int m = 0; m < rows; ++m) {
+    if (m >= lo && m < lo + na) continue;
+    const int pm = m < level ? m : Lfull + (m - level);
+    const double q = pc[pm].q, qinv = pc[pm].qinv;
+    const double* __restrict__ w = tw + (size_t)pm * N;
+    double bm[ALPHA];
+#pragma unroll
+    for (int a = 0; a < ALPHA; ++a) bm[a] = a < na ? basis[(size_t)a * Ltot + pm] : 0.0;
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < ALPHA; ++a) {
+        if (a < na) {
+          const double x = a < RSRC ? src[a < RSRC ? a : 0][i] : lsrc[((a - RSRC) * 16 + i) * NT_MAX + threadIdx.x];
+          acc += mul_lazy(x, bm[a], q, qinv);
+        }
+      }
+      v[i] = red(acc, q, qinv);
+    }
+    ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
+    if (T > 1) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+      ct_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, tmin_log, q, qinv);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
+    }
+    uint64_t* yp = yb + (size_t)m * N;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(d2u(canon(red(v[i], q, qinv), q)), &yp[(size_t)i << gs1_log]);
+  }
+}
+
+}  // namespace
+
+namespace lk {
+
+bool ntt_fused_inner_ok(const bgv_ctx* c) { return c->logN > 8; }
+
+bool modup_cols_ok(const bgv_ctx* c) {
+  int p1, p2;
+  ntt_split(c, &p1, &p2);
+  const int A = c->alpha;
+  return c->modup_fused && p2 > 0 && p1 >= 5 && p1 <= 8 && (A == 1 || A == 2 || A == 4 || A == 6) &&
+         c->d_modup_scale != nullptr;
+}
+
+void modup_cols(bgv_ctx* c, const uint64_t* xh, uint64_t* y, int n, int level) {
+  int p1, p2;
+  ntt_split(c, &p1, &p2);
+  const int N = c->N, A = c->alpha, K = c->prm.K;
+  const int dn = (level + A - 1) / A;
+  const int S = 1 << p1, T = S / 16;
+  const int NT = N / 16 < NT_MAX ? N / 16 : NT_MAX;
+  const int SUBS = NT / T;
+  dim3 grid((N / S) / SUBS, n * dn);
+#define MU_CASE(LS, AL)                                                                                        \
+  if (p1 == LS && A == AL) {                                                                                   \
+    hipLaunchKernelGGL((k_modup_cols<LS, AL>), grid, dim3(NT), 0, c->stream, xh, y, c->logN, level, dn, c->dnum, \
+                       A, K, c->prm.L, c->Ltot, c->d_modup_scale, c->d_modup, c->d_prime, c->d_tw, c->d_itw);   \
+    return;                                                                                                    \
+  }
+#define MU_ALPHAS(LS) MU_CASE(LS, 1) MU_CASE(LS, 2) MU_CASE(LS, 4) MU_CASE(LS, 6)
+  MU_ALPHAS(5)
+  MU_ALPHAS(6)
+  MU_ALPHAS(7)
+  MU_ALPHAS(8)
+#undef MU_ALPHAS
+#undef MU_CASE
+}
+
+void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,
+                         uint64_t* u, int n, int level, bool pass1_done) {
+  const int logN = c->logN;
+  int p1, p2;
+  ntt_split(c, &p1, &p2);
+  const int A = c->alpha, K = c->prm.K, L = c->prm.L;
+  const int dn = (level + A - 1) / A, rows = level + K;
+  // first pass over the non-own rows (unless the fused ModUp has done it)
+  if (!pass1_done) ntt_forward_first_pass(c, y, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0});
+  const int N = c->N, S = 1 << p2, T = S / 16;
+  const int NT = N / 16 < NT_MAX ? N / 16 : NT_MAX;
+  const int SUBS = NT / T;
+  dim3 grid(((N / S) / SUBS) * n * rows);
+  switch (p2) {
+#define CASE2(LS)                                                                                              \
+  case LS:                                                                                                     \
+    hipLaunchKernelGGL((k_ntt2_key_inner<LS>), grid, dim3(NT), 0, c->stream, y, x, x_ct_stride, key, u, logN, p1, \
+                       level, dn, K, A, L, c->Ltot, n, c->d_prime, c->d_tw);                                   \
+    break;
+    CASE2(4)
+    CASE2(5)
+    CASE2(6)
+    CASE2(7)
+    CASE2(8)
+#undef CASE2
+    default:
+      break;
+  }
+}
+
+}  // namespace lk
