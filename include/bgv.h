@@ -259,6 +259,24 @@ bgv_status bgv_relu(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* x, bgv_ct*
 bgv_status bgv_filter_products(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* a, const bgv_ct* thr,
                                const bgv_ct* b, const bgv_ct* c, bgv_ct* out);
 
+/* bgv_filter_and_products / bgv_filter_and_sum: the multi-predicate query
+ *   SUM(b*c WHERE col_0 op_0 thr_0 AND col_1 op_1 thr_1 AND ..) (the comparison subsection's
+ *   predicate family combined by conjunction, as range filters need: lo <= a AND a < hi).
+ *   Predicate i compares cols[i] with thrs[i] (one ciphertext, or a batch of the same size):
+ *   ops[i] is BGV_OP_LT / LE / GT / GE / EQ / NEQ applied to cols[i] - thrs[i] (so BGV_OP_LT
+ *   is [col < thr]).  Each predicate is reduced and compared in the digit space; the 0/1
+ *   results are multiplied there in a balanced tree over the predicates in their order
+ *   (pairs (0,1), (2,3), .., then pairs of those), raised once and multiplied by b * c.
+ *   The depth is one reduce, compare and raise plus ceil(log2 n_pred) products, so the chain
+ *   must be that much longer than the single-predicate query's (BGV_E_LEVEL otherwise).
+ *   1 <= n_pred <= 16.  _products gives the per-ciphertext result, _sum the batch summed and
+ *   rotated so that every slot holds the total (needs the keys of bgv_rotate_sum).          */
+bgv_status bgv_filter_and_products(bgv_ctx* ctx, const bgv_keys* keys, int32_t n_pred, const bgv_ct* cols,
+                                   const bgv_ct* thrs, const int32_t* ops, const bgv_ct* b, const bgv_ct* c,
+                                   bgv_ct* out);
+bgv_status bgv_filter_and_sum(bgv_ctx* ctx, const bgv_keys* keys, int32_t n_pred, const bgv_ct* cols,
+                              const bgv_ct* thrs, const int32_t* ops, const bgv_ct* b, const bgv_ct* c, bgv_ct* out);
+
 /* ---- graph capture ---------------------------------------------------------
  * bgv_capture_begin / bgv_capture_end record every device operation the context
  * enqueues in between into an executable graph (capture in relaxed mode on a

@@ -283,6 +283,25 @@ def filter_product(P, keys, a, tq, b, c, cnt=None):
     return _mul(P, keys, less_than(P, keys, a, tq, cnt), bc, cnt)
 
 
+def filter_and_product(P, keys, preds, b, c, cnt=None):
+    """[every predicate holds] * (b * c) for one ciphertext of rows: a conjunction of the
+    comparison subsection's predicates, as range filters need (lo <= a AND a < hi).
+
+    preds: (column, threshold, op) triples; predicate i is op applied to the digits of
+    column - threshold ('lt' is [column < threshold], 'ge' is [column >= threshold], ...).  Each
+    0/1 result stays in the digit space (t = p); the conjunction is their product there, taken
+    as a balanced tree over the predicates in their order (pairs (0, 1), (2, 3), .., then pairs of
+    those); it is raised once to t = p^r and multiplied by b * c."""
+    bc = _mul(P, keys, b, c, cnt)
+    bits = [compare(P, keys, space_reduce(P, keys, B.sub(P, col, thr), cnt), op, cnt) for col, thr, op in preds]
+    while len(bits) > 1:
+        paired = [_mul(P, keys, bits[i], bits[i + 1], cnt) for i in range(0, len(bits) - 1, 2)]
+        if len(bits) % 2:
+            paired.append(bits[-1])
+        bits = paired
+    return _mul(P, keys, space_raise(P, keys, bits[0], cnt), bc, cnt)
+
+
 def rotate_and_sum(P, keys, ct):
     """Every slot ends up holding the sum of all slots: row rotations by 2^i, then the row swap."""
     i = 1

@@ -115,6 +115,8 @@ _sigs = {
     "bgv_mod_switch_noalloc": [_vp, _P(_Ct), _P(_Ct)],
     "bgv_set_ntt_coop": [_vp, _i32, _i32],
     "bgv_set_modup_fused": [_vp, _i32],
+    "bgv_filter_and_products": [_vp, _vp, _i32, _vp, _vp, _vp, _P(_Ct), _P(_Ct), _P(_Ct)],
+    "bgv_filter_and_sum": [_vp, _vp, _i32, _vp, _vp, _vp, _P(_Ct), _P(_Ct), _P(_Ct)],
     "bgv_reset_stats": [_vp],
 }
 for _name, _args in _sigs.items():
@@ -453,6 +455,24 @@ class Context:
         self._check(_lib.bgv_filter_products(self.handle, keys.handle, *[ctypes.byref(x) for x in s]))
         out._update(s[-1])
         return out
+
+    def _filter_and(self, fn, keys, preds, b, c, out):
+        """preds: list of (column batch, threshold ciphertext or batch, op code)."""
+        cols = (_Ct * len(preds))(*[p[0]._struct() for p in preds])
+        thrs = (_Ct * len(preds))(*[p[1]._struct() for p in preds])
+        ops = np.ascontiguousarray([int(p[2]) for p in preds], dtype=np.int32)
+        sb, sc, so = b._struct(), c._struct(), out._struct()
+        self._check(fn(self.handle, keys.handle, len(preds), ctypes.cast(cols, _vp), ctypes.cast(thrs, _vp),
+                       _ptr(ops), ctypes.byref(sb), ctypes.byref(sc), ctypes.byref(so)))
+        out._update(so)
+        return out
+
+    def filter_and_products(self, keys, preds, b, c, out=None):
+        return self._filter_and(_lib.bgv_filter_and_products, keys, preds, b, c,
+                                self._out(out, b.n, b.level, b.t_exp))
+
+    def filter_and_sum(self, keys, preds, b, c, out=None):
+        return self._filter_and(_lib.bgv_filter_and_sum, keys, preds, b, c, self._out(out, 1, b.level, b.t_exp))
 
     def relu(self, keys, x, out=None):
         return self._un(_lib.bgv_relu, x, out=out, keys=keys)

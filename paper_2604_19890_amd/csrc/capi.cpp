@@ -469,6 +469,53 @@ BGV_EXPORT bgv_status bgv_filter_products(bgv_ctx* c, const bgv_keys* k, const b
   });
 }
 
+static bgv_status filter_and_args(bgv_ctx* c, const bgv_keys* k, int32_t n_pred, const bgv_ct* cols,
+                                  const bgv_ct* thrs, const int32_t* ops, const bgv_ct* b, const bgv_ct* cc,
+                                  std::vector<CipherP>& vc, std::vector<CipherP>& vt, std::vector<int>& vo) {
+  if (!k || !k->relin) return fail(c, BGV_E_NOKEY, "no keys");
+  if (n_pred < 1 || n_pred > 16 || !cols || !thrs || !ops) return fail(c, BGV_E_ARG, "1 to 16 predicates");
+  CHECK(check_in(c, b, "null b"));
+  CHECK(check_in(c, cc, "null c"));
+  const int r = c->prm.r;
+  if (b->t_exp != r || cc->t_exp != r) return fail(c, BGV_E_PTXT_MOD, "the query runs on inputs tagged t = p^r");
+  if (cc->n != b->n) return fail(c, BGV_E_ARG, "batch sizes differ");
+  for (int i = 0; i < n_pred; ++i) {
+    CHECK(check_in(c, &cols[i], "null column"));
+    CHECK(check_in(c, &thrs[i], "null threshold"));
+    if (ops[i] < BGV_OP_LT || ops[i] > BGV_OP_NEQ) return fail(c, BGV_E_ARG, "bad predicate op");
+    if (cols[i].t_exp != r || thrs[i].t_exp != r) return fail(c, BGV_E_PTXT_MOD, "predicates compare values tagged t = p^r");
+    if (cols[i].n != b->n || (thrs[i].n != 1 && thrs[i].n != b->n)) return fail(c, BGV_E_ARG, "batch sizes differ");
+    if (cols[i].level != thrs[i].level) return fail(c, BGV_E_LEVEL, "a column and its threshold at different levels");
+    vc.push_back(borrow(&cols[i]));
+    vt.push_back(borrow(&thrs[i]));
+    vo.push_back(ops[i]);
+  }
+  return BGV_OK;
+}
+
+BGV_EXPORT bgv_status bgv_filter_and_products(bgv_ctx* c, const bgv_keys* k, int32_t n_pred, const bgv_ct* cols,
+                                              const bgv_ct* thrs, const int32_t* ops, const bgv_ct* b, const bgv_ct* cc,
+                                              bgv_ct* out) {
+  NEED_CTX(c);
+  std::vector<CipherP> vc, vt;
+  std::vector<int> vo;
+  CHECK(filter_and_args(c, k, n_pred, cols, thrs, ops, b, cc, vc, vt, vo));
+  return guarded(c, [&] { return deliver(c, ev_filter_and_products(c, k, vc, vt, vo, borrow(b), borrow(cc)), out); });
+}
+
+BGV_EXPORT bgv_status bgv_filter_and_sum(bgv_ctx* c, const bgv_keys* k, int32_t n_pred, const bgv_ct* cols,
+                                         const bgv_ct* thrs, const int32_t* ops, const bgv_ct* b, const bgv_ct* cc,
+                                         bgv_ct* out) {
+  NEED_CTX(c);
+  std::vector<CipherP> vc, vt;
+  std::vector<int> vo;
+  CHECK(filter_and_args(c, k, n_pred, cols, thrs, ops, b, cc, vc, vt, vo));
+  for (int i = 1; i < c->ell / 2; i *= 2)
+    if (!k->galois.count(galois_elt(c, i))) return fail(c, BGV_E_NOKEY, "missing a power-of-two rotation key");
+  if (!k->galois.count(galois_elt(c, BGV_ROW_SWAP))) return fail(c, BGV_E_NOKEY, "missing the row-swap key");
+  return guarded(c, [&] { return deliver(c, ev_filter_and_sum(c, k, vc, vt, vo, borrow(b), borrow(cc)), out); });
+}
+
 BGV_EXPORT bgv_status bgv_relu(bgv_ctx* c, const bgv_keys* k, const bgv_ct* x, bgv_ct* out) {
   NEED_CTX(c);
   if (!k || !k->relin) return fail(c, BGV_E_NOKEY, "no keys");

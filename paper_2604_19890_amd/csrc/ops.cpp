@@ -1058,6 +1058,39 @@ CipherP ev_filter_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const Cip
   return ev_rotate_sum(c, k, ev_batch_sum(c, ev_filter_products(c, k, a, thr, b, cc)));
 }
 
+// [every predicate holds] * (b * c) per ciphertext.  Predicate i compares column i with
+// threshold i: op_i applied to the digits of col_i - thr_i (reduce, then compare; the results
+// are 0/1 tagged t = p).  The conjunction is the product of those results in the digit space,
+// formed as a balanced tree over the predicates in their order (pairs (0,1), (2,3), .., then
+// pairs of those), raised once to t = p^r and multiplied by b * c.
+CipherP ev_filter_and_products(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& cols,
+                               const std::vector<CipherP>& thrs, const std::vector<int>& ops, const CipherP& b,
+                               const CipherP& cc) {
+  CipherP bc = ev_mul(c, k, b, cc);
+  std::vector<CipherP> preds;
+  for (size_t i = 0; i < cols.size(); ++i) {
+    const CipherP& x = cols[i];
+    const CipherP& y = thrs[i];
+    if (y->v.n != x->v.n && y->v.n != 1) throw OpError{BGV_E_ARG};
+    CipherP d = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
+    op_add_sub(c, x->v, y->v, d->v, 1);
+    preds.push_back(ev_compare(c, k, ev_space_reduce(c, k, d), ops[i]));
+  }
+  while (preds.size() > 1) {
+    std::vector<CipherP> next;
+    for (size_t i = 0; i + 1 < preds.size(); i += 2) next.push_back(ev_mul(c, k, preds[i], preds[i + 1]));
+    if (preds.size() % 2) next.push_back(preds.back());
+    preds.swap(next);
+  }
+  return ev_mul(c, k, ev_space_raise(c, k, preds[0]), bc);
+}
+
+CipherP ev_filter_and_sum(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& cols,
+                          const std::vector<CipherP>& thrs, const std::vector<int>& ops, const CipherP& b,
+                          const CipherP& cc) {
+  return ev_rotate_sum(c, k, ev_batch_sum(c, ev_filter_and_products(c, k, cols, thrs, ops, b, cc)));
+}
+
 CipherP ev_relu(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
   CipherP lt = ev_less_than(c, k, x, nullptr);
   return ev_mul(c, k, x, ev_const(c, ev_neg(c, lt), 1));

@@ -87,4 +87,10 @@ CipherP ev_filter_products(bgv_ctx* c, const bgv_keys* k, const CipherP& a, cons
 CipherP ev_filter_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& thr, const CipherP& b,
                       const CipherP& cc);
 CipherP ev_relu(bgv_ctx* c, const bgv_keys* k, const CipherP& x);
+CipherP ev_filter_and_products(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& cols,
+                               const std::vector<CipherP>& thrs, const std::vector<int>& ops, const CipherP& b,
+                               const CipherP& cc);
+CipherP ev_filter_and_sum(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& cols,
+                          const std::vector<CipherP>& thrs, const std::vector<int>& ops, const CipherP& b,
+                          const CipherP& cc);
 int eval_depth(int degree);

@@ -97,6 +97,10 @@ class Engine:
             self.keys = self.ctx.keygen(self.s, ka, ke, steps=STEPS, with_conj=True)
         self.wl = 40 + log_n
         self.ct_bytes = self.ctx.words(self.ctx.L) * 8
+        # NTT pass split for this ring, picked by the autotuner on a round's transform shape
+        with torch.cuda.stream(self.stream):
+            self.ntt_split, self.ntt_split_us = self.ctx.autotune_ntt(
+                min(32 << (16 - log_n), self.ctx.max_batch) * 2 * self.ctx.L, reps=3)
         self.busy = None  # (segments, event) of the round on the GPU
         self.queue = []
 
@@ -347,8 +351,8 @@ def run_mix(n_queries: int = 24, rings=(14, 15, 16), rows_lo: int = 1 << 10, row
     plain = serve(qs, engines, mode="plain")
     bad += check(qs, engines)
     log(f"[serve] plain: p50 {plain['p50_ms']:.0f} ms, p99 {plain['p99_ms']:.0f} ms, {plain['rows_per_s']:.0f} rows/s")
-    chains = {str(r): {"L": RING_CHAINS[r][0], "K": RING_CHAINS[r][1], **security_estimate(r, *RING_CHAINS[r])}
-              for r in rings}
+    chains = {str(r): {"L": RING_CHAINS[r][0], "K": RING_CHAINS[r][1], "ntt_split": engines[r].ntt_split,
+                       **security_estimate(r, *RING_CHAINS[r])} for r in rings}
     out = {"queries": len(qs), "rows": sum(q.rows for q in qs), "rows_lo": rows_lo, "rows_hi": rows_hi,
            "load_of_batched_capacity": load, "arrival_rate_qps": rate, "batched_capacity_rows_per_s": cap["rows_per_s"],
            "batched": batched, "plain": plain, "wrong_results": bad, "chains": chains}

@@ -71,3 +71,9 @@ def p257():
     """The benchmark's plaintext modulus 257^2 with its chain (30 + 6 primes) on the smallest
     ring that holds all 128 slots (N = 2^8, two coefficients per slot)."""
     return Ctx(8, 257, 2, 30, 6)
+
+
+@functools.lru_cache(maxsize=None)
+def and5():
+    """p = 5 with two spare primes for the conjunction of up to four predicates."""
+    return Ctx(4, 5, 2, 14, 1)

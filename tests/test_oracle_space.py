@@ -8,7 +8,7 @@ import pytest
 from oracle import bgv as B
 from oracle import polys
 from oracle import space as S
-from tests.oracle_ctx import p257, tiny5, tiny5_r3, tiny5_r4, tiny17, tiny37_r4
+from tests.oracle_ctx import and5, p257, tiny5, tiny5_r3, tiny5_r4, tiny17, tiny37_r4
 
 
 def _balanced_digits(v, p):
@@ -375,3 +375,33 @@ def test_space_switching_at_p257_encrypted(sched):
     assert c.dec(lt) == lt_want
     assert c.dec(eq) == [1 if v == 0 else 0 for v in vals]
     assert c.dec(rs) == lt_want
+
+
+@pytest.mark.parametrize("preds_kind", ["range", "two_columns", "three"])
+def test_filter_conjunction_brute_force(preds_kind):
+    """The conjunction of predicates (range filters) against its plain definition over Z_{p^2},
+    p = 5: every slot of the result is b * c when every predicate holds on the centered values,
+    else 0; the predicates of the comparison subsection (LT, GE, LE, NEQ, EQ)."""
+    c = and5()
+    P, t, ell = c.P, c.P.t_full, c.P.ell
+    g = np.random.default_rng(len(preds_kind))
+    cen = lambda v: _centered(v, t)
+    rel = {"lt": lambda x, y: cen(x - y) < 0, "ge": lambda x, y: cen(x - y) >= 0, "le": lambda x, y: cen(x - y) <= 0,
+           "gt": lambda x, y: cen(x - y) > 0, "eq": lambda x, y: (x - y) % t == 0, "neq": lambda x, y: (x - y) % t != 0}
+    a = [int(v) for v in g.integers(0, t, size=ell)]
+    d = [int(v) for v in g.integers(0, t, size=ell)]
+    bv = [int(v) for v in g.integers(0, t, size=ell)]
+    cv = [int(v) for v in g.integers(0, t, size=ell)]
+    if preds_kind == "range":      # lo <= a < hi
+        spec = [(a, 3, "ge"), (a, 15, "lt")]
+    elif preds_kind == "two_columns":
+        spec = [(a, 10, "le"), (d, 7, "neq")]
+    else:
+        spec = [(a, 20, "lt"), (d, 0, "ge"), (a, 2, "neq")]
+    enc_cols = {id(a): c.enc(a), id(d): c.enc(d)}
+    preds = [(enc_cols[id(col)], c.enc([thr] * ell), op) for col, thr, op in spec]
+    cnt = S.Counter()
+    out = S.filter_and_product(P, c.keys, preds, c.enc(bv), c.enc(cv), cnt)
+    want = [(bv[j] * cv[j]) % t if all(rel[op](col[j], thr) for col, thr, op in spec) else 0 for j in range(ell)]
+    assert c.dec(out) == want
+    assert out.level >= 1
