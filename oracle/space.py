@@ -18,12 +18,13 @@ which decides every ciphertext bit, is:
   outer sum over j = 1..g-1 in increasing j (each term I_j * y^j a product as
   above), operands brought to the lower level before each addition, I_0 added last.
 
-Composites (Method section, r = 2 is the built case; the loops are general):
-  space_reduce = Algorithm 3: a_i = G_{p,r-i}(b); b = DivideByP(b - a_i); then
-                 ChangeModToP on every digit;
-  compare      = Algorithm 4: LT = LT_{r-1}, EQ = EQ_{r-1}; for i = r-2..0:
-                 LT = LT + EQ * LT_i (EQ = EQ * EQ_i only while still needed);
-                 EQ_i = 1 - x_i^(p-1) with the power from the power rule;
+Composites (Method section, any r):
+  space_reduce = Algorithm 3: balanced base-p digits by recursion (the lift polynomial
+                 G_{p,e} gives the lowest digit, DivideByP of the rest recurses), each
+                 digit finally read modulo p;
+  compare      = Algorithm 4: a fold over the digits from the most significant down,
+                 state (lt, eq) absorbing each digit's (LT_i, EQ_i), EQ_i = 1 - x_i^(p-1)
+                 with the power from the power rule;
   space_raise  = RaiseModToP2R: plaintext modulus back to p^r, then G_{p,r}.
 """
 from __future__ import annotations
@@ -206,17 +207,23 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
 
 
 def space_reduce(P, keys, a, cnt=None):
-    """Algorithm 3: digits a_0..a_{r-1} of a (plaintext modulus p^r) as t = p ciphertexts."""
-    r = a.t_exp
-    b = a
-    digits = []
-    for i in range(r - 1):
-        ai = eval_poly(P, keys, b, polys.g_poly(P.p, r - i), cnt)
-        bb = B.align(P, b, ai.level)
-        b = B.divide_by_p(P, B.sub(P, bb, ai))
-        digits.append(ai)
-    digits.append(b)
-    return [B.change_mod_to_p(P, d) for d in digits]
+    """Algorithm 3: the balanced base-p digits of a value tagged t = p^e, least significant
+    first, each tagged t = p.
+
+    The lowest digit is G_{p,e} of the value (Lemma 3: the polynomial keeps the residue mod p
+    and lands on its balanced representative mod p^e).  Subtracting it leaves a multiple of p;
+    dividing by p leaves the value of the remaining digits, tagged p^(e-1), whose digits follow
+    the same way, down to a value tagged p, which is the top digit itself.  Each digit is
+    finally read modulo p alone."""
+    def digits(b):
+        e = b.t_exp
+        if e == 1:
+            return [b]
+        low = eval_poly(P, keys, b, polys.g_poly(P.p, e), cnt)
+        rest = B.divide_by_p(P, B.sub(P, B.align(P, b, low.level), low))
+        return [low] + digits(rest)
+
+    return [B.change_mod_to_p(P, d) for d in digits(a)]
 
 
 def _eq_digit(P, keys, x, cnt):
@@ -229,26 +236,31 @@ def _one_minus(P, ct):
 
 
 def compare(P, keys, digits, op="lt", cnt=None):
-    """Algorithm 4 over the digits (least significant first).
+    """Algorithm 4 over the digits (given least significant first).
 
-    op: 'lt' and 'gt' (digit polynomial F_LT or F_GT, aggregated LT = LT + EQ * LT_i),
-    'eq' (product of the digit equalities), and the complements of the comparison
+    A value is below zero exactly when its most significant nonzero balanced digit is.  Reading
+    the digits from the top down, the state (lt, eq) says whether the digits read so far are
+    below zero, and whether they are all zero; the next digit with indicators (LT_i, EQ_i)
+    moves it to (lt + eq LT_i, eq EQ_i), and the top digit's indicators start it.  LT_i is the
+    digit polynomial F_LT (F_GT for 'gt') at the digit, EQ_i = 1 - x_i^(p-1) (Fermat).  The
+    last digit's eq is never formed.
+
+    op: 'lt', 'gt', 'eq' (the fold's eq alone), and the complements of the comparison
     subsection: 'ge' = 1 - LT, 'le' = 1 - GT, 'neq' = 1 - EQ."""
-    r = len(digits)
     if op in ("ge", "le", "neq"):
         base = {"ge": "lt", "le": "gt", "neq": "eq"}[op]
         return _one_minus(P, compare(P, keys, digits, base, cnt))
+    top = len(digits) - 1
     if op == "eq":
-        eq = _eq_digit(P, keys, digits[r - 1], cnt)
-        for i in range(r - 2, -1, -1):
-            eq = _mul(P, keys, eq, _eq_digit(P, keys, digits[i], cnt), cnt)
+        eq = _eq_digit(P, keys, digits[top], cnt)
+        for x in reversed(digits[:top]):
+            eq = _mul(P, keys, eq, _eq_digit(P, keys, x, cnt), cnt)
         return eq
-    flt = polys.f_lt(P.p) if op == "lt" else polys.f_gt(P.p)
-    lts = [eval_poly(P, keys, dg, flt, cnt) for dg in digits]
-    lt = lts[r - 1]
-    eq = _eq_digit(P, keys, digits[r - 1], cnt) if r > 1 else None
-    for i in range(r - 2, -1, -1):
-        lt = _add(P, lt, _mul(P, keys, eq, lts[i], cnt))
+    f = polys.f_lt(P.p) if op == "lt" else polys.f_gt(P.p)
+    lt = eval_poly(P, keys, digits[top], f, cnt)
+    eq = _eq_digit(P, keys, digits[top], cnt) if top > 0 else None
+    for i in range(top - 1, -1, -1):
+        lt = _add(P, lt, _mul(P, keys, eq, eval_poly(P, keys, digits[i], f, cnt), cnt))
         if i > 0:
             eq = _mul(P, keys, eq, _eq_digit(P, keys, digits[i], cnt), cnt)
     return lt
