@@ -429,6 +429,8 @@ def limb_products_per_query_ct():
     count = {"prod": 0}
 
     class Fake:
+        nz = 0  # no noise estimate: every lowering takes the rescaling path (products are what is counted)
+
         def __init__(self, level, t_exp):
             self.level, self.t_exp = level, t_exp
 

@@ -72,7 +72,12 @@ typedef struct {
   int32_t n;         /* ciphertexts in the batch, 1 .. bgv_info.max_batch         */
   int32_t level;     /* active primes q_0..q_{level-1}                           */
   int32_t t_exp;     /* plaintext modulus p^t_exp                                */
-  int32_t _pad;
+  int32_t noise;     /* noise estimate: log2 of a bound on the largest coefficient of
+                        [c0 + c1 s]_Q (the plaintext included), in sixteenths of a bit;
+                        0 = unknown.  Written by every call that writes a batch (fresh
+                        encryptions get lgc(20 t)); read by the evaluator to decide how
+                        an operand reaches a lower level (below).  A batch assembled by
+                        the caller should carry the largest estimate of its parts, or 0 */
 } bgv_ct;
 
 typedef struct {
@@ -191,20 +196,25 @@ bgv_status bgv_mod_switch_to(bgv_ctx* ctx, const bgv_ct* in, int32_t level, bgv_
  *   space-switching operations included (the paper fixes only the Paterson-Stockmeyer
  *   form).  Both form baby powers x^2..x^k and giant powers y^j, y = x^k, with
  *   x^i = (x^(i/2))^2 for i a power of two, else x^h x^(i-h) (h the largest power of two
- *   below i), each product aligning its operands by single-prime switches.
+ *   below i); each product first brings its operands to the lower level, as does
+ *   each addition.
  *   BGV_SCHED_FAST (0, the default): odd-structured polynomials (every even
  *   coefficient strictly between the constant and the leading term zero) take k =
  *   the smallest power of two with k^2 >= D + 1, others 2k^2 >= D + 1; inner sums
  *   are formed at the level where the outer products meet (or lower); the products
  *   I_j y^j are aligned to their lowest common level, their tensor products summed
  *   and relinearised once, then switched once; then c_jk y^j for constant I_j in
- *   increasing j, then I_0.  A power that is itself a product (x^i, i >= 2, and the
- *   y^j) is aligned by removing its top limbs without rescaling, since its noise is
- *   already at the floor the last switch left; every other operand is switched.
+ *   increasing j, then I_0.  An operand reaches a lower level by its noise estimate
+ *   (bgv_ct.noise): while the estimate is more than 4 bits above the floor a modulus
+ *   switch leaves (lgc(3 t) - 16 + 8 log2 N), one switch of the top prime; the limbs
+ *   left above the target level are dropped without rescaling (the decryption
+ *   relation holds modulo every divisor of the modulus and the primes are 1 mod t).
+ *   An operand without an estimate (noise 0) is switched all the way.
  *   BGV_SCHED_BASIC (1): k = the smallest power of two with 2k^2 >= D + 1 for every
  *   polynomial; inner sums at the lowest level among their powers; in increasing j,
  *   I_j y^j as one product (align, relinearise, switch) or c_jk y^j, added to the
- *   running sum at the lower level; then I_0.  BGV_E_ARG for other values.
+ *   running sum at the lower level; then I_0.  Every operand reaches a lower level by
+ *   single-prime switches.  BGV_E_ARG for other values.
  * bgv_space_reduce: Algorithm 3 on a value tagged t = p^e (1 <= e <= r): e - 1 rounds
  *   of digits[i] = G_{p,e-i}(b), b <- DivideByP(b - digits[i]) (b starts as `in`),
  *   and digits[e-1] = b, all tagged t = p (ChangeModToP); the digits are the

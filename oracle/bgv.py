@@ -21,8 +21,9 @@ Readings of what the paper leaves open:
     subtracts t*w before multiplying by P^-1;
   * modulus switching drops the top prime with w = centered([c_top t^-1]_{q_top}),
     c_i <- (c_i - t w) q_top^-1; a multi-level drop is that step repeated (align);
-    drop removes top limbs without rescaling, for operands whose noise is already
-    at the floor a switch leaves (the evaluator's powers in the fast schedule).
+    drop removes top limbs without rescaling (the noise keeps its size);
+  * every ciphertext carries the noise estimate of oracle/noise.py (nz), set by
+    each operation from its inputs'.
 """
 from __future__ import annotations
 
@@ -31,6 +32,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _ring as R
+from . import noise as NZ
 from .params import Params
 
 
@@ -44,9 +46,19 @@ class Ct:
     c: np.ndarray  # uint64 [2][level][N]
     level: int
     t_exp: int
+    nz: int = 0  # noise estimate, sixteenths of a bit (0: unknown)
 
     def copy(self):
-        return Ct(self.c.copy(), self.level, self.t_exp)
+        return Ct(self.c.copy(), self.level, self.t_exp, self.nz)
+
+
+@dataclass
+class Triple:
+    """A tensor product (d0, d1, d2) before relinearisation."""
+    d: np.ndarray  # uint64 [3][level][N]
+    level: int
+    t_exp: int
+    nz: int = 0
 
 
 # ----------------------------------------------------------------------------- encoding
@@ -156,7 +168,7 @@ def encrypt(P: Params, s, slots, c1, e) -> Ct:
         c1s = _small_mul(c1[i], s64, q)
         c[0, i] = (base[i] + np.uint64(q) - c1s) % np.uint64(q)
         c[1, i] = c1[i]
-    return Ct(c, P.L, P.r)
+    return Ct(c, P.L, P.r, NZ.model(P).fresh)
 
 
 def phase(P: Params, s, ct: Ct) -> list:
@@ -200,18 +212,18 @@ def _check_pair(a: Ct, b: Ct):
 def add(P: Params, a: Ct, b: Ct) -> Ct:
     _check_pair(a, b)
     q = _qcol(P.q[: a.level])
-    return Ct((a.c + b.c) % q, a.level, a.t_exp)
+    return Ct((a.c + b.c) % q, a.level, a.t_exp, NZ.add(a.nz, b.nz))
 
 
 def sub(P: Params, a: Ct, b: Ct) -> Ct:
     _check_pair(a, b)
     q = _qcol(P.q[: a.level])
-    return Ct((a.c + (q - b.c)) % q, a.level, a.t_exp)
+    return Ct((a.c + (q - b.c)) % q, a.level, a.t_exp, NZ.add(a.nz, b.nz))
 
 
 def neg(P: Params, a: Ct) -> Ct:
     q = _qcol(P.q[: a.level])
-    return Ct((q - a.c) % q, a.level, a.t_exp)
+    return Ct((q - a.c) % q, a.level, a.t_exp, a.nz)
 
 
 def mul_scalar(P: Params, a: Ct, c: int) -> Ct:
@@ -221,7 +233,7 @@ def mul_scalar(P: Params, a: Ct, c: int) -> Ct:
     for i, q in enumerate(P.q[: a.level]):
         for k in range(2):
             out[k, i] = R.mulmod_scalar(a.c[k, i], cc % q, q)
-    return Ct(out, a.level, a.t_exp)
+    return Ct(out, a.level, a.t_exp, NZ.scalar(a.nz, cc))
 
 
 def add_const(P: Params, a: Ct, c: int) -> Ct:
@@ -231,7 +243,7 @@ def add_const(P: Params, a: Ct, c: int) -> Ct:
     out = a.c.copy()
     for i, q in enumerate(P.q[: a.level]):
         out[0, i, 0] = (int(out[0, i, 0]) + cc) % q
-    return Ct(out, a.level, a.t_exp)
+    return Ct(out, a.level, a.t_exp, NZ.add_const(a.nz, cc))
 
 
 def divide_by_p(P: Params, a: Ct) -> Ct:
@@ -243,17 +255,17 @@ def divide_by_p(P: Params, a: Ct) -> Ct:
         pinv = pow(P.p, -1, q)
         for k in range(2):
             out[k, i] = R.mulmod_scalar(a.c[k, i], pinv, q)
-    return Ct(out, a.level, a.t_exp - 1)
+    return Ct(out, a.level, a.t_exp - 1, NZ.divide_by_p(NZ.model(P), a.nz))
 
 
 def change_mod_to_p(P: Params, a: Ct) -> Ct:
     """ChangeModToP: only the plaintext modulus tag changes (Lemma 4)."""
-    return Ct(a.c.copy(), a.level, 1)
+    return Ct(a.c.copy(), a.level, 1, a.nz)
 
 
 def raise_tag(P: Params, a: Ct) -> Ct:
     """First half of modulus raising: the plaintext modulus tag becomes p^r."""
-    return Ct(a.c.copy(), a.level, P.r)
+    return Ct(a.c.copy(), a.level, P.r, a.nz)
 
 
 # ----------------------------------------------------------------------------- modulus switching
@@ -275,7 +287,7 @@ def mod_switch(P: Params, a: Ct) -> Ct:
             tw = R.mulmod_scalar(wi, t % q, q)
             diff = (a.c[k, i] + np.uint64(q) - tw) % np.uint64(q)
             out[k, i] = R.mulmod_scalar(diff, pow(qt, -1, q), q)
-    return Ct(out, lv - 1, a.t_exp)
+    return Ct(out, lv - 1, a.t_exp, NZ.switch(NZ.model(P), a.nz, a.t_exp))
 
 
 def drop(P: Params, a: Ct, level: int) -> Ct:
@@ -284,7 +296,7 @@ def drop(P: Params, a: Ct, level: int) -> Ct:
     `level` are simply removed (the noise keeps its size)."""
     if level > a.level or level < 1:
         raise ValueError("cannot raise a level")
-    return Ct(a.c[:, :level, :].copy(), level, a.t_exp)
+    return Ct(a.c[:, :level, :].copy(), level, a.t_exp, a.nz)
 
 
 def align(P: Params, a: Ct, level: int) -> Ct:
@@ -391,7 +403,7 @@ def key_switch(P: Params, x: np.ndarray, key: SwitchKey, level: int, t_exp: int)
     return mod_down(P, u[0], level, t), mod_down(P, u[1], level, t)
 
 
-def tensor(P: Params, a: Ct, b: Ct):
+def tensor(P: Params, a: Ct, b: Ct) -> Triple:
     _check_pair(a, b)
     lv = a.level
     d = np.empty((3, lv, P.N), dtype=np.uint64)
@@ -399,20 +411,21 @@ def tensor(P: Params, a: Ct, b: Ct):
         d[0, i] = R.negacyclic_dot(a.c[0, i], b.c[0, i], q)
         d[1, i] = R.negacyclic_dot(np.stack([a.c[0, i], a.c[1, i]]), np.stack([b.c[1, i], b.c[0, i]]), q)
         d[2, i] = R.negacyclic_dot(a.c[1, i], b.c[1, i], q)
-    return d
+    return Triple(d, lv, a.t_exp, NZ.tensor(NZ.model(P), a.nz, b.nz))
 
 
-def add_tensor(P: Params, d: np.ndarray, e: np.ndarray, level: int) -> np.ndarray:
+def add_tensor(P: Params, d: Triple, e: Triple, level: int) -> Triple:
     """Sum of two tensor-product triples [3][level][N] (component-wise, mod every q_i)."""
-    return (d + e) % _qcol(P.q[:level])
+    return Triple((d.d + e.d) % _qcol(P.q[:level]), level, d.t_exp, NZ.add(d.nz, e.nz))
 
 
-def relin(P: Params, rk: SwitchKey, d: np.ndarray, level: int, t_exp: int) -> Ct:
+def relin(P: Params, rk: SwitchKey, d: Triple, level: int, t_exp: int) -> Ct:
     """Relinearisation of a triple (d0, d1, d2): (d0 + u0, d1 + u1) with (u0, u1) the key
     switch of d2 (no modulus switch inside)."""
-    u0, u1 = key_switch(P, d[2], rk, level, t_exp)
+    u0, u1 = key_switch(P, d.d[2], rk, level, t_exp)
     q = _qcol(P.q[:level])
-    return Ct(np.stack([(d[0] + u0) % q, (d[1] + u1) % q]), level, t_exp)
+    return Ct(np.stack([(d.d[0] + u0) % q, (d.d[1] + u1) % q]), level, t_exp,
+              NZ.key_switch(NZ.model(P), d.nz, t_exp, level))
 
 
 def mul_relin(P: Params, rk: SwitchKey, a: Ct, b: Ct) -> Ct:
@@ -449,7 +462,7 @@ def rotate(P: Params, gk: dict, a: Ct, step) -> Ct:
     c1 = automorph_limbs(P, a.c[1], g, primes)
     u0, u1 = key_switch(P, c1, gk[g], a.level, a.t_exp)
     q = _qcol(primes)
-    return Ct(np.stack([(c0 + u0) % q, u1]), a.level, a.t_exp)
+    return Ct(np.stack([(c0 + u0) % q, u1]), a.level, a.t_exp, NZ.key_switch(NZ.model(P), a.nz, a.t_exp, a.level))
 
 
 # ----------------------------------------------------------------------------- keys

@@ -9,14 +9,20 @@ which decides every ciphertext bit, is:
   degree D, k = smallest power of two with 2 k^2 >= D + 1, g = ceil((D+1)/k);
   baby powers x^i (2 <= i <= k) and giant powers y^j (y = x^k, 2 <= j <= g-1) by the
   power rule: h = 2^floor(log2 i); x^i = x^(i/2) x^(i/2) if i = h, else x^h x^(i-h);
-  every product is: bring both operands to the lower level by single-prime
-  modulus switches, relinearised product, one modulus switch;
+  every product is: bring both operands to the lower level (below), relinearised
+  product, one modulus switch;
   inner sums I_j = sum_{i=1}^{k-1} c_{jk+i} x^i over nonzero coefficients only,
   each power first brought to the lowest level among the powers used, scalar
   products accumulated in increasing i, then the constant c_{jk} added;
   an inner sum with no power term contributes c_{jk} y^j as a scalar product;
   outer sum over j = 1..g-1 in increasing j (each term I_j * y^j a product as
   above), operands brought to the lower level before each addition, I_0 added last.
+
+Bringing an operand to a lower level: in the basic schedule by single-prime modulus
+switches; in the fast schedule by its noise estimate (oracle/noise.py): while the
+estimate is more than SLACK above the floor a switch leaves, one switch of the top
+prime, then the remaining limbs are dropped without rescaling.  Dropping leaves the
+noise as it is, which is then at most SLACK above what switches would leave.
 
 Composites (Method section, any r):
   space_reduce = Algorithm 3: balanced base-p digits by recursion (the lift polynomial
@@ -30,6 +36,7 @@ Composites (Method section, any r):
 from __future__ import annotations
 
 from . import bgv as B
+from . import noise as NZ
 from . import polys
 
 
@@ -39,28 +46,37 @@ class Counter:
         self.max_depth = 0
 
 
-def _mul(P, keys, a, b, cnt=None, da=False, db=False):
-    """a b relinearised and switched down one prime; each operand first brought to the lower
-    level by dropping limbs (da, db: a power that is itself a product, whose noise is at the
-    floor of the last switch) or by rescaling switches."""
+def _lower(P, x, level):
+    """x brought to `level` (see the module docstring)."""
+    if x.level == level:
+        return x
+    if P.schedule == "basic" or not NZ.known(x.nz):
+        return B.align(P, x, level)
+    floor = NZ.model(P).floor[x.t_exp]
+    while x.level > level and x.nz > floor + NZ.SLACK:
+        x = B.mod_switch(P, x)
+    return B.drop(P, x, level) if x.level > level else x
+
+
+def _mul(P, keys, a, b, cnt=None):
+    """a b relinearised and switched down one prime, each operand first brought to the lower
+    level."""
     lv = min(a.level, b.level)
-    a = B.drop(P, a, lv) if da else B.align(P, a, lv)
-    b = B.drop(P, b, lv) if db else B.align(P, b, lv)
+    a = _lower(P, a, lv)
+    b = _lower(P, b, lv)
     r = B.mul_relin(P, keys.relin, a, b)
     if cnt is not None:
         cnt.mul += 1
     return B.mod_switch(P, r)
 
 
-def _lazy_products(P, keys, pairs, cnt=None, drop_second=False):
-    """sum_j a_j b_j relinearised once: every operand aligned to the lowest level among the
-    pairs (b_j by dropping limbs with drop_second), the tensor products summed, one key switch
-    of the summed d2, one modulus switch."""
+def _lazy_products(P, keys, pairs, cnt=None):
+    """sum_j a_j b_j relinearised once: every operand brought to the lowest level among the
+    pairs, the tensor products summed, one key switch of the summed d2, one modulus switch."""
     lv = min(min(a.level, b.level) for a, b in pairs)
     acc = None
     for a, b in pairs:
-        bb = B.drop(P, b, lv) if drop_second else B.align(P, b, lv)
-        d = B.tensor(P, B.align(P, a, lv), bb)
+        d = B.tensor(P, _lower(P, a, lv), _lower(P, b, lv))
         acc = d if acc is None else B.add_tensor(P, acc, d, lv)
         if cnt is not None:
             cnt.mul += 1
@@ -69,7 +85,7 @@ def _lazy_products(P, keys, pairs, cnt=None, drop_second=False):
 
 def _add(P, a, b):
     lv = min(a.level, b.level)
-    return B.add(P, B.align(P, a, lv), B.align(P, b, lv))
+    return B.add(P, _lower(P, a, lv), _lower(P, b, lv))
 
 
 def odd_structured(c, D: int) -> bool:
@@ -97,21 +113,18 @@ def bsgs_shape(D: int, odd: bool = False):
     return k, g
 
 
-def _power_rule(table, i, P, keys, cnt, unit=1):
+def _power_rule(table, i, P, keys, cnt):
     """x^i = x^(i/2) x^(i/2) for i a power of two, else x^h x^(i-h) (h the largest power of two
-    below i).  table[1] is x^unit of the underlying input; in the fast schedule an operand that is
-    itself a product (exponent times unit >= 2) is aligned by dropping limbs."""
+    below i)."""
     if i in table:
         return table[i]
     h = 1 << (i.bit_length() - 1)
     if i == h:
-        half = _power_rule(table, i // 2, P, keys, cnt, unit)
+        half = _power_rule(table, i // 2, P, keys, cnt)
         table[i] = _mul(P, keys, half, half, cnt)
     else:
-        fast = P.schedule == "fast"
-        table[i] = _mul(P, keys, _power_rule(table, h, P, keys, cnt, unit),
-                        _power_rule(table, i - h, P, keys, cnt, unit), cnt,
-                        da=fast and h * unit >= 2, db=fast and (i - h) * unit >= 2)
+        table[i] = _mul(P, keys, _power_rule(table, h, P, keys, cnt),
+                        _power_rule(table, i - h, P, keys, cnt), cnt)
     return table[i]
 
 
@@ -127,8 +140,8 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
 
     "fast": with parity (the default) an odd-structured polynomial takes the odd split of
     bsgs_shape; the outer products I_j y^j are relinearised once, after their tensor products
-    are summed; the inner sums are formed at the level where those products meet; a power that
-    is itself a product is aligned by dropping limbs (drop), every other operand by rescaling.
+    are summed; the inner sums are formed at the level where those products meet; operands are
+    lowered by their noise estimates.
     "basic": the dense split for every polynomial; each inner sum at the lowest level among
     its powers; in increasing j, I_j y^j as one product (_mul) or c_jk y^j, added to the
     running sum at the lower level; then I_0."""
@@ -144,7 +157,7 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
         _power_rule(baby, i, P, keys, cnt)
     giant = {1: baby[k]}
     for j in range(2, g):
-        _power_rule(giant, j, P, keys, cnt, unit=k)
+        _power_rule(giant, j, P, keys, cnt)
 
     def coef(n):
         return c[n] if n <= D else 0
@@ -165,8 +178,7 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
         lv = own[j] if meet is None else min(own[j], meet)
         acc = None
         for i in used:
-            # a baby power that is a product (i >= 2) drops limbs in the fast schedule
-            xi = B.drop(P, baby[i], lv) if (not basic and i >= 2) else B.align(P, baby[i], lv)
+            xi = _lower(P, baby[i], lv)
             term = B.mul_scalar(P, xi, coef(j * k + i))
             acc = term if acc is None else B.add(P, acc, term)
         if const != 0:
@@ -189,7 +201,7 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
         # the products I_j y^j, relinearised once together, then the scalar multiples
         # c_jk y^j of constant inner sums in increasing j
         pairs = [(v, giant[j]) for j, (kind, v) in enumerate(inner) if j >= 1 and kind == "ct"]
-        result = _lazy_products(P, keys, pairs, cnt, drop_second=k >= 2) if pairs else None
+        result = _lazy_products(P, keys, pairs, cnt) if pairs else None
         for j in range(1, g):
             kind, v = inner[j]
             if kind == "const" and v != 0:
@@ -220,7 +232,7 @@ def space_reduce(P, keys, a, cnt=None):
         if e == 1:
             return [b]
         low = eval_poly(P, keys, b, polys.g_poly(P.p, e), cnt)
-        rest = B.divide_by_p(P, B.sub(P, B.align(P, b, low.level), low))
+        rest = B.divide_by_p(P, B.sub(P, _lower(P, b, low.level), low))
         return [low] + digits(rest)
 
     return [B.change_mod_to_p(P, d) for d in digits(a)]

@@ -45,7 +45,7 @@ class _Params(ctypes.Structure):
 
 class _Ct(ctypes.Structure):
     _fields_ = [("d", ctypes.c_void_p), ("cap_words", ctypes.c_int64), ("n", ctypes.c_int32),
-                ("level", ctypes.c_int32), ("t_exp", ctypes.c_int32), ("_pad", ctypes.c_int32)]
+                ("level", ctypes.c_int32), ("t_exp", ctypes.c_int32), ("noise", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -138,17 +138,19 @@ def _ptr(a: np.ndarray):
 
 
 class Ct:
-    """A batch of n ciphertexts in a device tensor (int64 words holding uint64 residues)."""
+    """A batch of n ciphertexts in a device tensor (int64 words holding uint64 residues).
 
-    def __init__(self, tensor: torch.Tensor, n: int, level: int, t_exp: int):
+    noise: the library's noise estimate of the batch (sixteenths of a bit, 0 = unknown)."""
+
+    def __init__(self, tensor: torch.Tensor, n: int, level: int, t_exp: int, noise: int = 0):
         self.tensor = tensor
-        self.n, self.level, self.t_exp = n, level, t_exp
+        self.n, self.level, self.t_exp, self.noise = n, level, t_exp, noise
 
     def _struct(self) -> _Ct:
-        return _Ct(self.tensor.data_ptr(), self.tensor.numel(), self.n, self.level, self.t_exp, 0)
+        return _Ct(self.tensor.data_ptr(), self.tensor.numel(), self.n, self.level, self.t_exp, self.noise)
 
     def _update(self, s: _Ct):
-        self.n, self.level, self.t_exp = s.n, s.level, s.t_exp
+        self.n, self.level, self.t_exp, self.noise = s.n, s.level, s.t_exp, s.noise
 
     def words(self, N: int) -> np.ndarray:
         """uint64 array [n][2][level][N] copied to the host."""
@@ -238,7 +240,7 @@ class Context:
     def view(self, ct: Ct, start: int, count: int) -> Ct:
         """Ciphertexts start .. start+count-1 of a batch, sharing its memory."""
         per = self.words(ct.level)
-        return Ct(ct.tensor[start * per:(start + count) * per], count, ct.level, ct.t_exp)
+        return Ct(ct.tensor[start * per:(start + count) * per], count, ct.level, ct.t_exp, ct.noise)
 
     def concat(self, parts, out: Ct = None) -> Ct:
         """Copy batches of equal level and t_exp into one contiguous batch."""
@@ -252,6 +254,8 @@ class Context:
             out.tensor[pos * per:(pos + p.n) * per].copy_(p.tensor[:p.n * per])
             pos += p.n
         out.n, out.level, out.t_exp = n, lv, te
+        # the largest estimate bounds every part (unknown if any part is)
+        out.noise = 0 if any(p.noise <= 0 for p in parts) else max(p.noise for p in parts)
         return out
 
     def sync(self):
@@ -370,7 +374,7 @@ class Context:
     def set_t_exp(self, a: Ct, t_exp: int) -> Ct:
         s = a._struct()
         self._check(_lib.bgv_set_t_exp(self.handle, ctypes.byref(s), t_exp))
-        return Ct(a.tensor, a.n, a.level, t_exp)
+        return Ct(a.tensor, a.n, a.level, t_exp, a.noise)
 
     def rotate(self, keys, a, step: int, out=None):
         return self._un(_lib.bgv_rotate, a, ctypes.c_int32(step), out=out, keys=keys)

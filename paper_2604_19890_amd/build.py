@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbgv.so")
-SOURCES = ["ntt.hip", "keyswitch.hip", "kernels.hip", "ctx.cpp", "ops.cpp", "capi.cpp"]
+SOURCES = ["ntt.hip", "keyswitch.hip", "kernels.hip", "ctx.cpp", "ops.cpp", "noise.cpp", "capi.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off", "-fvisibility=hidden",

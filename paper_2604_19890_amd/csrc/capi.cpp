@@ -38,13 +38,15 @@ CtV view(const bgv_ct* x) {
   v.n = x->n;
   v.level = x->level;
   v.t_exp = x->t_exp;
+  v.nz = x->noise > 0 ? x->noise : 0;
   return v;
 }
 
-void set_out(bgv_ct* out, int n, int level, int t_exp) {
+void set_out(bgv_ct* out, int n, int level, int t_exp, int nz) {
   out->n = n;
   out->level = level;
   out->t_exp = t_exp;
+  out->noise = nz;
 }
 
 CipherP borrow(const bgv_ct* x) {
@@ -57,10 +59,11 @@ CipherP borrow(const bgv_ct* x) {
 bgv_status deliver(bgv_ctx* c, const CipherP& r, bgv_ct* out) {
   bgv_status st = check_out(c, out, r->v.n, r->v.level);
   if (st != BGV_OK) return st;
-  CtV o = r->v;
+  const CipherP flat = ev_materialize(c, r);  // a view of a deeper batch's lower limbs is copied first
+  CtV o = flat->v;
   o.d = out->d;
-  op_copy(c, r->v, o);
-  set_out(out, r->v.n, r->v.level, r->v.t_exp);
+  op_copy(c, flat->v, o);
+  set_out(out, r->v.n, r->v.level, r->v.t_exp, r->v.nz);
   return BGV_OK;
 }
 
@@ -210,7 +213,7 @@ BGV_EXPORT bgv_status bgv_encrypt(bgv_ctx* c, const int8_t* s, const uint64_t* s
   if (!s || !slots || !c1 || !e || !out || out->n < 1) return fail(c, BGV_E_ARG, "bad encrypt arguments");
   if (out->n > c->max_batch()) return fail(c, BGV_E_ARG, "batch count above the context's max_batch");
   CHECK(check_out(c, out, out->n, c->prm.L));
-  set_out(out, out->n, c->prm.L, c->prm.r);
+  set_out(out, out->n, c->prm.L, c->prm.r, c->nzm.fresh);
   return guarded(c, [&] { return op_encrypt(c, s, slots, c1, e, view(out)); });
 }
 
@@ -241,7 +244,7 @@ static bgv_status addsub(bgv_ctx* c, const bgv_ct* a, const bgv_ct* b, bgv_ct* o
     op_add_sub(c, view(&A), view(&B), o, op);
     return BGV_OK;
   });
-  if (st == BGV_OK) set_out(out, A.n, A.level, A.t_exp);
+  if (st == BGV_OK) set_out(out, A.n, A.level, A.t_exp, nz_add(view(&A).nz, view(&B).nz));
   return st;
 }
 
@@ -249,7 +252,7 @@ BGV_EXPORT bgv_status bgv_add(bgv_ctx* c, const bgv_ct* a, const bgv_ct* b, bgv_
 BGV_EXPORT bgv_status bgv_sub(bgv_ctx* c, const bgv_ct* a, const bgv_ct* b, bgv_ct* out) { return addsub(c, a, b, out, 1); }
 
 template <class F>
-static bgv_status unary(bgv_ctx* c, const bgv_ct* a, bgv_ct* out, int out_level, int out_t, F f) {
+static bgv_status unary(bgv_ctx* c, const bgv_ct* a, bgv_ct* out, int out_level, int out_t, int out_nz, F f) {
   NEED_CTX(c);
   CHECK(check_in(c, a, "null input"));
   CHECK(check_out(c, out, a->n, out_level));
@@ -262,29 +265,34 @@ static bgv_status unary(bgv_ctx* c, const bgv_ct* a, bgv_ct* out, int out_level,
     f(view(&A), o);
     return BGV_OK;
   });
-  if (st == BGV_OK) set_out(out, A.n, out_level, out_t);
+  if (st == BGV_OK) set_out(out, A.n, out_level, out_t, out_nz);
   return st;
 }
 
 BGV_EXPORT bgv_status bgv_negate(bgv_ctx* c, const bgv_ct* a, bgv_ct* out) {
-  if (!a) return BGV_E_ARG;
-  return unary(c, a, out, a->level, a->t_exp, [&](const CtV& x, const CtV& o) { op_negate(c, x, o); });
+  if (!a || !c) return BGV_E_ARG;
+  return unary(c, a, out, a->level, a->t_exp, view(a).nz, [&](const CtV& x, const CtV& o) { op_negate(c, x, o); });
 }
 
 BGV_EXPORT bgv_status bgv_mul_scalar(bgv_ctx* c, const bgv_ct* a, int64_t k, bgv_ct* out) {
-  if (!a) return BGV_E_ARG;
-  return unary(c, a, out, a->level, a->t_exp, [&](const CtV& x, const CtV& o) { op_mul_scalar(c, x, k, o); });
+  if (!a || !c) return BGV_E_ARG;
+  if (a->t_exp < 1 || a->t_exp > c->prm.r) return fail(c, BGV_E_PTXT_MOD, "t_exp out of range");
+  const int nz = nz_scalar(view(a).nz, hnt::centered(k, c->tpow[a->t_exp]));
+  return unary(c, a, out, a->level, a->t_exp, nz, [&](const CtV& x, const CtV& o) { op_mul_scalar(c, x, k, o); });
 }
 
 BGV_EXPORT bgv_status bgv_add_const(bgv_ctx* c, const bgv_ct* a, int64_t k, bgv_ct* out) {
-  if (!a) return BGV_E_ARG;
-  return unary(c, a, out, a->level, a->t_exp, [&](const CtV& x, const CtV& o) { op_add_const(c, x, k, o); });
+  if (!a || !c) return BGV_E_ARG;
+  if (a->t_exp < 1 || a->t_exp > c->prm.r) return fail(c, BGV_E_PTXT_MOD, "t_exp out of range");
+  const int nz = nz_add_const(view(a).nz, hnt::centered(k, c->tpow[a->t_exp]));
+  return unary(c, a, out, a->level, a->t_exp, nz, [&](const CtV& x, const CtV& o) { op_add_const(c, x, k, o); });
 }
 
 BGV_EXPORT bgv_status bgv_divide_by_p(bgv_ctx* c, const bgv_ct* a, bgv_ct* out) {
-  if (!a) return BGV_E_ARG;
+  if (!a || !c) return BGV_E_ARG;
   if (a->t_exp < 2) return fail(c, BGV_E_PTXT_MOD, "DivideByP needs t = p^k with k >= 2");
-  return unary(c, a, out, a->level, a->t_exp - 1, [&](const CtV& x, const CtV& o) { op_divide_by_p(c, x, o); });
+  return unary(c, a, out, a->level, a->t_exp - 1, nz_divide_by_p(c, view(a).nz),
+               [&](const CtV& x, const CtV& o) { op_divide_by_p(c, x, o); });
 }
 
 BGV_EXPORT bgv_status bgv_set_t_exp(bgv_ctx* c, bgv_ct* ct, int32_t t_exp) {
@@ -307,7 +315,9 @@ BGV_EXPORT bgv_status bgv_mul_relin(bgv_ctx* c, const bgv_keys* k, const bgv_ct*
     op_mul_relin(c, k, view(&A), view(&B), o);
     return BGV_OK;
   });
-  if (st == BGV_OK) set_out(out, A.n, A.level, A.t_exp);
+  if (st == BGV_OK)
+    set_out(out, A.n, A.level, A.t_exp,
+            nz_key_switch(c, nz_tensor(c, view(&A).nz, view(&B).nz), A.t_exp, A.level));
   return st;
 }
 
@@ -317,14 +327,16 @@ BGV_EXPORT bgv_status bgv_rotate(bgv_ctx* c, const bgv_keys* k, const bgv_ct* in
   CHECK(check_in(c, in, "null input"));
   const int g = galois_elt(c, step);
   if (!k->galois.count(g)) return fail(c, BGV_E_NOKEY, "no Galois key for this rotation");
-  return unary(c, in, out, in->level, in->t_exp, [&](const CtV& x, const CtV& o) { op_rotate(c, k, x, g, o); });
+  return unary(c, in, out, in->level, in->t_exp, nz_key_switch(c, view(in).nz, in->t_exp, in->level),
+               [&](const CtV& x, const CtV& o) { op_rotate(c, k, x, g, o); });
 }
 
 BGV_EXPORT bgv_status bgv_mod_switch(bgv_ctx* c, const bgv_ct* in, bgv_ct* out) {
   NEED_CTX(c);
   CHECK(check_in(c, in, "null input"));
   if (in->level < 2) return fail(c, BGV_E_LEVEL, "no prime left to drop");
-  return unary(c, in, out, in->level - 1, in->t_exp, [&](const CtV& x, const CtV& o) { op_mod_switch(c, x, o); });
+  return unary(c, in, out, in->level - 1, in->t_exp, nz_switch(c, view(in).nz, in->t_exp),
+               [&](const CtV& x, const CtV& o) { op_mod_switch(c, x, o); });
 }
 
 BGV_EXPORT bgv_status bgv_mod_switch_noalloc(bgv_ctx* c, const bgv_ct* in, bgv_ct* out) {
@@ -339,7 +351,7 @@ BGV_EXPORT bgv_status bgv_mod_switch_noalloc(bgv_ctx* c, const bgv_ct* in, bgv_c
     return fail(c, BGV_E_ARG, "the switch needs more scratch than the allocation-free variant holds");
   uint64_t* T = c->noalloc_scratch;
   uint64_t* W = T + t_words;
-  return unary(c, in, out, in->level - 1, in->t_exp,
+  return unary(c, in, out, in->level - 1, in->t_exp, nz_switch(c, view(in).nz, in->t_exp),
                [&](const CtV& x, const CtV& o) { op_mod_switch_with(c, x, o, T, W); });
 }
 
@@ -347,7 +359,9 @@ BGV_EXPORT bgv_status bgv_mod_switch_to(bgv_ctx* c, const bgv_ct* in, int32_t le
   NEED_CTX(c);
   CHECK(check_in(c, in, "null input"));
   if (level < 1 || level > in->level) return fail(c, BGV_E_LEVEL, "target level out of range");
-  return unary(c, in, out, level, in->t_exp, [&](const CtV& x, const CtV& o) { op_mod_switch_to(c, x, level, o); });
+  int nz = view(in).nz;
+  for (int l = in->level; l > level; --l) nz = nz_switch(c, nz, in->t_exp);
+  return unary(c, in, out, level, in->t_exp, nz, [&](const CtV& x, const CtV& o) { op_mod_switch_to(c, x, level, o); });
 }
 
 BGV_EXPORT bgv_status bgv_eval_poly(bgv_ctx* c, const bgv_keys* k, const bgv_ct* in, const int64_t* coeffs,

@@ -434,6 +434,7 @@ bgv_status ctx_build(bgv_ctx* c, const bgv_params* prm, hipStream_t stream) {
       !upload(c, &c->d_modup_scale, mus))
     return BGV_E_DEVICE;
   if (!build_encoder(c)) { c->err = "slot encoder construction failed"; return BGV_E_PARAM; }
+  noise_init(c);
   // the allocation-free variant's scratch on this device (looked up once per device)
   c->noalloc_scratch = noalloc_scratch_ptr(&c->device);
   return BGV_OK;

@@ -37,6 +37,17 @@ struct Stats {
   int32_t max_tensor_pairs = 0;
 };
 
+// Noise estimate model (sixteenths of a bit): the estimate of a fresh encryption, floor(16
+// log2) of the smallest ciphertext prime and of p, and per plaintext exponent e the floor a
+// modulus switch leaves and, per level, what one key switch adds.
+constexpr int NZ_UNIT = 16;
+constexpr int NZ_SLACK = 4 * NZ_UNIT;  // lowered by dropping limbs within this of the switch floor
+struct NoiseModel {
+  int fresh = 0, q16 = 0, lgp = 0;
+  std::vector<int> floor;            // [r+1]
+  std::vector<std::vector<int>> ks;  // [r+1][L+1]
+};
+
 struct bgv_ctx {
   bgv_params prm;
   int N = 0, logN = 0, ell = 0, dslot = 0, alpha = 0, dnum = 0, Ltot = 0;
@@ -56,6 +67,7 @@ struct bgv_ctx {
   hipStream_t saved_stream = nullptr;  // the context stream while capturing
   DevPool pool;
   Stats stats;
+  NoiseModel nzm;
   // device address of the allocation-free variant's scratch on this context's device
   // (looked up once per device at context creation; null if the lookup failed)
   uint64_t* noalloc_scratch = nullptr;
@@ -164,8 +176,8 @@ void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse, const u
          const NttEpi* epi = nullptr);
 
 // out = a (op) b elementwise per limb; op 0 add, 1 sub; b_bcast: b has one ciphertext
-void add_sub(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n, int level, int op,
-             bool b_bcast);
+void add_sub(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n, int level, int op, bool b_bcast,
+             int sa, int sb);
 void negate(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level);
 // out = a * s_i per limb (s per prime given as a double table of size level)
 void mul_scalar(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level, const double* s_host);

@@ -19,19 +19,21 @@ struct Tab64 {
 inline dim3 grid_for(int N, int y, int z = 1) { return dim3(N >= BS ? N / BS : 1, y, z); }
 inline int block_for(int N) { return N >= BS ? BS : N; }
 
+// a and b may be views of the lower `level` limbs of deeper batches: sa / sb limbs per
+// polynomial in memory (the output is contiguous)
 __global__ void k_add_sub(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b, uint64_t* __restrict__ out,
-                          int level, int N, int op, int b_bcast, const PrimeD* __restrict__ pc) {
+                          int level, int N, int op, int b_bcast, int sa, int sb, const PrimeD* __restrict__ pc) {
   const int limb = blockIdx.y;
-  const int pi = limb % level;
+  const int poly = limb / level, pi = limb - poly * level;
   const double q = pc[pi].q;
   const size_t n0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t ia = (size_t)limb * N + n0;
-  const size_t ib = (size_t)(b_bcast ? limb % (2 * level) : limb) * N + n0;
+  const size_t ia = ((size_t)poly * sa + pi) * N + n0;
+  const size_t ib = ((size_t)(b_bcast ? poly % 2 : poly) * sb + pi) * N + n0;
   double x = u2d(a[ia]), y = u2d(b[ib]);
   double r = op == 0 ? x + y : x - y;
   r = r >= q ? r - q : r;
   r = r < 0.0 ? r + q : r;
-  out[ia] = d2u(r);
+  out[(size_t)limb * N + n0] = d2u(r);
 }
 
 __global__ void k_negate(const uint64_t* __restrict__ a, uint64_t* __restrict__ out, int level, int N,
@@ -614,9 +616,10 @@ __global__ void k_mul_pointwise(const uint64_t* __restrict__ a, const uint64_t* 
 
 namespace lk {
 
-void add_sub(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n, int level, int op, bool bb) {
+void add_sub(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n, int level, int op, bool bb, int sa,
+             int sb) {
   hipLaunchKernelGGL(k_add_sub, grid_for(c->N, n * 2 * level), dim3(block_for(c->N)), 0, c->stream, a, b, out, level,
-                     c->N, op, bb ? 1 : 0, c->d_prime);
+                     c->N, op, bb ? 1 : 0, sa, sb, c->d_prime);
 }
 
 void negate(bgv_ctx* c, const uint64_t* a, uint64_t* out, int n, int level) {

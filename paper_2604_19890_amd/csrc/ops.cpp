@@ -75,7 +75,7 @@ void op_ntt(bgv_ctx* c, uint64_t* d, int n_polys, int level, bool inverse) {
 
 void op_add_sub(bgv_ctx* c, const CtV& a, const CtV& b, const CtV& out, int op) {
   algo(c, 6.0 * a.level * a.n);
-  lk::add_sub(c, a.d, b.d, out.d, a.n, a.level, op, b.n == 1 && a.n > 1);
+  lk::add_sub(c, a.d, b.d, out.d, a.n, a.level, op, b.n == 1 && a.n > 1, lstride(a), lstride(b));
 }
 
 void op_negate(bgv_ctx* c, const CtV& a, const CtV& out) {
@@ -218,13 +218,11 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
   relin_ms(c, keys, D, X, n, lv, a.t_exp, out);
 }
 
-static CipherP ev_drop(bgv_ctx* c, const CipherP& x, int level);
+static CipherP ev_lower(bgv_ctx* c, const CipherP& x, int level);
 
-// sum_j a_j b_j relinearised once: every operand aligned to the lowest level among the
-// pairs (b_j by dropping limbs when drop_second), the tensor products accumulated, one key
-// switch and one modulus switch.
-static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector<std::pair<CipherP, CipherP>>& pairs,
-                                bool drop_second) {
+// sum_j a_j b_j relinearised once: every operand brought to the lowest level among the
+// pairs, the tensor products accumulated, one key switch and one modulus switch.
+static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector<std::pair<CipherP, CipherP>>& pairs) {
   int lv = 1 << 30, n = 1;
   for (const auto& pr : pairs) {
     lv = std::min(lv, std::min(pr.first->v.level, pr.second->v.level));
@@ -236,14 +234,17 @@ static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector
   const int t_exp = pairs[0].first->v.t_exp, N = c->N;
   algo(c, (4.0 * lv * pairs.size() + 2.0 * (lv - 1)) * n + key_limbs(c, lv));
   Scratch D(c, (size_t)n * 2 * lv * N), X(c, (size_t)n * lv * N);
+  int nz = 0;  // the tensor estimates accumulated in the pairs' order
   // the pairs' tensor products summed in passes of at most TS_MAX pairs (each operand read once)
   for (size_t s0 = 0; s0 < pairs.size(); s0 += lk::TS_MAX) {
     const int np = (int)std::min<size_t>(lk::TS_MAX, pairs.size() - s0);
     std::vector<CipherP> keep;
     lk::TensorPairs tp{};
     for (int t = 0; t < np; ++t) {
-      CipherP a = ev_align(c, pairs[s0 + t].first, lv);
-      CipherP b = drop_second ? ev_drop(c, pairs[s0 + t].second, lv) : ev_align(c, pairs[s0 + t].second, lv);
+      CipherP a = ev_lower(c, pairs[s0 + t].first, lv);
+      CipherP b = ev_lower(c, pairs[s0 + t].second, lv);
+      const int tz = nz_tensor(c, a->v.nz, b->v.nz);
+      nz = s0 + t == 0 ? tz : nz_add(nz, tz);
       if (a->v.n == 1 && n > 1) std::swap(a, b);
       tp.a[t] = a->v.d;
       tp.b[t] = b->v.d;
@@ -258,6 +259,7 @@ static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector
   }
   CipherP r = new_cipher(c, n, lv - 1, t_exp);
   relin_ms(c, k, D, X, n, lv, t_exp, r->v);
+  r->v.nz = nz_switch(c, nz_key_switch(c, nz, t_exp, lv), t_exp);
   return r;
 }
 
@@ -568,11 +570,17 @@ bgv_status op_keygen(bgv_ctx* c, const int8_t* s, const uint64_t* a, const int32
 
 // ------------------------------------------------------------------ evaluator
 
+
+// x brought to `level` by single-prime rescaling switches
 CipherP ev_align(bgv_ctx* c, const CipherP& x, int level) {
   if (x->v.level == level) return x;
   if (level > x->v.level || level < 1) throw OpError{BGV_E_LEVEL};
+  const CipherP src = ev_materialize(c, x);  // the switch reads whole polynomials
   CipherP r = new_cipher(c, x->v.n, level, x->v.t_exp);
-  op_mod_switch_to(c, x->v, level, r->v);
+  op_mod_switch_to(c, src->v, level, r->v);
+  int nz = x->v.nz;
+  for (int l = x->v.level; l > level; --l) nz = nz_switch(c, nz, x->v.t_exp);
+  r->v.nz = nz;
   return r;
 }
 
@@ -587,10 +595,9 @@ static CipherP with_t(const CipherP& x, int t_exp) {
 // The ciphertext reduced modulo its first `level` primes: the top limbs are dropped
 // without rescaling (the decryption relation holds modulo every divisor of the
 // modulus, and the primes are 1 mod t, so the message is unchanged).  The noise
-// keeps its size, which equals what a rescaling switch leaves for a ciphertext whose
-// noise is already at the floor of the last switch: a power that is itself a product.
-// The result is a view of x's lower limbs (no copy, polynomial stride x's); only the
-// tensor kernels and the inner sums read views, and ev_materialize copies one.
+// keeps its size.  The result is a view of x's lower limbs (no copy, polynomial stride
+// x's); the tensor kernels, the inner sums and additions read views, and
+// ev_materialize copies one for the other operations.
 static CipherP ev_drop(bgv_ctx* c, const CipherP& x, int level) {
   if (x->v.level == level) return x;
   if (level > x->v.level || level < 1) throw OpError{BGV_E_LEVEL};
@@ -603,9 +610,10 @@ static CipherP ev_drop(bgv_ctx* c, const CipherP& x, int level) {
   return r;
 }
 
-static CipherP ev_materialize(bgv_ctx* c, const CipherP& x) {
+CipherP ev_materialize(bgv_ctx* c, const CipherP& x) {
   if (lstride(x->v) == x->v.level) return x;
   CipherP r = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
+  r->v.nz = x->v.nz;
   const size_t N = c->N;
   check_hip(c,
             hipMemcpy2DAsync(r->v.d, (size_t)x->v.level * N * 8, x->v.d, (size_t)lstride(x->v) * N * 8,
@@ -614,79 +622,86 @@ static CipherP ev_materialize(bgv_ctx* c, const CipherP& x) {
   return r;
 }
 
-// a * b with each operand brought to the lower level by dropping limbs (da, db) or by
-// rescaling switches
-static CipherP ev_mul_pw(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& b, bool da, bool db) {
-  const int lv = std::min(a->v.level, b->v.level);
-  if (lv < 2) throw OpError{BGV_E_LEVEL};
-  if (a->v.t_exp != b->v.t_exp) throw OpError{BGV_E_PTXT_MOD};
-  CipherP a2 = da ? ev_drop(c, a, lv) : ev_align(c, a, lv);
-  CipherP b2 = db ? ev_drop(c, b, lv) : ev_align(c, b, lv);
-  const int n = std::max(a->v.n, b->v.n);
-  CipherP r = new_cipher(c, n, lv - 1, a->v.t_exp);
-  if (a2->v.n == 1 && n > 1) op_mul_ms(c, k, b2->v, a2->v, r->v);
-  else op_mul_ms(c, k, a2->v, b2->v, r->v);
-  return r;
+// x brought to `level`.  In the basic schedule, or without a noise estimate, by
+// single-prime rescaling switches.  In the fast schedule by the estimate: while it is more
+// than NZ_SLACK above the floor a switch leaves, one switch of the top prime; the limbs
+// left above `level` are dropped without rescaling (their noise is then within NZ_SLACK
+// of what further switches would leave).
+static CipherP ev_lower(bgv_ctx* c, const CipherP& x, int level) {
+  if (x->v.level == level) return x;
+  if (level > x->v.level || level < 1) throw OpError{BGV_E_LEVEL};
+  if (c->schedule == BGV_SCHED_BASIC || x->v.nz <= 0) return ev_align(c, x, level);
+  const int te = x->v.t_exp, limit = c->nzm.floor[te] + NZ_SLACK;
+  int m = 0;
+  for (int e = x->v.nz; m < x->v.level - level && e > limit; ++m) e = nz_switch(c, e, te);
+  const CipherP y = m ? ev_align(c, x, x->v.level - m) : x;
+  return ev_drop(c, y, level);
 }
 
+// a * b relinearised and switched down one prime, each operand first brought to the lower level
 CipherP ev_mul(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& b) {
   const int lv = std::min(a->v.level, b->v.level);
   if (lv < 2) throw OpError{BGV_E_LEVEL};
   if (a->v.t_exp != b->v.t_exp) throw OpError{BGV_E_PTXT_MOD};
-  CipherP a2 = ev_align(c, a, lv), b2 = ev_align(c, b, lv);
+  CipherP a2 = ev_lower(c, a, lv), b2 = ev_lower(c, b, lv);
   const int n = std::max(a->v.n, b->v.n);
   CipherP r = new_cipher(c, n, lv - 1, a->v.t_exp);
   if (a2->v.n == 1 && n > 1) op_mul_ms(c, k, b2->v, a2->v, r->v);
   else op_mul_ms(c, k, a2->v, b2->v, r->v);
+  r->v.nz = nz_mul_ms(c, a2->v.nz, b2->v.nz, a->v.t_exp, lv);
   return r;
 }
 
 CipherP ev_add(bgv_ctx* c, const CipherP& a, const CipherP& b) {
   const int lv = std::min(a->v.level, b->v.level);
   if (a->v.t_exp != b->v.t_exp) throw OpError{BGV_E_PTXT_MOD};
-  CipherP a2 = ev_align(c, a, lv), b2 = ev_align(c, b, lv);
+  CipherP a2 = ev_lower(c, a, lv), b2 = ev_lower(c, b, lv);
   const int n = std::max(a->v.n, b->v.n);
   CipherP r = new_cipher(c, n, lv, a->v.t_exp);
   if (a2->v.n == 1 && n > 1) op_add_sub(c, b2->v, a2->v, r->v, 0);
   else op_add_sub(c, a2->v, b2->v, r->v, 0);
+  r->v.nz = nz_add(a2->v.nz, b2->v.nz);
   return r;
 }
 
-static CipherP ev_scalar(bgv_ctx* c, const CipherP& x, int64_t k) {
+static CipherP ev_scalar(bgv_ctx* c, const CipherP& x0, int64_t k) {
+  const CipherP x = ev_materialize(c, x0);
   CipherP r = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
   op_mul_scalar(c, x->v, k, r->v);
+  r->v.nz = nz_scalar(x->v.nz, centered(k, c->tpow[x->v.t_exp]));
   return r;
 }
 
-static CipherP ev_const(bgv_ctx* c, const CipherP& x, int64_t k) {
+static CipherP ev_const(bgv_ctx* c, const CipherP& x0, int64_t k) {
+  const CipherP x = ev_materialize(c, x0);
   CipherP r = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
   op_add_const(c, x->v, k, r->v);
+  r->v.nz = nz_add_const(x->v.nz, centered(k, c->tpow[x->v.t_exp]));
   return r;
 }
 
-static CipherP ev_neg(bgv_ctx* c, const CipherP& x) {
+static CipherP ev_neg(bgv_ctx* c, const CipherP& x0) {
+  const CipherP x = ev_materialize(c, x0);
   CipherP r = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
   op_negate(c, x->v, r->v);
+  r->v.nz = x->v.nz;
   return r;
 }
 
 // x^i by the power rule: h = 2^floor(log2 i); x^i = x^(i/2) x^(i/2) if i = h, else x^h x^(i-h).
-// tab[1] is x^unit of the underlying input; in the fast schedule an operand that is
-// itself a product (exponent h unit >= 2) is aligned by dropping limbs.
-static const CipherP& power(bgv_ctx* c, const bgv_keys* k, std::map<int, CipherP>& tab, int i, int unit = 1) {
+static const CipherP& power(bgv_ctx* c, const bgv_keys* k, std::map<int, CipherP>& tab, int i) {
   auto it = tab.find(i);
   if (it != tab.end()) return it->second;
   int h = 1;
   while (2 * h <= i) h *= 2;
   CipherP r;
   if (i == h) {
-    const CipherP& half = power(c, k, tab, i / 2, unit);
+    const CipherP& half = power(c, k, tab, i / 2);
     r = ev_mul(c, k, half, half);
   } else {
-    const CipherP& a = power(c, k, tab, h, unit);
-    const CipherP& b = power(c, k, tab, i - h, unit);
-    const bool drop = c->schedule == BGV_SCHED_FAST;
-    r = ev_mul_pw(c, k, a, b, drop && h * unit >= 2, drop && (i - h) * unit >= 2);
+    const CipherP& a = power(c, k, tab, h);
+    const CipherP& b = power(c, k, tab, i - h);
+    r = ev_mul(c, k, a, b);
   }
   return tab[i] = r;
 }
@@ -797,17 +812,29 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   std::map<int, CipherP> giant;
   giant[1] = baby[kk];
   for (int j = 2; j < g; ++j)
-    if (need_g[j]) power(c, k, giant, j, kk);
+    if (need_g[j]) power(c, k, giant, j);
 
   std::map<std::pair<int, int>, CipherP> aligned;
   auto aligned_power = [&](int i, int lv) -> CipherP {
     auto key = std::make_pair(i, lv);
     auto it = aligned.find(key);
     if (it != aligned.end()) return it->second;
-    // a baby power that is a product (i >= 2) drops limbs in the fast schedule
-    CipherP r = (!basic && i >= 2) ? ev_drop(c, baby[i], lv) : ev_align(c, baby[i], lv);
+    CipherP r = ev_lower(c, baby[i], lv);
     aligned[key] = r;
     return r;
+  };
+  // an inner sum's estimate: its scalar terms accumulated in increasing i, then the constant
+  const int64_t tt = c->tpow[x->v.t_exp];
+  auto inner_nz = [&](int j, int lv, const std::vector<int>& terms_used) {
+    int nz = 0;
+    bool first = true;
+    for (int i : terms_used) {
+      const int tz = nz_scalar(aligned_power(i, lv)->v.nz, centered(coef(j * kk + i), tt));
+      nz = first ? tz : nz_add(nz, tz);
+      first = false;
+    }
+    if (coef(j * kk) != 0) nz = nz_add_const(nz, centered(coef(j * kk), tt));
+    return nz;
   };
 
   struct Inner {
@@ -864,6 +891,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
           for (size_t t = 0; t < terms.size(); ++t)
             m.row[o][t] = coef(j * kk + terms[t]) != 0 ? j * kk + terms[t] : -1;
           m.cst_row[o] = coef(j * kk) != 0 ? j * kk : -1;
+          acc->v.nz = inner_nz(j, lv, used[j]);
           inner[j] = Inner{false, 0, acc};
         }
         c->stats.max_inner_terms = std::max(c->stats.max_inner_terms, (int)terms.size());
@@ -895,6 +923,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
                     part->v.d, x->v.n, lv);
         if (s > 0) op_add_sub(c, acc->v, part->v, acc->v, 0);
       }
+      acc->v.nz = inner_nz(j, lv, used[j]);
       inner[j] = Inner{false, 0, acc};
     }
   }
@@ -917,7 +946,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
     std::vector<std::pair<CipherP, CipherP>> pairs;
     for (int j = 1; j < g; ++j)
       if (!inner[j].is_const) pairs.push_back({inner[j].ct, giant[j]});
-    if (!pairs.empty()) result = ev_lazy_products(c, k, pairs, kk >= 2);  // y^j = x^(j kk) are products
+    if (!pairs.empty()) result = ev_lazy_products(c, k, pairs);
     pairs.clear();
     for (int j = 1; j < g; ++j) {
       if (!inner[j].is_const || inner[j].cst == 0) continue;
@@ -940,8 +969,10 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   return result;
 }
 
-// Algorithm 3: for a value tagged t = p^e, e - 1 rounds of a_i = G_{p,e-i}(b),
-// b <- DivideByP(align(b) - a_i); the digits a_0 .. a_{e-2}, b are tagged t = p.
+// Algorithm 3: the balanced base-p digits of a value tagged t = p^e, least significant
+// first.  G_{p,e'} of the current value b (tagged p^e') is its lowest digit (Lemma 3);
+// b minus that digit is a multiple of p, and DivideByP of it is the value of the remaining
+// digits, tagged p^(e'-1).  A value tagged p is the top digit.  Digits are tagged t = p.
 std::vector<CipherP> ev_space_reduce(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
   const int e = x->v.t_exp;
   if (e == 1) return {x};
@@ -951,11 +982,13 @@ std::vector<CipherP> ev_space_reduce(bgv_ctx* c, const bgv_keys* k, const Cipher
   for (int i = 0; i < e - 1; ++i) {
     const int te = e - i;  // b is tagged t = p^te
     CipherP ai = ev_eval_poly(c, k, b, c->gpe[te]);
-    CipherP bb = ev_align(c, b, ai->v.level);
+    CipherP bb = ev_lower(c, b, ai->v.level);
     CipherP d = new_cipher(c, x->v.n, ai->v.level, te);
     op_add_sub(c, bb->v, ai->v, d->v, 1);
+    d->v.nz = nz_add(bb->v.nz, ai->v.nz);
     CipherP nb = new_cipher(c, x->v.n, ai->v.level, te - 1);
     op_divide_by_p(c, d->v, nb->v);
+    nb->v.nz = nz_divide_by_p(c, d->v.nz);
     digits.push_back(with_t(ai, 1));
     b = nb;
   }
@@ -965,9 +998,12 @@ std::vector<CipherP> ev_space_reduce(bgv_ctx* c, const bgv_keys* k, const Cipher
 
 static CipherP one_minus(bgv_ctx* c, const CipherP& x) { return ev_const(c, ev_neg(c, x), 1); }
 
-// Algorithm 4 (digits least significant first).
+// Algorithm 4 (digits least significant first).  A value is below zero exactly when its
+// most significant nonzero balanced digit is: a fold from the top digit down carries
+// (lt, eq) -- the digits read so far are below zero / all zero -- and absorbs digit i as
+// (lt + eq LT_i, eq EQ_i); the last digit's eq is never formed.
 CipherP ev_compare(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& digits, int op) {
-  const int r = (int)digits.size();
+  const int top = (int)digits.size() - 1;
   const int p = c->prm.p;
   auto eq_digit = [&](const CipherP& x) {
     std::map<int, CipherP> tab;
@@ -979,27 +1015,24 @@ CipherP ev_compare(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& di
     return one_minus(c, ev_compare(c, k, digits, base));  // 1 - base
   }
   if (op == BGV_OP_EQ) {
-    CipherP eq = eq_digit(digits[r - 1]);
-    for (int i = r - 2; i >= 0; --i) eq = ev_mul(c, k, eq, eq_digit(digits[i]));
+    CipherP eq = eq_digit(digits[top]);
+    for (int i = top - 1; i >= 0; --i) eq = ev_mul(c, k, eq, eq_digit(digits[i]));
     return eq;
   }
   const std::vector<int64_t>& fdig = op == BGV_OP_GT ? c->fgt : c->flt;
-  std::vector<CipherP> lts(r);
+  std::vector<CipherP> giants;
+  int kk = 0;
+  CipherP lt = ev_eval_poly(c, k, digits[top], fdig, &giants, &kk);
   CipherP eq;
-  for (int i = 0; i < r; ++i) {
-    std::vector<CipherP> giants;
-    int kk = 0;
-    lts[i] = ev_eval_poly(c, k, digits[i], fdig, &giants, &kk);
-    if (i == r - 1 && r > 1) {
-      // x^(p-1) is the last giant power when (g-1) k = p-1 (same products as the power rule)
-      const int g = (int)giants.size();
-      if (g > 1 && (g - 1) * kk == p - 1 && giants[g - 1]) eq = one_minus(c, giants[g - 1]);
-      else eq = eq_digit(digits[i]);
-    }
+  if (top > 0) {
+    // x^(p-1) is the last giant power when (g-1) k = p-1 (same products as the power rule)
+    const int g = (int)giants.size();
+    if (g > 1 && (g - 1) * kk == p - 1 && giants[g - 1]) eq = one_minus(c, giants[g - 1]);
+    else eq = eq_digit(digits[top]);
   }
-  CipherP lt = lts[r - 1];
-  for (int i = r - 2; i >= 0; --i) {
-    lt = ev_add(c, lt, ev_mul(c, k, eq, lts[i]));
+  giants.clear();
+  for (int i = top - 1; i >= 0; --i) {
+    lt = ev_add(c, lt, ev_mul(c, k, eq, ev_eval_poly(c, k, digits[i], fdig)));
     if (i > 0) eq = ev_mul(c, k, eq, eq_digit(digits[i]));
   }
   return lt;
@@ -1013,14 +1046,16 @@ CipherP ev_space_raise(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
 }
 
 CipherP ev_rotate_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& x) {
-  CipherP acc = x;
+  CipherP acc = ev_materialize(c, x);
   for (int i = 1; i < c->ell / 2; i *= 2) {
     CipherP r = new_cipher(c, acc->v.n, acc->v.level, acc->v.t_exp);
     op_rotate(c, k, acc->v, galois_elt(c, i), r->v);
+    r->v.nz = nz_key_switch(c, acc->v.nz, acc->v.t_exp, acc->v.level);
     acc = ev_add(c, acc, r);
   }
   CipherP r = new_cipher(c, acc->v.n, acc->v.level, acc->v.t_exp);
   op_rotate(c, k, acc->v, galois_elt(c, BGV_ROW_SWAP), r->v);
+  r->v.nz = nz_key_switch(c, acc->v.nz, acc->v.t_exp, acc->v.level);
   return ev_add(c, acc, r);
 }
 
@@ -1032,15 +1067,21 @@ CipherP ev_less_than(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const Ciph
     if (y->v.n != x->v.n && y->v.n != 1) throw OpError{BGV_E_ARG};
     d = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
     op_add_sub(c, x->v, y->v, d->v, 1);
+    d->v.nz = nz_add(x->v.nz, y->v.nz);
   }
   std::vector<CipherP> dg = ev_space_reduce(c, k, d);
   return ev_space_raise(c, k, ev_compare(c, k, dg, BGV_OP_LT));
 }
 
-CipherP ev_batch_sum(bgv_ctx* c, const CipherP& x) {
+// the ciphertexts of a batch summed; the estimate is that of adding them one by one
+CipherP ev_batch_sum(bgv_ctx* c, const CipherP& x0) {
+  const CipherP x = ev_materialize(c, x0);
   algo(c, 2.0 * x->v.level * (x->v.n + 1));
   CipherP r = new_cipher(c, 1, x->v.level, x->v.t_exp);
   lk::batch_sum(c, x->v.d, r->v.d, x->v.n, x->v.level);
+  int nz = x->v.nz;
+  for (int i = 1; i < x->v.n; ++i) nz = nz_add(nz, x->v.nz);
+  r->v.nz = nz;
   return r;
 }
 
@@ -1074,6 +1115,7 @@ CipherP ev_filter_and_products(bgv_ctx* c, const bgv_keys* k, const std::vector<
     if (y->v.n != x->v.n && y->v.n != 1) throw OpError{BGV_E_ARG};
     CipherP d = new_cipher(c, x->v.n, x->v.level, x->v.t_exp);
     op_add_sub(c, x->v, y->v, d->v, 1);
+    d->v.nz = nz_add(x->v.nz, y->v.nz);
     preds.push_back(ev_compare(c, k, ev_space_reduce(c, k, d), ops[i]));
   }
   while (preds.size() > 1) {

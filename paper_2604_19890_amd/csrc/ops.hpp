@@ -17,6 +17,7 @@ struct CtV {
   // limbs per polynomial in memory when the batch is a view of the lower `level` limbs of a
   // deeper one (0: level).  Only the tensor kernels and the inner sums read views.
   int stride = 0;
+  int nz = 0;  // noise estimate, sixteenths of a bit (0: unknown)
 };
 inline int lstride(const CtV& v) { return v.stride ? v.stride : v.level; }
 
@@ -70,8 +71,22 @@ bgv_status op_decrypt(bgv_ctx* c, const int8_t* s, const CtV& in, uint64_t* slot
 bgv_status op_keygen(bgv_ctx* c, const int8_t* s, const uint64_t* a, const int32_t* e, const std::vector<int>& gal,
                      bgv_keys* keys);
 
+// ---- noise estimate (sixteenths of a bit; 0 = unknown, and unknown in gives unknown out)
+void noise_init(bgv_ctx* c);
+int nz_lgc(uint64_t x);  // ceil(16 log2 x)
+int nz_lgf(uint64_t x);  // floor(16 log2 x)
+int nz_add(int a, int b);
+int nz_scalar(int a, int64_t k_centered);
+int nz_add_const(int a, int64_t k_centered);
+int nz_divide_by_p(const bgv_ctx* c, int a);
+int nz_switch(const bgv_ctx* c, int a, int t_exp);
+int nz_tensor(const bgv_ctx* c, int a, int b);
+int nz_key_switch(const bgv_ctx* c, int a, int t_exp, int level);
+int nz_mul_ms(const bgv_ctx* c, int a, int b, int t_exp, int level);  // product at `level`, one switch
+
 // ---- evaluator and composites (owned results)
 CipherP ev_align(bgv_ctx* c, const CipherP& x, int level);
+CipherP ev_materialize(bgv_ctx* c, const CipherP& x);  // a contiguous batch (copies a view's limbs)
 CipherP ev_mul(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& b);
 CipherP ev_add(bgv_ctx* c, const CipherP& a, const CipherP& b);
 CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std::vector<int64_t>& coeffs,

@@ -74,6 +74,8 @@ class Pair:
         for b, o in enumerate(octs):
             assert gct.level == o.level, f"{what}: level {gct.level} != {o.level}"
             assert gct.t_exp == o.t_exp, f"{what}: t_exp {gct.t_exp} != {o.t_exp}"
+            if o.nz:
+                assert gct.noise == o.nz, f"{what}: noise estimate {gct.noise} != {o.nz}"
             if not np.array_equal(w[b], o.c):
                 bad = np.argwhere(w[b] != o.c)
                 raise AssertionError(f"{what}: ct {b}: {len(bad)} words differ, first at {bad[0].tolist()}")
