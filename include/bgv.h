@@ -200,7 +200,11 @@ bgv_status bgv_mod_switch_to(bgv_ctx* ctx, const bgv_ct* in, int32_t level, bgv_
  *   each addition.
  *   BGV_SCHED_FAST (0, the default): odd-structured polynomials (every even
  *   coefficient strictly between the constant and the leading term zero) take k =
- *   the smallest power of two with k^2 >= D + 1, others 2k^2 >= D + 1; inner sums
+ *   the smallest power of two with k^2 >= D + 1, others 2k^2 >= D + 1; only the baby
+ *   powers the inner sums need (closed under the power rule) are formed, the powers of
+ *   two and the giants first, then each other one at the level its consumers need
+ *   (the giants' lowest level F among the non-constant inner sums for the inner sums,
+ *   one level above each power it is the second operand of); inner sums
  *   are formed at the level where the outer products meet (or lower); the products
  *   I_j y^j are aligned to their lowest common level, their tensor products summed
  *   and relinearised once, then switched once; then c_jk y^j for constant I_j in

@@ -8,7 +8,9 @@ which decides every ciphertext bit, is:
 
   degree D, k = smallest power of two with 2 k^2 >= D + 1, g = ceil((D+1)/k);
   baby powers x^i (2 <= i <= k) and giant powers y^j (y = x^k, 2 <= j <= g-1) by the
-  power rule: h = 2^floor(log2 i); x^i = x^(i/2) x^(i/2) if i = h, else x^h x^(i-h);
+  power rule: h = 2^floor(log2 i); x^i = x^(i/2) x^(i/2) if i = h, else x^h x^(i-h)
+  (in the fast schedule the powers of two and the giants first, then the other baby
+  powers the inner sums need, each at the level its consumers need: _late_babies);
   every product is: bring both operands to the lower level (below), relinearised
   product, one modulus switch;
   inner sums I_j = sum_{i=1}^{k-1} c_{jk+i} x^i over nonzero coefficients only,
@@ -128,6 +130,51 @@ def _power_rule(table, i, P, keys, cnt):
     return table[i]
 
 
+def _late_babies(P, keys, baby, giant, k, g, coef, cnt):
+    """Fast schedule: the baby powers other than the powers of two, each formed at the level
+    its consumers need rather than as high as its operands allow.
+
+    The needed powers are the exponents the inner sums use, closed under the power rule's
+    operands.  The outer products meet at F, the lowest level among the giant powers of the
+    non-constant inner sums; a power x^i = x^h x^(i-h) (h the largest power of two below i)
+    is wanted at level F for the inner sums, and at one level above each power it is the
+    second operand of.  It is formed by a product at one level above that (or lower, if an
+    operand is lower), its operands brought down first."""
+    used = {i for j in range(g) for i in range(1, k) if coef(j * k + i) != 0}
+    need = set()
+
+    def close(i):
+        if i <= 1 or i in need:
+            return
+        need.add(i)
+        h = 1 << (i.bit_length() - 1)
+        if i == h:
+            close(i // 2)
+        else:
+            close(h)
+            close(i - h)
+
+    for i in used | {k}:
+        close(i)
+    late = sorted(i for i in need if i & (i - 1))
+    prods = [j for j in range(1, g) if any(coef(j * k + i) != 0 for i in range(1, k))]
+    if not prods:
+        for i in late:
+            _power_rule(baby, i, P, keys, cnt)
+        return
+    F = min(giant[j].level for j in prods)
+    want = {i: F for i in late}
+    for i in reversed(late):
+        second = i - (1 << (i.bit_length() - 1))
+        if second in want:
+            want[second] = max(want[second], want[i] + 1)
+    for i in late:
+        h = 1 << (i.bit_length() - 1)
+        a, b = baby[h], baby[i - h]
+        lv = min(want[i] + 1, a.level, b.level)
+        baby[i] = _mul(P, keys, _lower(P, a, lv), _lower(P, b, lv), cnt)
+
+
 def power(P, keys, x, e, cnt=None):
     """x^e by the power rule (e >= 1)."""
     table = {1: x}
@@ -152,15 +199,25 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
     while D > 0 and c[D] == 0:
         D -= 1
     k, g = bsgs_shape(D, (not basic) and parity and odd_structured(c, D))
-    baby = {1: x}
-    for i in range(2, k + 1):
-        _power_rule(baby, i, P, keys, cnt)
-    giant = {1: baby[k]}
-    for j in range(2, g):
-        _power_rule(giant, j, P, keys, cnt)
 
     def coef(n):
         return c[n] if n <= D else 0
+
+    baby = {1: x}
+    if basic:
+        for i in range(2, k + 1):
+            _power_rule(baby, i, P, keys, cnt)
+    else:
+        # the powers of two up to x^k (y) by squaring, then the giant powers
+        i = 2
+        while i <= k:
+            _power_rule(baby, i, P, keys, cnt)
+            i *= 2
+    giant = {1: baby[k]}
+    for j in range(2, g):
+        _power_rule(giant, j, P, keys, cnt)
+    if not basic:
+        _late_babies(P, keys, baby, giant, k, g, coef, cnt)
 
     # every inner sum is formed at the level where the outer products meet (the lowest
     # level among the non-constant I_j and their y^j), or at its own lowest level if lower

@@ -742,13 +742,14 @@ static const double* coeff_table(bgv_ctx* c, int t_exp, const std::vector<int64_
 // schedule: k = smallest power of two with 2k^2 >= D+1 (k^2 >= D+1 for an
 // odd-structured polynomial, see below), g = ceil((D+1)/k);
 // baby powers x^2..x^k and giant powers y^2..y^(g-1) (y = x^k) by the power
-// rule; inner sums over the nonzero coefficients with every power first brought
+// rule (the baby powers other than powers of two after the giants, each at the level its
+// consumers need); inner sums over the nonzero coefficients with every power first brought
 // to the level where the outer products meet (or its own lowest level if lower),
 // scalar terms accumulated in increasing order and the constant added last; the
 // outer products I_j y^j (j = 1..g-1, I_j not a constant) tensored at their lowest
 // common level, summed, relinearised once and switched down one prime; then the
 // scalar multiples c_jk y^j of constant inner sums in increasing j, then I_0.
-// Every other product aligns its operands, relinearises and switches down one prime.
+// Every other product lowers its operands, relinearises and switches down one prime.
 // The basic schedule (BGV_SCHED_BASIC) takes the dense split for every polynomial,
 // forms each inner sum at the lowest level among its powers, and adds the outer terms
 // in increasing j, each I_j y^j as one such product; then I_0.
@@ -807,12 +808,52 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   close(need_g);
   std::map<int, CipherP> baby;
   baby[1] = x;
+  // basic: every needed baby power by the power rule; fast: the powers of two up to x^k
+  // here, the others after the giants
   for (int i = 2; i <= kk; ++i)
-    if (need_b[i]) power(c, k, baby, i);
+    if (need_b[i] && (basic || (i & (i - 1)) == 0)) power(c, k, baby, i);
   std::map<int, CipherP> giant;
   giant[1] = baby[kk];
   for (int j = 2; j < g; ++j)
     if (need_g[j]) power(c, k, giant, j);
+  if (!basic) {
+    // Each other needed baby power x^i = x^h x^(i-h) at the level its consumers need: F (the
+    // lowest level among the giants of the non-constant inner sums, where the outer products
+    // meet) for the inner sums, and one level above each power it is the second operand of.
+    // It is formed by a product one level above that (lower if an operand is lower), its
+    // operands brought down first; with no outer product, by the power rule as it comes.
+    std::vector<int> late;
+    for (int i = 3; i < kk; ++i)
+      if (need_b[i] && (i & (i - 1)) != 0) late.push_back(i);
+    int F = 1 << 30;
+    for (int j = 1; j < g; ++j)
+      for (int i = 1; i < kk; ++i)
+        if (coef(j * kk + i) != 0) {
+          F = std::min(F, giant[j]->v.level);
+          break;
+        }
+    auto top_pow2 = [](int i) {
+      int h = 1;
+      while (2 * h <= i) h *= 2;
+      return h;
+    };
+    if (F == 1 << 30) {
+      for (int i : late) power(c, k, baby, i);
+    } else {
+      std::map<int, int> want;
+      for (int i : late) want[i] = F;
+      for (auto it = late.rbegin(); it != late.rend(); ++it) {
+        auto w = want.find(*it - top_pow2(*it));
+        if (w != want.end()) w->second = std::max(w->second, want[*it] + 1);
+      }
+      for (int i : late) {
+        const int h = top_pow2(i);
+        const CipherP a = baby[h], b = baby[i - h];
+        const int lv = std::min(want[i] + 1, std::min(a->v.level, b->v.level));
+        baby[i] = ev_mul(c, k, ev_lower(c, a, lv), ev_lower(c, b, lv));
+      }
+    }
+  }
 
   std::map<std::pair<int, int>, CipherP> aligned;
   auto aligned_power = [&](int i, int lv) -> CipherP {
