@@ -215,9 +215,8 @@ def time_plain(ctx, keys, cts, n_plain):
     def run():
         acc = None
         for i in range(n_plain):
-            bc = ctx.mul(keys, ctx.view(cts["b"], i, 1), ctx.view(cts["c"], i, 1))
-            lt = ctx.less_than(keys, ctx.view(cts["a"], i, 1), cts["t"])
-            prod = ctx.mul(keys, lt, bc)
+            prod = ctx.filter_products(keys, ctx.view(cts["a"], i, 1), cts["t"], ctx.view(cts["b"], i, 1),
+                                       ctx.view(cts["c"], i, 1))
             acc = prod if acc is None else ctx.add(acc, prod)
         return ctx.rotate_sum(keys, acc)
 

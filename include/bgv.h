@@ -250,16 +250,17 @@ bgv_status bgv_rotate_sum(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, 
 
 /* ---- workload glue ---------------------------------------------------------
  * bgv_mul: the evaluator's product step: both operands are brought to the lower
- *   level by single-prime modulus switches, multiplied and relinearised, then
- *   switched down one prime (output level = min level - 1).  b may be a single
- *   ciphertext broadcast against a batch.
+ *   level (as in the context's schedule, bgv_set_schedule), multiplied and
+ *   relinearised, then switched down one prime (output level = min level - 1).  b may
+ *   be a single ciphertext broadcast against a batch.
  * bgv_batch_sum: out (one ciphertext) = sum of the in->n ciphertexts of a batch.
  * bgv_filter_sum: the filter-and-aggregate query SUM(b*c WHERE a < thr) over the
  *   rows packed in the slots of the batches a, b, c (thr: one ciphertext, or a batch
  *   of the same size): per ciphertext [a < thr] * (b * c) with the product steps
  *   above, the batch summed, then rotate-and-sum so that every slot of `out` holds
- *   the total (Figure 1's WHERE -> multiply -> SUM pipeline).  Needs the keys of
- *   bgv_rotate_sum.
+ *   the total (Figure 1's WHERE -> multiply -> SUM pipeline).  In the fast schedule
+ *   b * c is formed one level above the predicate's result, from b and c brought down
+ *   first (in the basic one, at their own level).  Needs the keys of bgv_rotate_sum.
  * bgv_relu: x * (1 - [x < 0]) slot-wise (the ReLU-style sign/compare workload).   */
 bgv_status bgv_mul(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* a, const bgv_ct* b, bgv_ct* out);
 bgv_status bgv_batch_sum(bgv_ctx* ctx, const bgv_ct* in, bgv_ct* out);

@@ -358,10 +358,20 @@ def relu(P, keys, x, cnt=None):
     return _mul(P, keys, x, B.add_const(P, B.neg(P, lt), 1), cnt)
 
 
+def _product_at(P, keys, b, c, level, cnt=None):
+    """b c formed where it is consumed: by a product one level above `level` (the level of
+    the factor it meets; lower if an operand is lower), its operands brought down first.  In
+    the basic schedule, at the operands' own level."""
+    if P.schedule == "basic":
+        return _mul(P, keys, b, c, cnt)
+    lv = min(level + 1, b.level, c.level)
+    return _mul(P, keys, _lower(P, b, lv), _lower(P, c, lv), cnt)
+
+
 def filter_product(P, keys, a, tq, b, c, cnt=None):
-    """[a < tq] * (b * c) for one ciphertext of rows."""
-    bc = _mul(P, keys, b, c, cnt)
-    return _mul(P, keys, less_than(P, keys, a, tq, cnt), bc, cnt)
+    """[a < tq] * (b * c) for one ciphertext of rows; b * c is formed at the predicate's level."""
+    m = less_than(P, keys, a, tq, cnt)
+    return _mul(P, keys, m, _product_at(P, keys, b, c, m.level, cnt), cnt)
 
 
 def filter_and_product(P, keys, preds, b, c, cnt=None):
@@ -372,15 +382,15 @@ def filter_and_product(P, keys, preds, b, c, cnt=None):
     column - threshold ('lt' is [column < threshold], 'ge' is [column >= threshold], ...).  Each
     0/1 result stays in the digit space (t = p); the conjunction is their product there, taken
     as a balanced tree over the predicates in their order (pairs (0, 1), (2, 3), .., then pairs of
-    those); it is raised once to t = p^r and multiplied by b * c."""
-    bc = _mul(P, keys, b, c, cnt)
+    those); it is raised once to t = p^r and multiplied by b * c, formed at that level."""
     bits = [compare(P, keys, space_reduce(P, keys, B.sub(P, col, thr), cnt), op, cnt) for col, thr, op in preds]
     while len(bits) > 1:
         paired = [_mul(P, keys, bits[i], bits[i + 1], cnt) for i in range(0, len(bits) - 1, 2)]
         if len(bits) % 2:
             paired.append(bits[-1])
         bits = paired
-    return _mul(P, keys, space_raise(P, keys, bits[0], cnt), bc, cnt)
+    m = space_raise(P, keys, bits[0], cnt)
+    return _mul(P, keys, m, _product_at(P, keys, b, c, m.level, cnt), cnt)
 
 
 def rotate_and_sum(P, keys, ct):

@@ -1126,13 +1126,21 @@ CipherP ev_batch_sum(bgv_ctx* c, const CipherP& x0) {
   return r;
 }
 
-// SUM(b*c WHERE a < thr): [a < thr] * (b * c) per ciphertext, summed over the batch,
-// then rotate-and-sum over the slots.
+// b * c formed where it is consumed: by a product one level above `level` (the level of
+// the factor it meets; lower if an operand is lower), its operands brought down first.  In
+// the basic schedule, at the operands' own level.
+static CipherP ev_product_at(bgv_ctx* c, const bgv_keys* k, const CipherP& b, const CipherP& cc, int level) {
+  if (c->schedule == BGV_SCHED_BASIC) return ev_mul(c, k, b, cc);
+  const int lv = std::min(level + 1, std::min(b->v.level, cc->v.level));
+  return ev_mul(c, k, ev_lower(c, b, lv), ev_lower(c, cc, lv));
+}
+
+// SUM(b*c WHERE a < thr): [a < thr] * (b * c) per ciphertext (b * c formed at the
+// predicate's level), summed over the batch, then rotate-and-sum over the slots.
 CipherP ev_filter_products(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& thr, const CipherP& b,
                            const CipherP& cc) {
-  CipherP bc = ev_mul(c, k, b, cc);
   CipherP lt = ev_less_than(c, k, a, thr);
-  return ev_mul(c, k, lt, bc);
+  return ev_mul(c, k, lt, ev_product_at(c, k, b, cc, lt->v.level));
 }
 
 CipherP ev_filter_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const CipherP& thr, const CipherP& b,
@@ -1144,11 +1152,10 @@ CipherP ev_filter_sum(bgv_ctx* c, const bgv_keys* k, const CipherP& a, const Cip
 // threshold i: op_i applied to the digits of col_i - thr_i (reduce, then compare; the results
 // are 0/1 tagged t = p).  The conjunction is the product of those results in the digit space,
 // formed as a balanced tree over the predicates in their order (pairs (0,1), (2,3), .., then
-// pairs of those), raised once to t = p^r and multiplied by b * c.
+// pairs of those), raised once to t = p^r and multiplied by b * c, formed at that level.
 CipherP ev_filter_and_products(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& cols,
                                const std::vector<CipherP>& thrs, const std::vector<int>& ops, const CipherP& b,
                                const CipherP& cc) {
-  CipherP bc = ev_mul(c, k, b, cc);
   std::vector<CipherP> preds;
   for (size_t i = 0; i < cols.size(); ++i) {
     const CipherP& x = cols[i];
@@ -1165,7 +1172,8 @@ CipherP ev_filter_and_products(bgv_ctx* c, const bgv_keys* k, const std::vector<
     if (preds.size() % 2) next.push_back(preds.back());
     preds.swap(next);
   }
-  return ev_mul(c, k, ev_space_raise(c, k, preds[0]), bc);
+  CipherP m = ev_space_raise(c, k, preds[0]);
+  return ev_mul(c, k, m, ev_product_at(c, k, b, cc, m->v.level));
 }
 
 CipherP ev_filter_and_sum(bgv_ctx* c, const bgv_keys* k, const std::vector<CipherP>& cols,

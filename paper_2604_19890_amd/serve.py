@@ -152,8 +152,7 @@ class Engine:
             for i in range(q.n_cts):
                 b, c = ctx.view(q.b, i, 1), ctx.view(q.c, i, 1)
                 if q.kind == "filter":
-                    lt = ctx.less_than(keys, ctx.view(q.a, i, 1), q.t)
-                    prod = ctx.mul(keys, lt, ctx.mul(keys, b, c))
+                    prod = ctx.filter_products(keys, ctx.view(q.a, i, 1), q.t, b, c)
                 else:
                     prod = ctx.mul(keys, b, c)
                 q.partial = prod if q.partial is None else ctx.add(q.partial, prod)
