@@ -142,7 +142,9 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
 // rows are never stored.  The second pass, fused with the key inner product, follows.
 // With ALPHA = 6 the operands of the last source row are kept in LDS (each thread reads back
 // only its own words, so no barrier is needed for them): the other five rows and the working
-// registers then fit two waves per SIMD.
+// registers then fit two waves per SIMD.  blockIdx.z splits the target rows into gridDim.z
+// contiguous ranges (each block redoes the digit's source rows): small batches then still
+// fill the chip.
 template <int LOGS, int ALPHA>
 __global__ void __launch_bounds__(NT_MAX, 2) k_modup_cols(const uint64_t* __restrict__ xh, uint64_t* __restrict__ y,
                                                        int logN, int level, int dn, int dnum, int alpha, int K,
@@ -225,7 +227,9 @@ __global__ void __launch_bounds__(NT_MAX, 2) k_modup_cols(const uint64_t* __rest
   // ---- every target row outside the digit: ModUp value, first forward pass, store
   const double* __restrict__ basis = modup + tab * (size_t)alpha * (1 + Ltot) + alpha;
   uint64_t* __restrict__ yb = y + ((size_t)ct * dn + j) * rows * N + g1;
-  for (int m = 0; m < rows; ++m) {
+  const int per = (rows + gridDim.z - 1) / gridDim.z;
+  const int m_end = min(rows, ((int)blockIdx.z + 1) * per);
+  for (int m = blockIdx.z * per; m < m_end; ++m) {
     if (m >= lo && m < lo + na) continue;
     const int pm = m < level ? m : Lfull + (m - level);
     const double q = pc[pm].q, qinv = pc[pm].qinv;
@@ -289,7 +293,12 @@ void modup_cols(bgv_ctx* c, const uint64_t* xh, uint64_t* y, int n, int level) {
   const int S = 1 << p1, T = S / 16;
   const int NT = N / 16 < NT_MAX ? N / 16 : NT_MAX;
   const int SUBS = NT / T;
-  dim3 grid((N / S) / SUBS, n * dn);
+  // the target rows of each (ciphertext, digit) over up to 4 blocks while the grid is under
+  // 1024 blocks (four per compute unit)
+  const int base_blocks = ((N / S) / SUBS) * n * dn;
+  int split = 1;
+  while (split < 4 && base_blocks * split < 1024) split *= 2;
+  dim3 grid((N / S) / SUBS, n * dn, split);
 #define MU_CASE(LS, AL)                                                                                        \
   if (p1 == LS && A == AL) {                                                                                   \
     hipLaunchKernelGGL((k_modup_cols<LS, AL>), grid, dim3(NT), 0, c->stream, xh, y, c->logN, level, dn, c->dnum, \
