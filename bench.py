@@ -229,10 +229,15 @@ def time_plain(ctx, keys, cts, n_plain):
 
 
 def time_graph(ctx, keys, cts, steps):
-    """The batched step captured once as a hipGraph and replayed."""
+    """The batched step captured once as a hipGraph and replayed; returns the time per replay and
+    whether the last replay's result equals the eager step's, word for word."""
     import torch
     out = ctx.empty(1, 1)
     ctx.filter_sum(keys, cts["a"], cts["t"], cts["b"], cts["c"], out=out)  # eager run: tables, scratch
+    torch.cuda.synchronize()
+    words = ctx.words(out.level)
+    eager = out.tensor[:words].clone()
+    out.tensor.zero_()
     torch.cuda.synchronize()
     ctx.capture_begin()
     ctx.filter_sum(keys, cts["a"], cts["t"], cts["b"], cts["c"], out=out)
@@ -245,8 +250,9 @@ def time_graph(ctx, keys, cts, steps):
         graph.launch()
     stop.record()
     torch.cuda.synchronize()
+    same = bool(torch.equal(out.tensor[:words], eager))
     del graph
-    return start.elapsed_time(stop) / 1e3 / steps
+    return start.elapsed_time(stop) / 1e3 / steps, same
 
 
 def time_ntt(ctx, n_cts, reps=20, warm_s=1.0):
@@ -551,7 +557,7 @@ def main():
     ap.add_argument("--plain", type=int, default=8, help="ciphertexts timed in the plain form")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="also time the step replayed from a hipGraph")
+    ap.add_argument("--no-graph", action="store_true", help="skip timing the step replayed from a hipGraph")
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the forward NTT at the query shape and a copy of the same bytes (for counters)")
     ap.add_argument("--ks-only", action="store_true",
@@ -643,9 +649,10 @@ def main():
         basic_sched = {"ms_per_step": el / args.steps * 1e3, "rows_per_s": rows * args.steps / el}
         log(f"[bench] basic schedule: {el / args.steps * 1e3:.1f} ms/step, {rows * args.steps / el:.1f} rows/s")
 
-    t_graph = time_graph(ctx, keys, cts, args.steps) if args.graph else None
+    t_graph, graph_same = time_graph(ctx, keys, cts, args.steps) if not args.no_graph else (None, None)
     if t_graph:
-        log(f"[bench] graph replay: {t_graph * 1e3:.1f} ms/step, {rows / t_graph:.1f} rows/s")
+        log(f"[bench] graph replay: {t_graph * 1e3:.1f} ms/step, {rows / t_graph:.1f} rows/s, "
+            f"result {'equal to' if graph_same else 'DIFFERENT from'} the eager step's")
     n_plain = min(args.plain, args.cts)
     t_plain = time_plain(ctx, keys, cts, n_plain) if n_plain > 0 else None
     plain_rows = (n_plain * ctx.slots / t_plain) if t_plain else None
@@ -682,6 +689,7 @@ def main():
         "plain_rows_per_s": plain_rows,
         "plain_cts_timed": n_plain,
         "graph_rows_per_s": (rows / t_graph) if t_graph else None,
+        "graph_equals_eager": graph_same,
         "batched_over_plain": (value / plain_rows) if plain_rows else None,
         "basic_schedule": basic_sched,
         "ntt_gb_per_s": ntt_gbs,

@@ -419,6 +419,18 @@ def add_tensor(P: Params, d: Triple, e: Triple, level: int) -> Triple:
     return Triple((d.d + e.d) % _qcol(P.q[:level]), level, d.t_exp, NZ.add(d.nz, e.nz))
 
 
+def add_to_triple(P: Params, d: Triple, x: Ct) -> Triple:
+    """(d0 + c0, d1 + c1, d2): the triple then decrypts to its product plus x's message (both at
+    the triple's level and plaintext modulus)."""
+    if x.level != d.level or x.t_exp != d.t_exp:
+        raise ValueError("level or plaintext modulus mismatch")
+    q = _qcol(P.q[: d.level])
+    out = d.d.copy()
+    out[0] = (out[0] + x.c[0]) % q
+    out[1] = (out[1] + x.c[1]) % q
+    return Triple(out, d.level, d.t_exp, NZ.add(d.nz, x.nz))
+
+
 def relin(P: Params, rk: SwitchKey, d: Triple, level: int, t_exp: int) -> Ct:
     """Relinearisation of a triple (d0, d1, d2): (d0 + u0, d1 + u1) with (u0, u1) the key
     switch of d2 (no modulus switch inside)."""

@@ -18,7 +18,9 @@ which decides every ciphertext bit, is:
   products accumulated in increasing i, then the constant c_{jk} added;
   an inner sum with no power term contributes c_{jk} y^j as a scalar product;
   outer sum over j = 1..g-1 in increasing j (each term I_j * y^j a product as
-  above), operands brought to the lower level before each addition, I_0 added last.
+  above), operands brought to the lower level before each addition, I_0 added last
+  (in the fast schedule the constant inner sums' terms c_jk y^j and I_0 join the summed outer
+  products before their one switch).
 
 Bringing an operand to a lower level: in the basic schedule by single-prime modulus
 switches; in the fast schedule by its noise estimate (oracle/noise.py): while the
@@ -72,16 +74,26 @@ def _mul(P, keys, a, b, cnt=None):
     return B.mod_switch(P, r)
 
 
-def _lazy_products(P, keys, pairs, cnt=None):
+def _lazy_level(pairs):
+    return min(min(a.level, b.level) for a, b in pairs)
+
+
+def _lazy_products(P, keys, pairs, cnt=None, addends=()):
     """sum_j a_j b_j relinearised once: every operand brought to the lowest level among the
-    pairs, the tensor products summed, one key switch of the summed d2, one modulus switch."""
-    lv = min(min(a.level, b.level) for a, b in pairs)
+    pairs, the tensor products summed, one key switch of the summed d2, one modulus switch.
+    Addends (k, x): k x for each, in their order, x at that level or above and brought down by
+    dropping limbs, join (d0, d1) before the key switch, so the one modulus switch also divides
+    their noise."""
+    lv = _lazy_level(pairs)
     acc = None
     for a, b in pairs:
         d = B.tensor(P, _lower(P, a, lv), _lower(P, b, lv))
         acc = d if acc is None else B.add_tensor(P, acc, d, lv)
         if cnt is not None:
             cnt.mul += 1
+    for k, x in addends:
+        xd = B.drop(P, x, lv)
+        acc = B.add_to_triple(P, acc, xd if k == 1 else B.mul_scalar(P, xd, k))
     return B.mod_switch(P, B.relin(P, keys.relin, acc, lv, pairs[0][0].t_exp))
 
 
@@ -255,22 +267,32 @@ def eval_poly(P, keys, x, coeffs, cnt=None, parity=True):
                 continue
             result = term if result is None else _add(P, result, term)
     else:
-        # the products I_j y^j, relinearised once together, then the scalar multiples
-        # c_jk y^j of constant inner sums in increasing j
+        # the products I_j y^j, relinearised once together; the scalar multiples c_jk y^j of
+        # constant inner sums (increasing j), then I_0, join them before the switch when they
+        # are at that level or above, otherwise they are added after it
         pairs = [(v, giant[j]) for j, (kind, v) in enumerate(inner) if j >= 1 and kind == "ct"]
-        result = _lazy_products(P, keys, pairs, cnt) if pairs else None
-        for j in range(1, g):
-            kind, v = inner[j]
-            if kind == "const" and v != 0:
-                term = B.mul_scalar(P, giant[j], v)
-                result = term if result is None else _add(P, result, term)
+        scalars = [(v, giant[j]) for j, (kind, v) in enumerate(inner) if j >= 1 and kind == "const" and v != 0]
+        if pairs:
+            lv = _lazy_level(pairs)
+            add = [(k, y) for k, y in scalars if y.level >= lv]
+            scalars = [(k, y) for k, y in scalars if y.level < lv]
+            kind0, v0 = inner[0]
+            if kind0 == "ct" and v0.level >= lv:
+                add.append((1, v0))
+                inner[0] = ("folded", None)
+            result = _lazy_products(P, keys, pairs, cnt, addends=add)
+        else:
+            result = None
+        for k, y in scalars:
+            term = B.mul_scalar(P, y, k)
+            result = term if result is None else _add(P, result, term)
     kind, v = inner[0]
     if kind == "const":
         if result is None:
             raise ValueError("constant polynomial: nothing to evaluate")
         if v != 0:
             result = B.add_const(P, result, v)
-    else:
+    elif kind == "ct":
         result = v if result is None else _add(P, result, v)
     return result
 

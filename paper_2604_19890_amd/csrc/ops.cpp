@@ -219,10 +219,21 @@ void op_mul_ms(bgv_ctx* c, const bgv_keys* keys, const CtV& a, const CtV& b, con
 }
 
 static CipherP ev_lower(bgv_ctx* c, const CipherP& x, int level);
+static CipherP ev_drop(bgv_ctx* c, const CipherP& x, int level);
+static CipherP ev_scalar(bgv_ctx* c, const CipherP& x0, int64_t k);
+
+static int lazy_level(const std::vector<std::pair<CipherP, CipherP>>& pairs) {
+  int lv = 1 << 30;
+  for (const auto& pr : pairs) lv = std::min(lv, std::min(pr.first->v.level, pr.second->v.level));
+  return lv;
+}
 
 // sum_j a_j b_j relinearised once: every operand brought to the lowest level among the
-// pairs, the tensor products accumulated, one key switch and one modulus switch.
-static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector<std::pair<CipherP, CipherP>>& pairs) {
+// pairs, the tensor products accumulated, one key switch and one modulus switch.  Addends
+// (k, x): k x for each, in their order, x at that level or above and brought down by dropping
+// limbs, join (d0, d1) before the key switch, so the one modulus switch also divides their noise.
+static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector<std::pair<CipherP, CipherP>>& pairs,
+                                const std::vector<std::pair<int64_t, CipherP>>& addends = {}) {
   int lv = 1 << 30, n = 1;
   for (const auto& pr : pairs) {
     lv = std::min(lv, std::min(pr.first->v.level, pr.second->v.level));
@@ -256,6 +267,19 @@ static CipherP ev_lazy_products(bgv_ctx* c, const bgv_keys* k, const std::vector
     }
     c->stats.max_tensor_pairs = std::max(c->stats.max_tensor_pairs, np);
     lk::tensor_sum(c, tp, np, D.d, X.d, n, lv, s0 > 0);
+  }
+  for (const auto& ad : addends) {
+    if (ad.second->v.level < lv || ad.second->v.t_exp != t_exp || (ad.second->v.n != n && ad.second->v.n != 1))
+      throw OpError{BGV_E_ARG};
+    const CipherP xd = ev_drop(c, ad.second, lv);
+    const CipherP term = ad.first == 1 ? xd : ev_scalar(c, xd, ad.first);
+    CtV dv;
+    dv.d = D.d;
+    dv.n = n;
+    dv.level = lv;
+    dv.t_exp = t_exp;
+    op_add_sub(c, dv, term->v, dv, 0);  // (d0, d1) += term, a single ciphertext broadcast
+    nz = nz_add(nz, term->v.nz);
   }
   CipherP r = new_cipher(c, n, lv - 1, t_exp);
   relin_ms(c, k, D, X, n, lv, t_exp, r->v);
@@ -627,15 +651,34 @@ CipherP ev_materialize(bgv_ctx* c, const CipherP& x) {
 // than NZ_SLACK above the floor a switch leaves, one switch of the top prime; the limbs
 // left above `level` are dropped without rescaling (their noise is then within NZ_SLACK
 // of what further switches would leave).
+static int lower_switches(const bgv_ctx* c, const CipherP& x, int level) {
+  const int te = x->v.t_exp, limit = c->nzm.floor[te] + NZ_SLACK;
+  int m = 0;
+  for (int e = x->v.nz; m < x->v.level - level && e > limit; ++m) e = nz_switch(c, e, te);
+  return m;
+}
+
 static CipherP ev_lower(bgv_ctx* c, const CipherP& x, int level) {
   if (x->v.level == level) return x;
   if (level > x->v.level || level < 1) throw OpError{BGV_E_LEVEL};
   if (c->schedule == BGV_SCHED_BASIC || x->v.nz <= 0) return ev_align(c, x, level);
-  const int te = x->v.t_exp, limit = c->nzm.floor[te] + NZ_SLACK;
-  int m = 0;
-  for (int e = x->v.nz; m < x->v.level - level && e > limit; ++m) e = nz_switch(c, e, te);
+  const int m = lower_switches(c, x, level);
   const CipherP y = m ? ev_align(c, x, x->v.level - m) : x;
   return ev_drop(c, y, level);
+}
+
+// ev_lower for an operand lowered to several levels: its switched form (the switches depend
+// only on its estimate and level) is formed once and kept in `done`
+typedef std::map<std::pair<const Cipher*, int>, CipherP> SwitchedForms;
+static CipherP ev_lower_shared(bgv_ctx* c, const CipherP& x, int level, SwitchedForms& done) {
+  if (x->v.level == level || c->schedule == BGV_SCHED_BASIC || x->v.nz <= 0) return ev_lower(c, x, level);
+  if (level > x->v.level || level < 1) throw OpError{BGV_E_LEVEL};
+  const int m = lower_switches(c, x, level);
+  if (m == 0) return ev_drop(c, x, level);
+  const auto key = std::make_pair(x.get(), m);
+  auto it = done.find(key);
+  if (it == done.end()) it = done.emplace(key, ev_align(c, x, x->v.level - m)).first;
+  return ev_drop(c, it->second, level);
 }
 
 // a * b relinearised and switched down one prime, each operand first brought to the lower level
@@ -806,6 +849,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   };
   close(need_b);
   close(need_g);
+  SwitchedForms switched;  // operands switched down once for several lowerings
   std::map<int, CipherP> baby;
   baby[1] = x;
   // basic: every needed baby power by the power rule; fast: the powers of two up to x^k
@@ -850,7 +894,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
         const int h = top_pow2(i);
         const CipherP a = baby[h], b = baby[i - h];
         const int lv = std::min(want[i] + 1, std::min(a->v.level, b->v.level));
-        baby[i] = ev_mul(c, k, ev_lower(c, a, lv), ev_lower(c, b, lv));
+        baby[i] = ev_mul(c, k, ev_lower_shared(c, a, lv, switched), ev_lower_shared(c, b, lv, switched));
       }
     }
   }
@@ -860,7 +904,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
     auto key = std::make_pair(i, lv);
     auto it = aligned.find(key);
     if (it != aligned.end()) return it->second;
-    CipherP r = ev_lower(c, baby[i], lv);
+    CipherP r = ev_lower_shared(c, baby[i], lv, switched);
     aligned[key] = r;
     return r;
   };
@@ -984,13 +1028,32 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
       result = result ? ev_add(c, result, term) : term;
     }
   } else {
+    // the products I_j y^j relinearised once together; the scalar multiples c_jk y^j of
+    // constant inner sums (increasing j), then I_0, join them before the switch when they are
+    // at that level or above, otherwise they are added after it
     std::vector<std::pair<CipherP, CipherP>> pairs;
     for (int j = 1; j < g; ++j)
       if (!inner[j].is_const) pairs.push_back({inner[j].ct, giant[j]});
-    if (!pairs.empty()) result = ev_lazy_products(c, k, pairs);
+    std::vector<int> late_scalars;
+    if (!pairs.empty()) {
+      const int lv = lazy_level(pairs);
+      std::vector<std::pair<int64_t, CipherP>> addends;
+      for (int j = 1; j < g; ++j) {
+        if (!inner[j].is_const || inner[j].cst == 0) continue;
+        if (giant[j]->v.level >= lv) addends.push_back({inner[j].cst, giant[j]});
+        else late_scalars.push_back(j);
+      }
+      if (!inner[0].is_const && inner[0].ct->v.level >= lv) {
+        addends.push_back({1, inner[0].ct});
+        inner[0].ct = nullptr;  // folded
+      }
+      result = ev_lazy_products(c, k, pairs, addends);
+    } else {
+      for (int j = 1; j < g; ++j)
+        if (inner[j].is_const && inner[j].cst != 0) late_scalars.push_back(j);
+    }
     pairs.clear();
-    for (int j = 1; j < g; ++j) {
-      if (!inner[j].is_const || inner[j].cst == 0) continue;
+    for (int j : late_scalars) {
       CipherP term = ev_scalar(c, giant[j], inner[j].cst);
       result = result ? ev_add(c, result, term) : term;
     }
@@ -998,7 +1061,7 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
   if (inner[0].is_const) {
     if (!result) throw OpError{BGV_E_ARG};
     if (inner[0].cst != 0) result = ev_const(c, result, inner[0].cst);
-  } else {
+  } else if (inner[0].ct) {
     result = result ? ev_add(c, result, inner[0].ct) : inner[0].ct;
   }
   if (giant_out) {
