@@ -460,12 +460,13 @@ def limb_products_per_query_ct():
 
     saved = {k: getattr(OB, k) for k in ("mul_relin", "mod_switch", "add", "sub", "neg", "mul_scalar",
                                         "add_const", "divide_by_p", "change_mod_to_p", "raise_tag", "rotate",
-                                        "tensor", "relin", "add_tensor", "drop")}
+                                        "tensor", "relin", "add_tensor", "add_to_triple", "drop")}
     try:
         OB.mul_relin = mul_relin
         OB.tensor = tensor
         OB.relin = relin
         OB.add_tensor = lambda P_, d, e, level: d
+        OB.add_to_triple = lambda P_, d, x: d
         OB.rotate = rotate
         OB.mod_switch = lambda P_, a: Fake(a.level - 1, a.t_exp)
         OB.drop = lambda P_, a, level: Fake(level, a.t_exp)

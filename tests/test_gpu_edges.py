@@ -131,3 +131,32 @@ def test_unknown_schedule_is_rejected():
     with pytest.raises(KeyError):
         c.lib.set_schedule("fastest")
     c.lib.set_schedule("fast")
+
+
+def test_noise_estimates_through_the_binding():
+    """Every call that writes a batch gives it an estimate; a batch without one (noise 0) is
+    lowered by rescaling switches only and still decrypts to the right values; concat keeps the
+    largest estimate of its parts, or none if a part has none."""
+    c = pair_tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(41)
+    ra, rb = g.integers(0, t, size=(2, P.ell)), g.integers(0, t, size=(2, P.ell))
+    ga, _ = c.enc_both(ra, oracle=False)
+    gb, _ = c.enc_both(rb, oracle=False)
+    assert ga.noise > 0 and gb.noise == ga.noise
+    c.lib.reset_stats()
+    known = c.lib.less_than(c.keys, ga, gb)
+    st_known = c.lib.stats()
+    assert known.noise > 0
+    c.lib.reset_stats()
+    blind_a = c.G.Ct(ga.tensor, ga.n, ga.level, ga.t_exp)  # noise 0: unknown
+    blind = c.lib.less_than(c.keys, blind_a, gb)
+    st = c.lib.stats()
+    assert blind.noise == 0 and st["rescale_drops"] > st_known["rescale_drops"]
+    cen = lambda v: v - t if v > (t - 1) // 2 else v
+    want = [[1 if cen((int(x) - int(y)) % t) < 0 else 0 for x, y in zip(r1, r2)] for r1, r2 in zip(ra, rb)]
+    assert c.lib.decrypt(c.s, blind).tolist() == want
+    assert c.lib.decrypt(c.s, known).tolist() == want
+    both = c.lib.concat([ga, gb])
+    assert both.noise == ga.noise
+    assert c.lib.concat([ga, blind_a]).noise == 0
