@@ -13,6 +13,8 @@
 // lgc / lgf are ceil / floor of 16 log2 x, exact; lsum(a, b) bounds log2(2^a + 2^b).
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
+#include <unordered_map>
 
 #include "ops.hpp"
 
@@ -70,9 +72,17 @@ inline int known1(int v) { return std::max(1, v); }
 
 }  // namespace
 
+// lgc of the operands the estimates meet (scalars and constants of the evaluated polynomials,
+// the model's constants) is asked for many times per call: the values are kept once computed
 int nz_lgc(uint64_t x) {
+  static std::mutex mu;
+  static std::unordered_map<uint64_t, int> seen;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = seen.find(x);
+  if (it != seen.end()) return it->second;
   int f, c;
   lg16(x, &f, &c);
+  if (seen.size() < (1u << 16)) seen.emplace(x, c);
   return c;
 }
 

@@ -1012,8 +1012,10 @@ CipherP ev_eval_poly(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const std:
       inner[j] = Inner{false, 0, acc};
     }
   }
-  // the inner sums hold everything the outer sum needs from the baby steps
+  // the inner sums hold everything the outer sum needs from the baby steps (the switched
+  // forms are keyed by their sources' addresses: dropped before any source is)
   aligned.clear();
+  switched.clear();
   for (auto it = baby.begin(); it != baby.end();) it = (it->first != 1 && it->first != kk) ? baby.erase(it) : std::next(it);
   // outer sum: the products I_j y^j (relinearised once together in the fast schedule),
   // the scalar multiples c_jk y^j of constant inner sums, then I_0

@@ -1,8 +1,10 @@
 """hipGraph capture of library operations: every replay gives the eager result, with eager
-work and synchronisations between the replays."""
+work and synchronisations between the replays, and the eager result is the oracle's, word for
+word."""
 import numpy as np
 import pytest
 
+from oracle import space as S
 from tests.gpu_ctx import pair_two_pass_deep
 
 pytestmark = pytest.mark.gpu
@@ -13,8 +15,8 @@ def test_captured_pipeline_replays_bit_exactly():
     c = pair_two_pass_deep()
     P, t = c.P, c.P.t_full
     g = np.random.default_rng(31)
-    ga, _ = c.enc_both(g.integers(0, t, size=(2, P.ell)), oracle=False)
-    gb, _ = c.enc_both(g.integers(0, t, size=(2, P.ell)), oracle=False)
+    ga, oa = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(2, P.ell)))
     lib = c.lib
     out_lt = lib.empty(2, P.L)
     out_m = lib.empty(2, P.L)
@@ -22,6 +24,10 @@ def test_captured_pipeline_replays_bit_exactly():
     lib.less_than(c.keys, ga, gb, out=out_lt)
     lib.mul(c.keys, out_lt, ga, out=out_m)
     torch.cuda.synchronize()
+    # the eager results against the oracle's pipeline on the same inputs
+    o_lt = [S.less_than(P, c.okeys, x, y) for x, y in zip(oa, ob)]
+    c.assert_equal(out_lt, o_lt, "less_than")
+    c.assert_equal(out_m, [S._mul(P, c.okeys, l, x) for l, x in zip(o_lt, oa)], "masked product")
     ref_lt = out_lt.tensor.clone()
     ref_m = out_m.tensor.clone()
     ref_level = out_m.level
