@@ -281,7 +281,8 @@ bgv_status bgv_filter_products(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct*
  *   ops[i] is BGV_OP_LT / LE / GT / GE / EQ / NEQ applied to cols[i] - thrs[i] (so BGV_OP_LT
  *   is [col < thr]).  Each predicate is reduced and compared in the digit space; the 0/1
  *   results are multiplied there in a balanced tree over the predicates in their order
- *   (pairs (0,1), (2,3), .., then pairs of those), raised once and multiplied by b * c.
+ *   (pairs (0,1), (2,3), .., then pairs of those), raised once and multiplied by b * c
+ *   (in the fast schedule formed one level above the raised result, as in bgv_filter_sum).
  *   The depth is one reduce, compare and raise plus ceil(log2 n_pred) products, so the chain
  *   must be that much longer than the single-predicate query's (BGV_E_LEVEL otherwise).
  *   1 <= n_pred <= 16.  _products gives the per-ciphertext result, _sum the batch summed and
