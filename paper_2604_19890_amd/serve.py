@@ -10,8 +10,10 @@ resident in HBM; every ring keeps its evaluation keys resident.  A query is admi
 its ciphertext footprint fits the memory budget next to the resident keys, and waits (FIFO)
 otherwise; a query larger than the whole budget is rejected.
 
-Batched mode: per ring, a scheduling round takes ciphertext chunks from the head of the
-ring's queue -- several queries, large queries split across rounds -- concatenates them into
+Batched mode: per ring, a scheduling round takes ciphertext chunks from the ring's queue,
+the queries with the fewest ciphertexts left first (ties by arrival; policy "srpt", the
+default) or in admission order (policy "fifo") -- several queries,
+large queries split across rounds -- concatenates them into
 one batch and runs the per-ciphertext products in one set of launches on the ring's stream
 (rings run on separate streams, so their rounds overlap on the device).  Each query's products
 are summed over its own ciphertexts and added to its running total; when the last chunk is
@@ -224,7 +226,8 @@ def reset(queries):
         q.latency_ms = None
 
 
-def serve(queries, engines, mode: str = "batched", round_cts: dict = None, budget_bytes: float = 200e9):
+def serve(queries, engines, mode: str = "batched", round_cts: dict = None, budget_bytes: float = 200e9,
+          policy: str = "srpt"):
     """Serve the queries in real time; returns stats.  round_cts[log_n] bounds a round's batch."""
     reset(queries)
     key_bytes = sum(e.keys.bytes for e in engines.values())
@@ -273,7 +276,10 @@ def serve(queries, engines, mode: str = "batched", round_cts: dict = None, budge
             if e.queue:
                 limit = min(round_cts.get(e.log_n, 32) if round_cts else 32, e.ctx.max_batch)
                 segs, used = [], 0
-                for q in e.queue:
+                # "srpt": the queries with the fewest ciphertexts left first (ties by arrival),
+                # so small queries do not wait behind a large one; "fifo": in admission order
+                order = e.queue if policy == "fifo" else sorted(e.queue, key=lambda q: (q.n_cts - q.next_ct, q.arrival))
+                for q in order:
                     if used >= limit:
                         break
                     n = min(q.n_cts - q.next_ct, limit - used)
@@ -325,7 +331,7 @@ def poisson_arrivals(queries, rate: float, seed: int = 0):
 
 
 def run_mix(n_queries: int = 24, rings=(14, 15, 16), rows_lo: int = 1 << 10, rows_hi: int = 1 << 12,
-            load: float = 0.8, round_cts_16: int = 16, seed: int = 0, log=print) -> dict:
+            load: float = 0.8, round_cts_16: int = 16, seed: int = 0, log=print, policy: str = "srpt") -> dict:
     """A bounded serving run: the mix's columns are encrypted first; the batched capacity is
     measured with every query present at time 0; then arrivals are Poisson at `load` times that
     capacity, served batched and then plain (one at a time).  Every result is checked against
@@ -338,11 +344,11 @@ def run_mix(n_queries: int = 24, rings=(14, 15, 16), rows_lo: int = 1 << 10, row
     round_cts = {r: round_cts_16 << (16 - r) for r in rings}
     for q in qs:
         q.arrival = 0.0
-    cap = serve(qs, engines, mode="batched", round_cts=round_cts)
+    cap = serve(qs, engines, mode="batched", round_cts=round_cts, policy=policy)
     rate = load * len(qs) / cap["makespan_s"]
     poisson_arrivals(qs, rate, seed)
     release_cache(engines)
-    batched = serve(qs, engines, mode="batched", round_cts=round_cts)
+    batched = serve(qs, engines, mode="batched", round_cts=round_cts, policy=policy)
     bad = check(qs, engines)
     log(f"[serve] batched: p50 {batched['p50_ms']:.0f} ms, p99 {batched['p99_ms']:.0f} ms, "
         f"{batched['rows_per_s']:.0f} rows/s")
@@ -354,7 +360,7 @@ def run_mix(n_queries: int = 24, rings=(14, 15, 16), rows_lo: int = 1 << 10, row
                        **security_estimate(r, *RING_CHAINS[r])} for r in rings}
     out = {"queries": len(qs), "rows": sum(q.rows for q in qs), "rows_lo": rows_lo, "rows_hi": rows_hi,
            "load_of_batched_capacity": load, "arrival_rate_qps": rate, "batched_capacity_rows_per_s": cap["rows_per_s"],
-           "batched": batched, "plain": plain, "wrong_results": bad, "chains": chains}
+           "policy": policy, "batched": batched, "plain": plain, "wrong_results": bad, "chains": chains}
     del engines
     release_cache({})
     return out
@@ -369,9 +375,11 @@ def main(argv=None):
     ap.add_argument("--rows-hi", type=int, default=1 << 14)
     ap.add_argument("--load", type=float, default=0.8, help="offered load as a fraction of the batched capacity")
     ap.add_argument("--round-cts", type=int, default=16, help="ciphertexts per round at N = 2^16 (scaled by N)")
+    ap.add_argument("--policy", choices=("srpt", "fifo"), default="srpt",
+                    help="order in which a round takes the queued queries' ciphertexts")
     args = ap.parse_args(argv)
     rings = [int(x) for x in args.rings.split(",")]
-    out = run_mix(args.queries, rings, args.rows_lo, args.rows_hi, args.load, args.round_cts)
+    out = run_mix(args.queries, rings, args.rows_lo, args.rows_hi, args.load, args.round_cts, policy=args.policy)
     print(json.dumps(out), flush=True)
     return out
 
