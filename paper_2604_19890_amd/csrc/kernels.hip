@@ -530,16 +530,30 @@ __device__ __forceinline__ uint32_t brv32(uint32_t v, int bits) { return __brev(
 
 // X -> X^g in evaluation form: slot j holds a(psi^(2 brv(j)+1)); the image holds
 // a(psi^((2 brv(j)+1) g)), i.e. the input slot j' with 2 brv(j')+1 = (2 brv(j)+1) g mod 2N.
+__device__ __forceinline__ uint32_t automorph_src(uint32_t j, int logN, uint32_t g) {
+  const uint32_t e = 2 * brv32(j, logN) + 1;
+  const uint32_t e2 = (uint32_t)(((uint64_t)e * g) & ((2u << logN) - 1));
+  return brv32((e2 - 1) >> 1, logN);
+}
+
+// Multiplying by the odd g mod 2N maps the low bits of an exponent to low bits only, and the
+// low bits of 2 brv(j)+1 are the high bits of j: the 2^logB destination slots that share their
+// high bits read 2^logB source slots that share theirs.  A block stages that source block in
+// LDS (coalesced reads), gathers there and writes its destination block (coalesced writes).
+// x and y must not overlap.
 __global__ void k_automorph(const uint64_t* __restrict__ x, int64_t xs, uint64_t* __restrict__ y, int64_t ys, int rows,
-                            int logN, int g) {
-  const int N = 1 << logN;
+                            int logN, int logB, uint32_t g) {
+  extern __shared__ uint64_t sblk[];
+  const int N = 1 << logN, B = 1 << logB;
   const int ct = blockIdx.y / rows;
   const int r = blockIdx.y % rows;
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t e = 2 * brv32(j, logN) + 1;
-  const uint32_t e2 = (uint32_t)(((uint64_t)e * (uint32_t)g) & (uint32_t)(2 * N - 1));
-  const uint32_t jp = brv32((e2 - 1) >> 1, logN);
-  y[(size_t)ct * ys + (size_t)r * N + j] = x[(size_t)ct * xs + (size_t)r * N + jp];
+  const uint32_t d0 = (uint32_t)blockIdx.x << logB;  // first destination slot of the block
+  const uint32_t s0 = automorph_src(d0, logN, g) & ~(uint32_t)(B - 1);  // its source block
+  const uint64_t* __restrict__ xr = x + (size_t)ct * xs + (size_t)r * N + s0;
+  for (int t = threadIdx.x; t < B; t += blockDim.x) sblk[t] = __builtin_nontemporal_load(&xr[t]);
+  __syncthreads();
+  uint64_t* __restrict__ yr = y + (size_t)ct * ys + (size_t)r * N + d0;
+  for (int t = threadIdx.x; t < B; t += blockDim.x) yr[t] = sblk[automorph_src(d0 + t, logN, g) - s0];
 }
 
 __global__ void k_from_signed(const int64_t* __restrict__ v, uint64_t* __restrict__ y, int rows, int N, LimbMap lm,
@@ -747,8 +761,10 @@ void batch_sum(bgv_ctx* c, const uint64_t* x, uint64_t* out, int n, int level) {
 }
 
 void automorph(bgv_ctx* c, const uint64_t* x, int64_t xs, uint64_t* y, int64_t ys, int n, int rows, int g) {
-  hipLaunchKernelGGL(k_automorph, grid_for(c->N, n * rows), dim3(block_for(c->N)), 0, c->stream, x, xs, y, ys, rows,
-                     c->logN, g);
+  const int logB = c->logN < 12 ? c->logN : 12;  // 32 KiB of LDS per block
+  const int B = 1 << logB;
+  hipLaunchKernelGGL(k_automorph, dim3(c->N >> logB, n * rows), dim3(B < 256 ? B : 256), (size_t)B * 8, c->stream, x,
+                     xs, y, ys, rows, c->logN, logB, (uint32_t)g);
 }
 
 void from_signed(bgv_ctx* c, const int64_t* v, uint64_t* y, int n_polys, int rows, LimbMap lm) {
