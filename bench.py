@@ -60,11 +60,11 @@ NTT_COUNTERS = {
 # summed) from the same two counter runs of `bench.py --ks-only --cts 32 --steps 3`, with the
 # copy-derived scales (profiles/product_step_n65536_b32.md).
 KS_COUNTERS = {
-    "sources_sha256": "3423460456f66ba90c5b1515becd05cc0742cbba298cba15f4fa5591dc4412e2",
+    "sources_sha256": "497fb3f429c55cdcf1f36f58207cb57e4b92e3b5ebea532b3a8b4392aed76ebe",
     "sources": ('ntt.hip', 'keyswitch.hip', 'kernels.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp', 'ops.cpp'),
     "units": 32,  # ciphertext pairs
-    "fetch_kib": [5366160],  # the step's 11 dispatches summed (mean of two repetitions)
-    "write_kib": [8983898],
+    "fetch_kib": [5366164],  # the step's 11 dispatches summed (mean of two repetitions)
+    "write_kib": [8984011],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
