@@ -1,0 +1,58 @@
+"""The fused ModUp gives the same words as ModUp between full transforms.
+
+Key switching raises d2 to the special primes either inside the column pass of the forward
+transform (bgv_set_modup_fused on, the default) or as inverse transform, basis extension and
+forward transform in separate launches.  The two are compared on a two-pass ring small
+enough for the oracle (whose parity tests run the fused form), at every first-pass length
+the ring allows, and at the benchmark's ring (N = 2^16, 30 + 6 primes) with a broadcast
+operand and with an operand that is a view of the lower limbs of a deeper batch."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import space as S
+from tests.gpu_ctx import Pair, log, pair_two_pass
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(lib, keys, a, b):
+    f = lib.mul(keys, a, b)
+    lib.set_modup_fused(False)
+    try:
+        u = lib.mul(keys, a, b)
+    finally:
+        lib.set_modup_fused(True)
+    torch.cuda.synchronize()
+    assert (f.n, f.level, f.t_exp, f.noise) == (u.n, u.level, u.t_exp, u.noise)
+    w = f.n * lib.words(f.level)
+    assert torch.equal(f.tensor[:w], u.tensor[:w]), "fused ModUp differs from the separate launches"
+    return f
+
+
+def test_fused_modup_matches_on_a_two_pass_ring():
+    c = pair_two_pass()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(61)
+    ga, oa = c.enc_both(g.integers(0, t, size=(3, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(3, P.ell)))
+    try:
+        for split in range(4, 7):  # every first-pass length the ring allows, so every second pass
+            c.lib.set_ntt_split(split)
+            f = _both(c.lib, c.keys, ga, gb)
+            c.assert_equal(f, [S._mul(P, c.okeys, x, y) for x, y in zip(oa, ob)], f"product, split {split}")
+    finally:
+        c.lib.set_ntt_split(0)
+
+
+def test_fused_modup_matches_at_the_benchmark_ring():
+    log("[fusions] N=2^16 L=30 K=6")
+    c = Pair(16, 257, 2, 30, 6, steps=(), conj=False, oracle_keys=False, hw=120)
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(62)
+    ga, _ = c.enc_both(g.integers(0, t, size=(3, P.ell)), oracle=False)
+    gb, _ = c.enc_both(g.integers(0, t, size=(1, P.ell)), oracle=False)
+    _both(c.lib, c.keys, ga, gb)  # broadcast b
+    lo = c.lib.mod_switch_to(ga, 29)
+    hi = c.lib.mul(c.keys, ga, ga)  # level 29: its noise lets lo's partner be dropped to 28
+    _both(c.lib, c.keys, c.lib.mod_switch_to(lo, 28), hi)  # hi reaches 28 as a view of its limbs
