@@ -60,11 +60,11 @@ NTT_COUNTERS = {
 # summed) from the same two counter runs of `bench.py --ks-only --cts 32 --steps 3`, with the
 # copy-derived scales (profiles/product_step_n65536_b32.md).
 KS_COUNTERS = {
-    "sources_sha256": "497fb3f429c55cdcf1f36f58207cb57e4b92e3b5ebea532b3a8b4392aed76ebe",
+    "sources_sha256": "abfe68b57a5ee8a7648a93ebdf9912e75a1f213e31d0bff43046627dbdad34c1",
     "sources": ('ntt.hip', 'keyswitch.hip', 'kernels.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp', 'ops.cpp'),
     "units": 32,  # ciphertext pairs
-    "fetch_kib": [5366164],  # the step's 11 dispatches summed (mean of two repetitions)
-    "write_kib": [8984011],
+    "fetch_kib": [5366148],  # the step's 11 dispatches summed (mean of three repetitions)
+    "write_kib": [8983926],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -290,6 +290,75 @@ def product_step(ctx, keys, cts, reps=5):
             "traffic": counter_bytes(KS_COUNTERS, b.n),
             "op": f"bgv_mul of {b.n} ciphertext pairs at level {b.level} (N=2^16, K=6): reads 4 l, writes "
                   f"2 (l - 1) limbs per ciphertext, plus the relinearisation key once"}
+
+
+def stream_query(ctx, keys, s, total_rows, cts_per_step, seed=0, wl=3):
+    """The whole filter+SUM query over `total_rows` rows, streamed through the GPU in steps of
+    `cts_per_step` ciphertexts per column: each step's columns are drawn and encrypted on the
+    host, their masked products formed and summed over the batch on the GPU; the steps' sums
+    are summed as one batch (so the noise estimate bounds n terms at once) and one
+    rotate-and-sum ends the query.  GPU time is taken with events around each
+    step's calls (host encryption is outside it) and reported beside the wall time."""
+    import torch
+    from paper_2604_19890_amd import synth
+    ell, t = ctx.slots, ctx.t
+    per = cts_per_step * ell
+    n_steps = -(-total_rows // per)
+    g = synth.rng(seed, wl, synth.SLOTS, 0)
+    thr = int(g.integers(0, 1 << 16))
+    t_ct = encrypt_rows(ctx, s, np.full((1, ell), thr), wl, 1 << 30, seed)
+    parts, exp, sql, agree, done = [], 0, 0, 0, 0
+    gpu_ms, host_s = 0.0, 0.0
+    wall0 = time.perf_counter()
+    start, stop = events()
+    for k in range(n_steps):
+        rows_k = min(per, total_rows - done)
+        n_k = -(-rows_k // ell)
+        h0 = time.perf_counter()
+        gk = synth.rng(seed, wl, synth.SLOTS, 1 + k)
+        cols = {c: gk.integers(0, 1 << 16, size=(n_k, ell), dtype=np.uint64) for c in "abc"}
+        if rows_k < n_k * ell:  # a ragged last ciphertext: its unused slots carry b = 0
+            cols["b"].reshape(-1)[rows_k:] = 0
+        cts = {c: encrypt_rows(ctx, s, cols[c], wl, (3 * k + j) * cts_per_step, seed) for j, c in enumerate("abc")}
+        a, b, c = (cols[x].astype(np.int64) for x in "abc")
+        circ = ((a - thr) % t) > (t - 1) // 2
+        exp = (exp + int((b * c * circ).sum())) % t
+        sql = (sql + int((b * c * (a < thr)).sum())) % t
+        agree += int((circ == (a < thr)).reshape(-1)[:rows_k].sum())
+        host_s += time.perf_counter() - h0
+        start.record()
+        parts.append(ctx.batch_sum(ctx.filter_products(keys, cts["a"], t_ct, cts["b"], cts["c"])))
+        stop.record()
+        torch.cuda.synchronize()
+        gpu_ms += start.elapsed_time(stop)
+        done += rows_k
+        if (k + 1) % 16 == 0 or k + 1 == n_steps:
+            log(f"[full] step {k + 1}/{n_steps}: {done} rows, GPU {gpu_ms / 1e3:.1f} s, host {host_s:.1f} s")
+    start.record()
+    total = ctx.rotate_sum(keys, ctx.batch_sum(ctx.concat(parts)))
+    stop.record()
+    torch.cuda.synchronize()
+    gpu_ms += start.elapsed_time(stop)
+    got = ctx.decrypt(s, total)[0]
+    return {"rows": done, "steps": n_steps, "cts_per_step": cts_per_step, "gpu_s": gpu_ms / 1e3,
+            "rows_per_s_gpu": done / (gpu_ms / 1e3), "wall_s": time.perf_counter() - wall0,
+            "host_encrypt_s": host_s, "decrypted_sum_correct": all(int(v) == exp for v in got),
+            "rows_agree": agree / done, "sum_equals_sql": exp == sql, "final_level": total.level,
+            "final_noise_bits": total.noise / 16}
+
+
+def full_query(args):
+    """The configured query at its full size (2^20 rows, 8192 ciphertexts per column at
+    N = 2^16), streamed in steps of --cts ciphertexts per column."""
+    from paper_2604_19890_amd import bgv as G
+    from paper_2604_19890_amd import synth
+    ctx = G.Context(LOG_N, P_, R_, L_, K_)
+    wl = 3
+    s = synth.ternary(ctx.N, args.seed, wl)
+    keys = make_keys(ctx, s, wl, args.seed, [1 << i for i in range(6)], True)
+    res = stream_query(ctx, keys, s, 1 << 20, args.cts, args.seed, wl)
+    print(json.dumps({"full_query": res, "config": {
+        "workload": "filter_sum N=2^16 p=257 r=2 L=30 K=6, 2^20 rows of 16-bit columns streamed"}}), flush=True)
 
 
 def ntt_only(args):
@@ -561,6 +630,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip timing the step replayed from a hipGraph")
     ap.add_argument("--ntt-only", action="store_true",
                     help="only the forward NTT at the query shape and a copy of the same bytes (for counters)")
+    ap.add_argument("--full-query", action="store_true",
+                    help="only the whole 2^20-row query, streamed in steps of --cts ciphertexts per column")
     ap.add_argument("--ks-only", action="store_true",
                     help="only the product step at the query shape and a copy (for counters)")
     ap.add_argument("--no-check", action="store_true")
@@ -589,6 +660,9 @@ def main():
         return
     if args.ks_only:
         ks_only(args)
+        return
+    if args.full_query:
+        full_query(args)
         return
     ctx, keys, s, cols, thr, cts, cols15, thr15, cts15 = setup(args)
     if args.bits < 16:  # the whole run on the narrower filter column

@@ -253,7 +253,9 @@ bgv_status bgv_rotate_sum(bgv_ctx* ctx, const bgv_keys* keys, const bgv_ct* in, 
  *   level (as in the context's schedule, bgv_set_schedule), multiplied and
  *   relinearised, then switched down one prime (output level = min level - 1).  b may
  *   be a single ciphertext broadcast against a batch.
- * bgv_batch_sum: out (one ciphertext) = sum of the in->n ciphertexts of a batch.
+ * bgv_batch_sum: out (one ciphertext) = sum of the in->n ciphertexts of a batch;
+ *   its noise estimate is the batch's plus ceil(16 log2 n) (n terms, each bounded by
+ *   the batch's estimate).
  * bgv_filter_sum: the filter-and-aggregate query SUM(b*c WHERE a < thr) over the
  *   rows packed in the slots of the batches a, b, c (thr: one ciphertext, or a batch
  *   of the same size): per ciphertext [a < thr] * (b * c) with the product steps

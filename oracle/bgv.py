@@ -215,6 +215,21 @@ def add(P: Params, a: Ct, b: Ct) -> Ct:
     return Ct((a.c + b.c) % q, a.level, a.t_exp, NZ.add(a.nz, b.nz))
 
 
+def add_many(P: Params, cts) -> Ct:
+    """The sum of ciphertexts of one level and plaintext modulus, as one sum of n terms:
+    its estimate bounds n terms by the largest (a + lgc(n)), not by a chain of pairwise
+    additions, each of which would add at least a sixteenth of a bit."""
+    acc = cts[0]
+    for x in cts[1:]:
+        _check_pair(acc, x)
+    q = _qcol(P.q[: acc.level])
+    tot = acc.c
+    for x in cts[1:]:
+        tot = (tot + x.c) % q
+    nz = NZ.sum_of(max(x.nz for x in cts), len(cts)) if all(NZ.known(x.nz) for x in cts) else 0
+    return Ct(tot, acc.level, acc.t_exp, nz)
+
+
 def sub(P: Params, a: Ct, b: Ct) -> Ct:
     _check_pair(a, b)
     q = _qcol(P.q[: a.level])

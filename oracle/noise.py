@@ -105,6 +105,11 @@ def known(*xs) -> bool:
     return all(x > 0 for x in xs)
 
 
+def sum_of(a: int, n: int) -> int:
+    """A bound on a sum of n terms, each bounded by 2^(a/16): n 2^(a/16), i.e. a + lgc(n)."""
+    return max(1, a + lgc(n)) if known(a) else 0
+
+
 def add(a: int, b: int) -> int:
     return max(1, lsum(a, b)) if known(a, b) else 0
 

@@ -10,6 +10,7 @@
 //   key switch adds    lsum(lgc(23 alpha t) + ceil(lgc(dnum_l) / 2) + 8 n, lgc(3 alpha t) + 8 n)
 //   scalar k           a + lgc(|k|);  constant k: lsum(a, lgc(|k|));  DivideByP: a - lgf(p)
 //   add / sub          lsum(a, b);  tag changes, negation, dropped limbs: a
+//   sum of n terms     a + lgc(n)   (each bounded by 2^a; the batch sum)
 // lgc / lgf are ceil / floor of 16 log2 x, exact; lsum(a, b) bounds log2(2^a + 2^b).
 #include <algorithm>
 #include <cstdlib>
@@ -114,6 +115,8 @@ void noise_init(bgv_ctx* c) {
 }
 
 int nz_add(int a, int b) { return a > 0 && b > 0 ? known1(lsum(a, b)) : 0; }
+
+int nz_sum_of(int a, int n) { return a > 0 ? known1(a + nz_lgc((uint64_t)n)) : 0; }
 
 int nz_scalar(int a, int64_t k) { return a > 0 ? known1(a + (k ? nz_lgc((uint64_t)std::llabs(k)) : 0)) : 0; }
 

@@ -1179,15 +1179,14 @@ CipherP ev_less_than(bgv_ctx* c, const bgv_keys* k, const CipherP& x, const Ciph
   return ev_space_raise(c, k, ev_compare(c, k, dg, BGV_OP_LT));
 }
 
-// the ciphertexts of a batch summed; the estimate is that of adding them one by one
+// the ciphertexts of a batch summed; the estimate bounds the n terms by the largest
+// (a + lgc(n)) rather than chaining n - 1 pairwise sums
 CipherP ev_batch_sum(bgv_ctx* c, const CipherP& x0) {
   const CipherP x = ev_materialize(c, x0);
   algo(c, 2.0 * x->v.level * (x->v.n + 1));
   CipherP r = new_cipher(c, 1, x->v.level, x->v.t_exp);
   lk::batch_sum(c, x->v.d, r->v.d, x->v.n, x->v.level);
-  int nz = x->v.nz;
-  for (int i = 1; i < x->v.n; ++i) nz = nz_add(nz, x->v.nz);
-  r->v.nz = nz;
+  r->v.nz = nz_sum_of(x->v.nz, x->v.n);
   return r;
 }
 

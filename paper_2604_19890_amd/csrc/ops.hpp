@@ -76,6 +76,7 @@ void noise_init(bgv_ctx* c);
 int nz_lgc(uint64_t x);  // ceil(16 log2 x)
 int nz_lgf(uint64_t x);  // floor(16 log2 x)
 int nz_add(int a, int b);
+int nz_sum_of(int a, int n);
 int nz_scalar(int a, int64_t k_centered);
 int nz_add_const(int a, int64_t k_centered);
 int nz_divide_by_p(const bgv_ctx* c, int a);

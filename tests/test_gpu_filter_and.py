@@ -53,10 +53,7 @@ def _run(c, spec, n, seed, sum_too):
             assert int(got[b][j]) == ((int(bv[b][j]) * int(cv[b][j])) % t if ok else 0), (b, j)
     if sum_too:
         fs = c.lib.filter_and_sum(c.keys, gpreds, gb, gc)
-        acc = oprods[0]
-        for pr in oprods[1:]:
-            acc = B.add(P, acc, pr)
-        c.assert_equal(fs, [S.rotate_and_sum(P, c.okeys, acc)], "filter_and_sum")
+        c.assert_equal(fs, [S.rotate_and_sum(P, c.okeys, B.add_many(P, oprods))], "filter_and_sum")
 
 
 @pytest.mark.parametrize("spec", [[("a", 40, "ge"), ("a", 200, "lt")],

@@ -233,10 +233,10 @@ def test_workload_glue_matches():
     gbc = c.lib.mul_scalar(gb, 1)  # a copy of gb's words
     c.assert_equal(c.lib.mul(c.keys, gbc, gc, out=gbc), om, "mul into its first operand")
     bs = c.lib.batch_sum(gb)
-    c.assert_equal(bs, [B.add(P, ob[0], ob[1])], "batch_sum")
+    c.assert_equal(bs, [B.add_many(P, ob)], "batch_sum")
     fs = c.lib.filter_sum(c.keys, ga, gt, gb, gc)
     prods = [S.filter_product(P, c.okeys, x, ot[0], y, z) for x, y, z in zip(oa, ob, oc)]
-    ref = S.rotate_and_sum(P, c.okeys, B.add(P, prods[0], prods[1]))
+    ref = S.rotate_and_sum(P, c.okeys, B.add_many(P, prods))
     c.assert_equal(fs, [ref], "filter_sum")
     cen = lambda v: v - t if v > (t - 1) // 2 else v
     expect = sum(int(y) * int(z) for ra, rb, rc in zip(a_rows, b_rows, c_rows)

@@ -159,7 +159,7 @@ def test_filter_sum_and_relu_match_at_p257(log_n):
     assert st["max_inner_terms"] == 16 and st["max_inner_outputs"] >= 9 and st["max_tensor_pairs"] >= 8
     log(f"[p257] N={P.N} filter_sum done; oracle ...")
     prods = [S.filter_product(P, c.okeys, x, ot[0], y, z) for x, y, z in zip(oa, ob, oc)]
-    ref = S.rotate_and_sum(P, c.okeys, B.add(P, B.add(P, prods[0], prods[1]), prods[2]))
+    ref = S.rotate_and_sum(P, c.okeys, B.add_many(P, prods))
     c.assert_equal(fs, [ref], "filter_sum")
     want = sum(int(y) * int(z) for ra, rb, rc in zip(a_rows, b_rows, c_rows)
                for x, y, z in zip(ra, rb, rc) if centered(int(x) - thr) < 0) % T_

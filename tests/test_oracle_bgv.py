@@ -74,6 +74,26 @@ def test_linear_operations_act_slotwise():
         B.add(P, A, B.mod_switch(P, Bc))
 
 
+def test_sum_of_many_is_the_chained_sum():
+    """add_many: the same words as pairwise additions, slot-wise sums under decryption, and
+    level checks; only its estimate differs (n terms bounded by the largest)."""
+    c = tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(21)
+    rows = [list(g.integers(0, t, size=P.ell)) for _ in range(6)]
+    cts = [c.enc(r) for r in rows]
+    tot = B.add_many(P, cts)
+    chain = cts[0]
+    for x in cts[1:]:
+        chain = B.add(P, chain, x)
+    assert np.array_equal(tot.c, chain.c) and (tot.level, tot.t_exp) == (chain.level, chain.t_exp)
+    assert c.dec(tot) == [sum(col) % t for col in zip(*rows)]
+    assert B.add_many(P, cts[:1]).nz == cts[0].nz and np.array_equal(B.add_many(P, cts[:1]).c, cts[0].c)
+    assert tot.nz < chain.nz
+    with pytest.raises(ValueError):
+        B.add_many(P, [cts[0], B.mod_switch(P, cts[1])])
+
+
 @pytest.mark.parametrize("ctx", [tiny5, tiny17])
 def test_mod_switch_is_the_nearest_congruent_rescaling(ctx):
     """BGV modulus switching: the output (as an integer mod Q') is the integer x closest to

@@ -52,6 +52,40 @@ def test_lsum_bounds_the_sum_of_the_bounds():
     assert NZ.lsum(100, 100) == 116  # equal bounds: one bit more
 
 
+def test_sum_of_n_bounds_n_terms():
+    for a in (1, 7, 100, 333, 800):
+        for n in list(range(1, 70)) + [255, 256, 257, 8192, 10 ** 6]:
+            e = NZ.sum_of(a, n)
+            assert e >= a + 16 * math.log2(n) - 1e-9 and e - (a + 16 * math.log2(n)) < 1, (a, n)
+            assert 2 ** e >= n ** 16 * 2 ** a  # exact: n 2^(a/16) <= 2^(e/16)
+    assert NZ.sum_of(0, 5) == 0  # unknown stays unknown
+    # against the chain of pairwise sums: equal for two and three terms, tighter from four on
+    for a in (50, 400):
+        chain = a
+        for n in range(2, 300):
+            chain = NZ.add(chain, a)
+            if n <= 3:
+                assert NZ.sum_of(a, n) == chain, n
+            else:
+                assert NZ.sum_of(a, n) < chain, n
+
+
+def test_sum_estimate_bounds_the_noise_of_long_sums():
+    """The n-term bound against the measured noise of sums of fresh ciphertexts and of
+    products, at the benchmark's plaintext modulus."""
+    c = p257()
+    P = c.P
+    rng = np.random.default_rng(15)
+    fresh = [c.enc(rng.integers(0, P.t_full, P.ell)) for _ in range(40)]
+    for n in (4, 17, 40):
+        tot = B.add_many(P, fresh[:n])
+        assert _measured_bits(P, c.s, tot) <= tot.nz / 16
+    prods = [S._mul(P, c.keys, fresh[i], fresh[i + 1]) for i in range(0, 16, 2)]
+    tot = B.add_many(P, prods)
+    assert _measured_bits(P, c.s, tot) <= tot.nz / 16
+    assert _measured_bits(P, c.s, S.rotate_and_sum(P, c.keys, tot)) <= S.rotate_and_sum(P, c.keys, tot).nz / 16
+
+
 def _measured_bits(P, s, ct):
     V = B.phase(P, s, ct)
     mx = max(abs(v) for v in V)

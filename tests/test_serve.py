@@ -67,10 +67,7 @@ def test_served_results_match_the_oracle():
             prods = [S.filter_product(P, okeys, x, ot, y, z) for x, y, z in zip(oa, ob, oc)]
         else:
             prods = [S._mul(P, okeys, y, z) for y, z in zip(ob, oc)]
-        acc = prods[0]
-        for pr in prods[1:]:
-            acc = B.add(P, acc, pr)
-        ref = S.rotate_and_sum(P, okeys, acc)
+        ref = S.rotate_and_sum(P, okeys, B.add_many(P, prods))
         r = q.result
         w = r.tensor[: e.ctx.words(r.level)].clone()
         e.ctx.ntt(w, 2, r.level, inverse=True)
