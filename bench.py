@@ -347,6 +347,57 @@ def stream_query(ctx, keys, s, total_rows, cts_per_step, seed=0, wl=3):
             "final_noise_bits": total.noise / 16}
 
 
+def stream_relu(ctx, keys, s, total, cts_per_call, seed=0, wl=6):
+    """ReLU over `total` int8 activations (round-half-even of N(0, 32^2), clipped to [-128, 127],
+    embedded mod p^r), in calls of `cts_per_call` ciphertexts drawn and encrypted on the host
+    call by call; every output is decrypted and checked against max(x, 0).  GPU time is taken
+    with events around each call."""
+    import torch
+    from paper_2604_19890_amd import synth
+    ell = ctx.slots
+    per = cts_per_call * ell
+    n_calls = -(-total // per)
+    gpu_ms, host_s, done, wrong = 0.0, 0.0, 0, 0
+    wall0 = time.perf_counter()
+    start, stop = events()
+    for k in range(n_calls):
+        n_k = -(-min(per, total - done) // ell)
+        h0 = time.perf_counter()
+        x = synth.int8_activations(n_k * ell, 32.0, seed, wl, 1 + k).reshape(n_k, ell)
+        X = encrypt_rows(ctx, s, x % ctx.t, wl, k * cts_per_call, seed)
+        host_s += time.perf_counter() - h0
+        start.record()
+        out = ctx.relu(keys, X)
+        stop.record()
+        torch.cuda.synchronize()
+        gpu_ms += start.elapsed_time(stop)
+        h0 = time.perf_counter()
+        got = ctx.decrypt(s, out)
+        cnt = min(per, total - done)
+        wrong += int((got.reshape(-1)[:cnt] != (np.maximum(x, 0) % ctx.t).reshape(-1)[:cnt]).sum())
+        host_s += time.perf_counter() - h0
+        done += cnt
+        if (k + 1) % 8 == 0 or k + 1 == n_calls:
+            log(f"[relu] call {k + 1}/{n_calls}: {done} activations, GPU {gpu_ms / 1e3:.1f} s, host {host_s:.1f} s")
+    return {"activations": done, "calls": n_calls, "cts_per_call": cts_per_call, "gpu_s": gpu_ms / 1e3,
+            "activations_per_s_gpu": done / (gpu_ms / 1e3), "wall_s": time.perf_counter() - wall0,
+            "host_s": host_s, "wrong": wrong}
+
+
+def full_relu(args):
+    """The ReLU workload at its full size (2^18 activations = 2048 ciphertexts at N = 2^16), in
+    calls of --relu-cts ciphertexts."""
+    from paper_2604_19890_amd import bgv as G
+    from paper_2604_19890_amd import synth
+    ctx = G.Context(LOG_N, P_, R_, L_, K_)
+    wl = 6
+    s = synth.ternary(ctx.N, args.seed, wl)
+    keys = make_keys(ctx, s, wl, args.seed, [], False)
+    res = stream_relu(ctx, keys, s, 1 << 18, args.relu_cts, args.seed, wl)
+    print(json.dumps({"full_relu": res, "config": {
+        "workload": "relu N=2^16 p=257 r=2 L=30 K=6, 2^18 int8 activations"}}), flush=True)
+
+
 def full_query(args):
     """The configured query at its full size (2^20 rows, 8192 ciphertexts per column at
     N = 2^16), streamed in steps of --cts ciphertexts per column."""
@@ -632,6 +683,8 @@ def main():
                     help="only the forward NTT at the query shape and a copy of the same bytes (for counters)")
     ap.add_argument("--full-query", action="store_true",
                     help="only the whole 2^20-row query, streamed in steps of --cts ciphertexts per column")
+    ap.add_argument("--full-relu", action="store_true",
+                    help="only the whole 2^18-activation ReLU workload, in calls of --relu-cts ciphertexts")
     ap.add_argument("--ks-only", action="store_true",
                     help="only the product step at the query shape and a copy (for counters)")
     ap.add_argument("--no-check", action="store_true")
@@ -663,6 +716,9 @@ def main():
         return
     if args.full_query:
         full_query(args)
+        return
+    if args.full_relu:
+        full_relu(args)
         return
     ctx, keys, s, cols, thr, cts, cols15, thr15, cts15 = setup(args)
     if args.bits < 16:  # the whole run on the narrower filter column

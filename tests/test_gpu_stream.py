@@ -1,4 +1,5 @@
-"""The streamed whole-query leg of the benchmark (bench.stream_query) on a small ring.
+"""The streamed whole-workload legs of the benchmark (bench.stream_query, bench.stream_relu)
+on a small ring.
 
 The full-size run (2^20 rows at N = 2^16) takes minutes, so the leg's bookkeeping is checked
 here on the benchmark's plaintext modulus and chain at N = 2^10: several steps, a ragged
@@ -25,3 +26,14 @@ def test_streamed_query_sums_every_row():
     assert res["decrypted_sum_correct"], res
     assert 0.0 < res["rows_agree"] <= 1.0
     assert res["final_noise_bits"] > 0
+
+
+def test_streamed_relu_is_right_on_every_activation():
+    log("[stream] relu N=2^9 p=257 r=2 L=30 K=6")
+    ctx = G.Context(9, 257, 2, 30, 6)
+    s = synth.ternary(ctx.N, 7, 6)
+    keys = bench.make_keys(ctx, s, 6, 7, [], False)
+    total = 3 * ctx.slots + 50  # two calls of two ciphertexts; the last call is ragged
+    res = bench.stream_relu(ctx, keys, s, total, 2, seed=7, wl=6)
+    assert res["activations"] == total and res["calls"] == 2
+    assert res["wrong"] == 0, res
