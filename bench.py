@@ -515,6 +515,45 @@ def primitives(args):
 
 # ----------------------------------------------------------------------------- ReLU sample
 
+def range_leg(args):
+    """A conjunctive filter at the query's shape: SUM(b * c WHERE lo <= a < hi) over --cts
+    ciphertexts per column of 16-bit columns, each predicate reduced and compared in the
+    digit space, the two results multiplied there and raised once.  The AND takes one more
+    product, so the chain has 31 primes.  Timed over --steps steps after one warm-up."""
+    import torch
+    from paper_2604_19890_amd import bgv as G
+    from paper_2604_19890_amd import synth
+    ctx = G.Context(LOG_N, P_, R_, L_ + 1, K_)
+    wl = 7
+    s = synth.ternary(ctx.N, args.seed, wl)
+    keys = make_keys(ctx, s, wl, args.seed, [1 << i for i in range(6)], True)
+    B, ell, t = args.cts, ctx.slots, ctx.t
+    g = synth.rng(args.seed, wl, synth.SLOTS, 0)
+    cols = {k: g.integers(0, 1 << 16, size=(B, ell), dtype=np.uint64) for k in "abc"}
+    lo, hi = sorted(int(v) for v in g.integers(0, 1 << 16, size=2))
+    cts = {k: encrypt_rows(ctx, s, cols[k], wl, 100000 * (j + 1), args.seed) for j, k in enumerate("abc")}
+    tlo = encrypt_rows(ctx, s, np.full((1, ell), lo), wl, 900000, args.seed)
+    thi = encrypt_rows(ctx, s, np.full((1, ell), hi), wl, 900001, args.seed)
+    preds = [(cts["a"], tlo, G.OP_GE), (cts["a"], thi, G.OP_LT)]
+    per = time_calls(lambda: ctx.filter_and_sum(keys, preds, cts["b"], cts["c"]), args.steps, warm=1)
+    out = ctx.filter_and_sum(keys, preds, cts["b"], cts["c"])
+    a, b, c = (cols[k].astype(np.int64) for k in "abc")
+    cen = lambda d: np.where(d % t > (t - 1) // 2, d % t - t, d % t)
+    circ = (cen(a - lo) >= 0) & (cen(a - hi) < 0)
+    sql = (a >= lo) & (a < hi)
+    exp = int((b * c * circ).sum() % t)
+    ok = all(int(v) == exp for v in ctx.decrypt(s, out)[0])
+    res = {"rows_per_s": B * ell / per, "ms_per_step": per * 1e3, "lo": lo, "hi": hi, "primes": ctx.L,
+           "decrypted_sum_correct": ok, "rows_agree": float((circ == sql).mean()),
+           "sum_equals_sql": int((b * c * sql).sum() % t) == exp}
+    log(f"[bench] range filter: {per * 1e3:.1f} ms/step, {B * ell / per:.1f} rows/s, correct={ok}")
+    del cts, preds, keys, out
+    ctx.trim()
+    del ctx
+    torch.cuda.empty_cache()
+    return res
+
+
 def relu_leg(args, ctx, keys, s):
     """ReLU x * (1 - [x < 0]) on int8 activations (round-half-even of N(0, 32^2), clipped to
     [-128, 127], embedded mod 257^2) at the query's ring: calls of `--relu-cts` ciphertexts,
@@ -791,6 +830,7 @@ def main():
         log(f"[bench] plain: {t_plain * 1e3:.1f} ms for {n_plain} ciphertexts, {plain_rows:.1f} rows/s")
 
     relu = relu_leg(args, ctx, keys, s) if extras else None
+    range_filter = range_leg(args) if extras else None
     ctx.trim()
     torch.cuda.empty_cache()
     prims = primitives(args) if extras else None
@@ -838,6 +878,7 @@ def main():
         "sql_exact": sql_exact,
         "primitives": prims,
         "relu": relu,
+        "range_filter": range_filter,
         "served": served,
         "cpu_baseline": cpu,
         "sql_agreement": sql_agreement(cols, thr),
