@@ -225,15 +225,28 @@ __global__ void __launch_bounds__(NT_MAX, 2) k_modup_cols(const uint64_t* __rest
     }
   }
   // ---- every target row outside the digit: ModUp value, first forward pass, store
+  // The first pass under q_m reads only the twiddles w[1 .. S) of its prime (S = 2^LOGS <= NT):
+  // they are staged in LDS, the next target's while the current one is transformed (each
+  // thread loads one word at the top of a row and stores it after the row's second barrier,
+  // when the previous row's readers of that buffer are done; the third barrier publishes it).
+  static_assert(T > 1, "the staged twiddles rely on the exchange barriers");
+  __shared__ double ltw[2][S];
   const double* __restrict__ basis = modup + tab * (size_t)alpha * (1 + Ltot) + alpha;
   uint64_t* __restrict__ yb = y + ((size_t)ct * dn + j) * rows * N + g1;
   const int per = (rows + gridDim.z - 1) / gridDim.z;
   const int m_end = min(rows, ((int)blockIdx.z + 1) * per);
-  for (int m = blockIdx.z * per; m < m_end; ++m) {
-    if (m >= lo && m < lo + na) continue;
-    const int pm = m < level ? m : Lfull + (m - level);
+  auto skip_digit = [&](int m) { return (m >= lo && m < lo + na) ? lo + na : m; };
+  auto prime_of = [&](int m) { return m < level ? m : Lfull + (m - level); };
+  int m = skip_digit(blockIdx.z * per);
+  if (m < m_end && (int)threadIdx.x < S) ltw[0][threadIdx.x] = tw[(size_t)prime_of(m) * N + threadIdx.x];
+  __syncthreads();
+  for (int buf = 0; m < m_end; buf ^= 1) {
+    const int mn = skip_digit(m + 1);
+    const bool stage = mn < m_end && (int)threadIdx.x < S;
+    const double pre = stage ? tw[(size_t)prime_of(mn) * N + threadIdx.x] : 0.0;
+    const int pm = prime_of(m);
     const double q = pc[pm].q, qinv = pc[pm].qinv;
-    const double* __restrict__ w = tw + (size_t)pm * N;
+    const double* w = ltw[buf];
     double bm[ALPHA];
 #pragma unroll
     for (int a = 0; a < ALPHA; ++a) bm[a] = a < na ? basis[(size_t)a * Ltot + pm] : 0.0;
@@ -251,23 +264,23 @@ __global__ void __launch_bounds__(NT_MAX, 2) k_modup_cols(const uint64_t* __rest
       v[i] = red(acc, q, qinv);
     }
     ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
-    if (T > 1) {
-      __syncthreads();
+    __syncthreads();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
-      __syncthreads();
+    for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);
+    __syncthreads();
+    if (stage) ltw[buf ^ 1][threadIdx.x] = pre;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
-      ct_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, tmin_log, q, qinv);
+    for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+    ct_stages<T / 2>(v, w, N, g2, tmin_log, q, qinv);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
-      __syncthreads();
+    for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
+    __syncthreads();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
-    }
+    for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
     uint64_t* yp = yb + (size_t)m * N;
 #pragma unroll
     for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(d2u(canon(red(v[i], q, qinv), q)), &yp[(size_t)i << gs1_log]);
+    m = mn;
   }
 }
 
