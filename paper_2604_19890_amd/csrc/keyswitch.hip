@@ -183,32 +183,54 @@ __global__ void __launch_bounds__(NT_MAX, 2) k_modup_cols(const uint64_t* __rest
   double src[RSRC][16];
   // tables of (level, digit): the folded scales [alpha] and ModUp's Qhat_i mod prime [alpha][Ltot]
   const size_t tab = (size_t)level * dnum + j;
+  // Both passes read only the twiddles w[1 .. S) of their prime (S = 2^LOGS <= NT).  They are
+  // staged in LDS, one row ahead: a thread loads one word of the next row's table at the top
+  // of a row and stores it after the row's second barrier, when the readers of that buffer in
+  // the row before are done; the row's third barrier publishes it.  The last source row
+  // stages the first target's (forward) table.
+  static_assert(T > 1, "the staged twiddles rely on the exchange barriers");
+  __shared__ double ltw[2][S];
+  const double* __restrict__ basis = modup + tab * (size_t)alpha * (1 + Ltot) + alpha;
+  uint64_t* __restrict__ yb = y + ((size_t)ct * dn + j) * rows * N + g1;
+  const int per = (rows + gridDim.z - 1) / gridDim.z;
+  const int m_end = min(rows, ((int)blockIdx.z + 1) * per);
+  auto skip_digit = [&](int m) { return (m >= lo && m < lo + na) ? lo + na : m; };
+  auto prime_of = [&](int m) { return m < level ? m : Lfull + (m - level); };
+  int m = skip_digit(blockIdx.z * per);
+  const bool lane_stages = (int)threadIdx.x < S;
+  if (lane_stages) ltw[0][threadIdx.x] = itw[(size_t)lo * N + threadIdx.x];
+  __syncthreads();
+  int buf = 0;
   // ---- the digit's source rows: last inverse pass, scaled to the ModUp operands
 #pragma unroll
   for (int a = 0; a < ALPHA; ++a) {
     if (a < na) {
       const int pi = lo + a;
       const double q = pc[pi].q, qinv = pc[pi].qinv;
-      const double* __restrict__ w = itw + (size_t)pi * N;
+      const double* w = ltw[buf];
+      const bool last = a + 1 == na;
+      const bool stage = lane_stages && (!last || m < m_end);
+      const double pre = !stage ? 0.0 : last ? tw[(size_t)prime_of(m) * N + threadIdx.x]
+                                             : itw[(size_t)(pi + 1) * N + threadIdx.x];
       const uint64_t* xp = xh + ((size_t)ct * level + pi) * N + g1;
       double v[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = u2d(__builtin_nontemporal_load(&xp[(size_t)i << gs1_log]));
-      if (T > 1) {
-        __syncthreads();  // the previous pass's last LDS reads are done
+      __syncthreads();  // the previous pass's last LDS reads are done
 #pragma unroll
-        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = v[i];
-        __syncthreads();
+      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = v[i];
+      __syncthreads();
+      if (stage) ltw[buf ^ 1][threadIdx.x] = pre;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
-        gs_stages<(T > 1 ? T / 2 : 1)>(v, w, N, g2, tmin_log, q, qinv);
+      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+      gs_stages<T / 2>(v, w, N, g2, tmin_log, q, qinv);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
-        __syncthreads();
+      for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
+      __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
-      }
+      for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
       gs_stages<8>(v, w, N, g1, gs1_log, q, qinv);
+      buf ^= 1;
       const double sc = mu_scale[tab * alpha + a];  // N^-1 Qhat_i^-1 mod q_i
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
@@ -225,22 +247,7 @@ __global__ void __launch_bounds__(NT_MAX, 2) k_modup_cols(const uint64_t* __rest
     }
   }
   // ---- every target row outside the digit: ModUp value, first forward pass, store
-  // The first pass under q_m reads only the twiddles w[1 .. S) of its prime (S = 2^LOGS <= NT):
-  // they are staged in LDS, the next target's while the current one is transformed (each
-  // thread loads one word at the top of a row and stores it after the row's second barrier,
-  // when the previous row's readers of that buffer are done; the third barrier publishes it).
-  static_assert(T > 1, "the staged twiddles rely on the exchange barriers");
-  __shared__ double ltw[2][S];
-  const double* __restrict__ basis = modup + tab * (size_t)alpha * (1 + Ltot) + alpha;
-  uint64_t* __restrict__ yb = y + ((size_t)ct * dn + j) * rows * N + g1;
-  const int per = (rows + gridDim.z - 1) / gridDim.z;
-  const int m_end = min(rows, ((int)blockIdx.z + 1) * per);
-  auto skip_digit = [&](int m) { return (m >= lo && m < lo + na) ? lo + na : m; };
-  auto prime_of = [&](int m) { return m < level ? m : Lfull + (m - level); };
-  int m = skip_digit(blockIdx.z * per);
-  if (m < m_end && (int)threadIdx.x < S) ltw[0][threadIdx.x] = tw[(size_t)prime_of(m) * N + threadIdx.x];
-  __syncthreads();
-  for (int buf = 0; m < m_end; buf ^= 1) {
+  for (; m < m_end; buf ^= 1) {
     const int mn = skip_digit(m + 1);
     const bool stage = mn < m_end && (int)threadIdx.x < S;
     const double pre = stage ? tw[(size_t)prime_of(mn) * N + threadIdx.x] : 0.0;
