@@ -254,19 +254,20 @@ __global__ void __launch_bounds__(NT_MAX, 2) k_modup_cols(const uint64_t* __rest
     const int pm = prime_of(m);
     const double q = pc[pm].q, qinv = pc[pm].qinv;
     const double* w = ltw[buf];
+    // Branch-free over the digit's ALPHA slots: in a shorter last digit (na < ALPHA) the
+    // missing sources are zero and so are their rows of the table (it is zero-filled), so
+    // their terms add exact zeros; every slot's products can then be interleaved.
     double bm[ALPHA];
 #pragma unroll
-    for (int a = 0; a < ALPHA; ++a) bm[a] = a < na ? basis[(size_t)a * Ltot + pm] : 0.0;
+    for (int a = 0; a < ALPHA; ++a) bm[a] = basis[(size_t)a * Ltot + pm];
     double v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       double acc = 0.0;
 #pragma unroll
       for (int a = 0; a < ALPHA; ++a) {
-        if (a < na) {
-          const double x = a < RSRC ? src[a < RSRC ? a : 0][i] : lsrc[((a - RSRC) * 16 + i) * NT_MAX + threadIdx.x];
-          acc += mul_lazy(x, bm[a], q, qinv);
-        }
+        const double x = a < RSRC ? src[a < RSRC ? a : 0][i] : lsrc[((a - RSRC) * 16 + i) * NT_MAX + threadIdx.x];
+        acc += mul_lazy(x, bm[a], q, qinv);
       }
       v[i] = red(acc, q, qinv);
     }
