@@ -172,3 +172,34 @@ def test_filter_sum_and_relu_match_at_p257(log_n):
     got = c.lib.decrypt(c.s, gr)
     for b, row in enumerate(x_rows):
         assert [int(v) for v in got[b]] == [v % T_ if centered(v) >= 0 else 0 for v in row], b
+
+
+def test_sixteen_bit_query_exact_with_r3():
+    """The 16-bit query with t = 257^3: every difference of two 16-bit values lies in the
+    centered range of Z_{257^3}, so the circuit's predicate is the integer one.  Algorithm 3
+    takes two G evaluations (G_{257,3} of degree 513, then G_{257,2}), Algorithm 4 aggregates
+    three digits, and the raise is G_{257,3}; the chain needs 41 primes.  The filter products
+    and the filter+SUM are compared with the oracle word for word at N = 2^8, and the SUM with
+    the integer query."""
+    c = Pair(8, P_, 3, 41, K_, steps=ROT_STEPS, conj=True)
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(313)
+    a_rows = g.integers(0, 1 << 16, size=(2, P.ell))
+    a_rows[0][:6] = [0, 65535, 30000, 29999, 30001, 1]
+    b_rows = g.integers(0, 1 << 16, size=(2, P.ell))
+    c_rows = g.integers(0, 1 << 16, size=(2, P.ell))
+    thr = 30000
+    ga, oa = c.enc_both(a_rows)
+    gb, ob = c.enc_both(b_rows)
+    gc, oc = c.enc_both(c_rows)
+    gt, ot = c.enc_both([[thr] * P.ell])
+    log("[p257 r=3] N=2^8 L=41: library ...")
+    fp = c.lib.filter_products(c.keys, ga, gt, gb, gc)
+    fs = c.lib.filter_sum(c.keys, ga, gt, gb, gc)
+    log("[p257 r=3] oracle ...")
+    prods = [S.filter_product(P, c.okeys, x, ot[0], y, z) for x, y, z in zip(oa, ob, oc)]
+    c.assert_equal(fp, prods, "filter products, r = 3")
+    c.assert_equal(fs, [S.rotate_and_sum(P, c.okeys, B.add_many(P, prods))], "filter_sum, r = 3")
+    want = int(sum(int(y) * int(z) for ra, rb, rc in zip(a_rows, b_rows, c_rows)
+                   for x, y, z in zip(ra, rb, rc) if int(x) < thr) % t)
+    assert np.array_equal(c.lib.decrypt(c.s, fs), np.array([[want] * P.ell]))
