@@ -160,3 +160,22 @@ def test_noise_estimates_through_the_binding():
     both = c.lib.concat([ga, gb])
     assert both.noise == ga.noise
     assert c.lib.concat([ga, blind_a]).noise == 0
+
+
+def test_batch_sum_of_many_matches_the_oracle():
+    """bgv_batch_sum over batches of 1, 4 and 9 ciphertexts: the words and the noise estimate of
+    the oracle's sum of n terms (a + ceil(16 log2 n); a chain of pairwise bounds would differ
+    from four terms on), and the slot-wise sums under decryption."""
+    from oracle import noise as NZ
+    c = pair_tiny17()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(43)
+    rows = g.integers(0, t, size=(9, P.ell))
+    gx, ox = c.enc_both(rows)
+    for n in (1, 4, 9):
+        part = c.lib.view(gx, 0, n)
+        s = c.lib.batch_sum(part)
+        ref = B.add_many(P, ox[:n])
+        c.assert_equal(s, [ref], f"batch_sum of {n}")
+        assert s.noise == NZ.sum_of(ox[0].nz, n) == ref.nz
+        assert c.lib.decrypt(c.s, s).tolist() == [[int(v) % t for v in rows[:n].sum(axis=0)]]
