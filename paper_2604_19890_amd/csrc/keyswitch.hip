@@ -63,10 +63,15 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
   double acc0[16], acc1[16], v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = 0.0;
+  // the first four stages' twiddles depend on the sub-transform only, the same for every digit:
+  // loaded once, so a digit's transform starts without waiting for memory
+  double tw1[15];
+  ct_twiddles<8>(tw1, w, N, g1, gs1_log);
   // Digit j + 1's y row is requested at the start of digit j, in the same batch
-  // as digit j's twiddle loads: loads complete in issue order, so the transform
-  // waits for both, and each digit costs one round trip to memory for its data
-  // and twiddles instead of two.
+  // as digit j's last-four-stage twiddle loads (the first four stages' twiddles are
+  // held in registers): loads complete in issue order, so the transform waits for
+  // both, and each digit costs one round trip to memory for its data and twiddles
+  // instead of two.
   const uint64_t* __restrict__ yrow = y + ((size_t)ct * dn * rows + m) * N + g1;
   const size_t ystep = (size_t)rows * N;
   const int own_j = m < level ? m / alpha : -1;  // the digit whose own prime m is
@@ -86,7 +91,7 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
       for (int i = 0; i < 16; ++i) yn[i] = __builtin_nontemporal_load(&yp[(size_t)i << gs1_log]);
     }
     if (j != own_j) {
-      ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
+      ct_stages_tw<8>(v, tw1, q, qinv);
       if (T > 1) {  // with T = 1 the four register stages were all of the pass
 #pragma unroll
         for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = red(v[i], q, qinv);

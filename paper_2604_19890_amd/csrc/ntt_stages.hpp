@@ -27,6 +27,39 @@ MA_FN void ct_stages(double* v, const double* __restrict__ w, int N, int g0, int
   }
 }
 
+// The twiddles ct_stages<DMAX> reads for (g0, gs_log), in the order it uses them
+// (1 + 2 + .. + 8 = 15 for DMAX = 8), and the same stages taking them from that array: a
+// caller that runs the stages on several rows under one prime loads them once.
+template <int DMAX>
+MA_FN void ct_twiddles(double* tws, const double* __restrict__ w, int N, int g0, int gs_log) {
+  int n = 0;
+#pragma unroll
+  for (int dd = DMAX; dd >= 1; dd >>= 1) {
+    const double* wp = w + ((N + g0) >> (__builtin_ctz(2 * dd) + gs_log));
+#pragma unroll
+    for (int g = 0; g < 16 / (2 * dd); ++g) tws[n++] = wp[g];
+  }
+}
+
+template <int DMAX>
+MA_FN void ct_stages_tw(double* v, const double* tws, double q, double qinv) {
+  int n = 0;
+#pragma unroll
+  for (int dd = DMAX; dd >= 1; dd >>= 1) {
+#pragma unroll
+    for (int g = 0; g < 16 / (2 * dd); ++g) {
+      const double wt = tws[n++];
+#pragma unroll
+      for (int i = g * 2 * dd; i < g * 2 * dd + dd; ++i) {
+        const double r = mul_lazy(v[i + dd], wt, q, qinv);
+        const double a = v[i];
+        v[i] = a + r;
+        v[i + dd] = a - r;
+      }
+    }
+  }
+}
+
 // Gentleman-Sande stages at register distances 1, 2, .., DMAX.
 template <int DMAX>
 MA_FN void gs_stages(double* v, const double* __restrict__ w, int N, int g0, int gs_log,
