@@ -60,11 +60,11 @@ NTT_COUNTERS = {
 # summed) from the same two counter runs of `bench.py --ks-only --cts 32 --steps 3`, with the
 # copy-derived scales (profiles/product_step_n65536_b32.md).
 KS_COUNTERS = {
-    "sources_sha256": "f4793d9c0904f83c94546a61545106c47e192dabc0e4b23eacc303c39f7a908d",
+    "sources_sha256": "bf5703b12649eeae8136ccc2b5424ec603a9e0634adfcb27ec553896865ba2e7",
     "sources": ('ntt.hip', 'keyswitch.hip', 'kernels.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp', 'ops.cpp'),
     "units": 32,  # ciphertext pairs
-    "fetch_kib": [5363661],  # the step's 11 dispatches summed (mean of four repetitions)
-    "write_kib": [8978490],
+    "fetch_kib": [5363657],  # the step's 11 dispatches summed (mean of four repetitions)
+    "write_kib": [8978491],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
