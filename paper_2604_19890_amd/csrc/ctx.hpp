@@ -139,9 +139,13 @@ bool ntt_fused_inner_ok(const bgv_ctx* c);
 // ModUp output y [n][dn][level+K][N] (coefficient form; the own-digit rows are not
 // read): first NTT pass in place, then the second pass fused with the inner product
 // -> u [n][2][level+K][N].  The own-digit rows are the rows of x, the switched
-// polynomial in evaluation form ([n][level][N] at ciphertext stride x_ct_stride).
+// polynomial in evaluation form ([n][level][N] at ciphertext stride x_ct_stride).  With
+// dtop, u's top row (row level - 1) of ciphertext ct and component comp receives
+// + pmod_top * dtop[ct * dtop_ct + comp * dtop_comp] (evaluation form, pmod_top = P mod
+// q_{level-1}).
 void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,
-                         uint64_t* u, int n, int level, bool pass1_done = false);
+                         uint64_t* u, int n, int level, bool pass1_done = false, const uint64_t* dtop = nullptr,
+                         int64_t dtop_ct = 0, int64_t dtop_comp = 0, double pmod_top = 0.0);
 // true when the fused ModUp below applies (two-pass transforms whose first pass has 5..8
 // stages, digits of 1, 2, 4 or 6 primes)
 bool modup_cols_ok(const bgv_ctx* c);
@@ -240,7 +244,7 @@ void lincomb_multi(bgv_ctx* c, const LinMulti& m, int nt, int no, const double* 
 void lincomb(bgv_ctx* c, const uint64_t* const* xs, const int* rows, int nt, const double* sc, int sc_stride,
              int cst_row, uint64_t* out, int n, int level);
 // product step with the modulus switch merged into ModDown, part 1 (part 2 is the
-// epilogue of the forward NTT of e)
+// epilogue of the forward NTT of e); dtop null: u's top row already holds u_top + P d_top
 void ms_corr(bgv_ctx* c, const uint64_t* up, int64_t up_stride, const uint64_t* utop, int64_t ut_stride,
              const uint64_t* dtop, int64_t dt_stride, uint64_t* e, int n, int level, int t_exp);
 // out (one ciphertext) = sum of the n ciphertexts of x

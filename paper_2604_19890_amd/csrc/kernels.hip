@@ -506,7 +506,9 @@ __global__ void k_ms_corr(const uint64_t* __restrict__ up, int64_t up_stride, co
     const double q = pc[it].q, qinv = pc[it].qinv;
     const double wt = fbc(it, q, qinv);
     const double ut = u2d(ld_once(utop + (size_t)cc * ut_stride + n0));
-    const double dt = u2d(ld_once(dtop + (size_t)cc * dt_stride + n0));
+    // with dtop null, u's top row holds u_top + P d_top: (u_top + P d_top - t wt) P^-1 is
+    // the same residue as d_top + (u_top - t wt) P^-1
+    const double dt = dtop ? u2d(ld_once(dtop + (size_t)cc * dt_stride + n0)) : 0.0;
     const double diff = red(ut - mul_lazy(wt, tmod[it], q, qinv), q, qinv);
     const double o = canon(red(dt + mul_lazy(diff, pinv[it], q, qinv), q, qinv), q);
     const double w = canon(mul_lazy(o, tinv[it], q, qinv), q);

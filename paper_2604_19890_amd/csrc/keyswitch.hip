@@ -26,7 +26,9 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
                                                            uint64_t* __restrict__ u, int logN, int s0, int level,
                                                            int dn, int K, int alpha, int Lfull, int Ltot, int n_ct,
                                                            const PrimeD* __restrict__ pc,
-                                                           const double* __restrict__ tw) {
+                                                           const double* __restrict__ tw,
+                                                           const uint64_t* __restrict__ dtop, int64_t dtop_ct,
+                                                           int64_t dtop_comp, double pmod_top) {
   constexpr int S = 1 << LOGS;
   constexpr int T = S / 16;
   constexpr int T_LOG = LOGS - 4;
@@ -122,6 +124,18 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
         acc0[i] = red(acc0[i], q, qinv);
         acc1[i] = red(acc1[i], q, qinv);
       }
+    }
+  }
+  // The product step's switch drops the top prime: there u's top row leaves as
+  // u_top + P d_top (d_top: the tensor's top row, evaluation form), which carries d_top
+  // through the inverse transform of u's top row instead of a transform of its own.
+  if (dtop && m == level - 1) {
+    const uint64_t* __restrict__ d0 = dtop + (size_t)ct * dtop_ct + g1;
+    const uint64_t* __restrict__ d1 = d0 + dtop_comp;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      acc0[i] += mul_lazy(u2d(d0[(size_t)i << gs1_log]), pmod_top, q, qinv);
+      acc1[i] += mul_lazy(u2d(d1[(size_t)i << gs1_log]), pmod_top, q, qinv);
     }
   }
   uint64_t* __restrict__ u0 = u + ((size_t)ct * 2 * rows + m) * N + g1;
@@ -341,7 +355,8 @@ void modup_cols(bgv_ctx* c, const uint64_t* xh, uint64_t* y, int n, int level) {
 }
 
 void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,
-                         uint64_t* u, int n, int level, bool pass1_done) {
+                         uint64_t* u, int n, int level, bool pass1_done, const uint64_t* dtop, int64_t dtop_ct,
+                         int64_t dtop_comp, double pmod_top) {
   const int logN = c->logN;
   int p1, p2;
   ntt_split(c, &p1, &p2);
@@ -357,7 +372,7 @@ void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_c
 #define CASE2(LS)                                                                                              \
   case LS:                                                                                                     \
     hipLaunchKernelGGL((k_ntt2_key_inner<LS>), grid, dim3(NT), 0, c->stream, y, x, x_ct_stride, key, u, logN, p1, \
-                       level, dn, K, A, L, c->Ltot, n, c->d_prime, c->d_tw);                                   \
+                       level, dn, K, A, L, c->Ltot, n, c->d_prime, c->d_tw, dtop, dtop_ct, dtop_comp, pmod_top);  \
     break;
     CASE2(4)
     CASE2(5)

@@ -116,7 +116,9 @@ void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out) {
 // Hybrid key switching, first half: ModUp of each digit of the polynomial x
 // (X = [n][level][N] in evaluation form, left as it is), NTT, and the inner product
 // with the key.  Returns u [n][2][level+K][N] in evaluation form.
-static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const Scratch& X, int n, int level) {
+static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const Scratch& X, int n, int level,
+                                         const uint64_t* dtop = nullptr, int64_t dtop_ct = 0, int64_t dtop_comp = 0,
+                                         double pmod_top = 0.0) {
   const int N = c->N, K = c->prm.K, L = c->prm.L, A = c->alpha;
   const int dn = (level + A - 1) / A, rows = level + K;
   c->stats.key_switches += 1;
@@ -138,7 +140,8 @@ static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const 
   }
   std::unique_ptr<Scratch> U(new Scratch(c, (size_t)n * 2 * rows * N));
   if (fused) {
-    lk::ntt_pass1_key_inner(c, Y.d, X.d, (int64_t)level * N, key, U->d, n, level, mu_fused);
+    lk::ntt_pass1_key_inner(c, Y.d, X.d, (int64_t)level * N, key, U->d, n, level, mu_fused, dtop, dtop_ct, dtop_comp,
+                            pmod_top);
   } else {
     lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0}, false);
     lk::key_inner(c, Y.d, key, U->d, n, level);
@@ -178,7 +181,19 @@ static void relin_ms(bgv_ctx* c, const bgv_keys* keys, Scratch& D, Scratch& X, i
                      const CtV& out) {
   const int N = c->N, K = c->prm.K;
   const int rows = lv + K;
-  auto U = ks_inner(c, keys->relin, X, n, lv);
+  // With the fused inner product, d's top row joins u's as u_top + P d_top (P mod the top
+  // prime), so it needs no inverse transform of its own; otherwise it is transformed apart.
+  const bool fold_top = lk::ntt_fused_inner_ok(c);
+  const uint64_t* dtop = D.d + (size_t)(lv - 1) * N;
+  double pmod_top = 0.0;
+  if (fold_top) {
+    const uint64_t qt = c->primes[lv - 1];
+    uint64_t pm = 1;
+    for (int k = 0; k < K; ++k) pm = mulmod(pm, c->primes[c->prm.L + k] % qt, qt);
+    pmod_top = (double)pm;
+  }
+  auto U = fold_top ? ks_inner(c, keys->relin, X, n, lv, dtop, (int64_t)2 * lv * N, (int64_t)lv * N, pmod_top)
+                    : ks_inner(c, keys->relin, X, n, lv);
   // u's top row and its special rows are the K + 1 consecutive rows lv-1 .. lv+K-1
   // of every polynomial: one inverse transform brings them all to coefficient form
   LimbMap ut{K + 1, 1, c->prm.L, 0, 1, lv - 1, 0};
@@ -186,14 +201,16 @@ static void relin_ms(bgv_ctx* c, const bgv_keys* keys, Scratch& D, Scratch& X, i
   ut.grp_stride = rows;
   ut.grp_first = lv - 1;
   lk::ntt(c, U->d, 2 * n * (K + 1), ut, true);
-  LimbMap top{1, 1, c->prm.L, 0, 1, lv - 1, 0};
-  top.grp = 1;
-  top.grp_stride = lv;
-  top.grp_first = lv - 1;
-  lk::ntt(c, D.d, 2 * n, top, true);  // d tops
+  if (!fold_top) {
+    LimbMap top{1, 1, c->prm.L, 0, 1, lv - 1, 0};
+    top.grp = 1;
+    top.grp_stride = lv;
+    top.grp_first = lv - 1;
+    lk::ntt(c, D.d, 2 * n, top, true);  // d tops
+  }
   Scratch E(c, (size_t)n * 2 * (lv - 1) * N);
   lk::ms_corr(c, U->d + (size_t)lv * N, (int64_t)rows * N, U->d + (size_t)(lv - 1) * N, (int64_t)rows * N,
-              D.d + (size_t)(lv - 1) * N, (int64_t)lv * N, E.d, n, lv, t_exp);
+              fold_top ? nullptr : dtop, (int64_t)lv * N, E.d, n, lv, t_exp);
   // forward NTT of e with the final step in its last pass:
   // out_i = (d_i - e_i + u_i P^-1) q_top^-1 for i < level-1
   lk::NttEpi ep{};
