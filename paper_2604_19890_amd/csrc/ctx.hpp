@@ -142,10 +142,11 @@ bool ntt_fused_inner_ok(const bgv_ctx* c);
 // polynomial in evaluation form ([n][level][N] at ciphertext stride x_ct_stride).  With
 // dtop, u's top row (row level - 1) of ciphertext ct and component comp receives
 // + pmod_top * dtop[ct * dtop_ct + comp * dtop_comp] (evaluation form, pmod_top = P mod
-// q_{level-1}).
+// q_{level-1}).  Rows m >= inv_from (when inv_from >= 0) leave after the first pass of
+// their inverse transform; ntt_inverse_last_pass completes it.
 void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,
                          uint64_t* u, int n, int level, bool pass1_done = false, const uint64_t* dtop = nullptr,
-                         int64_t dtop_ct = 0, int64_t dtop_comp = 0, double pmod_top = 0.0);
+                         int64_t dtop_ct = 0, int64_t dtop_comp = 0, double pmod_top = 0.0, int inv_from = -1);
 // true when the fused ModUp below applies (two-pass transforms whose first pass has 5..8
 // stages, digits of 1, 2, 4 or 6 primes)
 bool modup_cols_ok(const bgv_ctx* c);
@@ -155,6 +156,8 @@ bool modup_cols_ok(const bgv_ctx* c);
 void modup_cols(bgv_ctx* c, const uint64_t* xh, uint64_t* y, int n, int level);
 // the first pass of the inverse transform alone, from src into d
 void ntt_inverse_first_pass(bgv_ctx* c, uint64_t* d, const uint64_t* src, int n_limbs, LimbMap lm);
+// the last pass of the inverse transform alone (two-pass transforms), in place
+void ntt_inverse_last_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm);
 // the first pass of the forward transform alone, in place
 void ntt_forward_first_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm);
 // NTT over n_limbs limbs of length N at d (limb l uses the prime given by lm).

@@ -28,7 +28,8 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
                                                            const PrimeD* __restrict__ pc,
                                                            const double* __restrict__ tw,
                                                            const uint64_t* __restrict__ dtop, int64_t dtop_ct,
-                                                           int64_t dtop_comp, double pmod_top) {
+                                                           int64_t dtop_comp, double pmod_top, int inv_from,
+                                                           const double* __restrict__ itw) {
   constexpr int S = 1 << LOGS;
   constexpr int T = S / 16;
   constexpr int T_LOG = LOGS - 4;
@@ -140,6 +141,37 @@ __global__ void __launch_bounds__(NT_MAX) k_ntt2_key_inner(const uint64_t* __res
   }
   uint64_t* __restrict__ u0 = u + ((size_t)ct * 2 * rows + m) * N + g1;
   uint64_t* __restrict__ u1 = u0 + (size_t)rows * N;
+  if (inv_from >= 0 && m >= inv_from) {
+    // Rows that go on to coefficient form: the first pass of their inverse transform (the
+    // contiguous pass, the geometry of this one) is run here on the canonical sums, as the
+    // separate pass would run it on the stored words.
+    const double* __restrict__ iw = itw + (size_t)pm * N;
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+      double* acc = comp == 0 ? acc0 : acc1;
+      uint64_t* __restrict__ up = comp == 0 ? u0 : u1;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = canon(red(acc[i], q, qinv), q);
+      if (T > 1) {  // with T = 1 the four register stages are the whole pass
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = v[i];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+        gs_stages<(T > 1 ? T / 2 : 1)>(v, iw, N, g2, 0, q, qinv);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
+      }
+      gs_stages<8>(v, iw, N, g1, gs1_log, q, qinv);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(d2u(canon(red(v[i], q, qinv), q)), &up[(size_t)i << gs1_log]);
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     u0[(size_t)i << gs1_log] = to_u(acc0[i], q, qinv);
@@ -356,7 +388,7 @@ void modup_cols(bgv_ctx* c, const uint64_t* xh, uint64_t* y, int n, int level) {
 
 void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,
                          uint64_t* u, int n, int level, bool pass1_done, const uint64_t* dtop, int64_t dtop_ct,
-                         int64_t dtop_comp, double pmod_top) {
+                         int64_t dtop_comp, double pmod_top, int inv_from) {
   const int logN = c->logN;
   int p1, p2;
   ntt_split(c, &p1, &p2);
@@ -372,7 +404,8 @@ void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_c
 #define CASE2(LS)                                                                                              \
   case LS:                                                                                                     \
     hipLaunchKernelGGL((k_ntt2_key_inner<LS>), grid, dim3(NT), 0, c->stream, y, x, x_ct_stride, key, u, logN, p1, \
-                       level, dn, K, A, L, c->Ltot, n, c->d_prime, c->d_tw, dtop, dtop_ct, dtop_comp, pmod_top);  \
+                       level, dn, K, A, L, c->Ltot, n, c->d_prime, c->d_tw, dtop, dtop_ct, dtop_comp, pmod_top,     \
+                       inv_from, c->d_itw);                                                                     \
     break;
     CASE2(4)
     CASE2(5)

@@ -236,6 +236,12 @@ void ntt_inverse_first_pass(bgv_ctx* c, uint64_t* d, const uint64_t* src, int n_
   launch_pass<true>(c, d, n_limbs, lm, p2, p1, 0, src);
 }
 
+void ntt_inverse_last_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm) {
+  int p1, p2;
+  ntt_split(c, &p1, &p2);
+  launch_pass<true>(c, d, n_limbs, lm, p1, 0, 1);
+}
+
 void ntt_forward_first_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm) {
   int p1, p2;
   ntt_split(c, &p1, &p2);

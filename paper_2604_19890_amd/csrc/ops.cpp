@@ -118,7 +118,7 @@ void op_divide_by_p(bgv_ctx* c, const CtV& a, const CtV& out) {
 // with the key.  Returns u [n][2][level+K][N] in evaluation form.
 static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const Scratch& X, int n, int level,
                                          const uint64_t* dtop = nullptr, int64_t dtop_ct = 0, int64_t dtop_comp = 0,
-                                         double pmod_top = 0.0) {
+                                         double pmod_top = 0.0, int inv_from = -1) {
   const int N = c->N, K = c->prm.K, L = c->prm.L, A = c->alpha;
   const int dn = (level + A - 1) / A, rows = level + K;
   c->stats.key_switches += 1;
@@ -141,7 +141,7 @@ static std::unique_ptr<Scratch> ks_inner(bgv_ctx* c, const uint64_t* key, const 
   std::unique_ptr<Scratch> U(new Scratch(c, (size_t)n * 2 * rows * N));
   if (fused) {
     lk::ntt_pass1_key_inner(c, Y.d, X.d, (int64_t)level * N, key, U->d, n, level, mu_fused, dtop, dtop_ct, dtop_comp,
-                            pmod_top);
+                            pmod_top, inv_from);
   } else {
     lk::ntt(c, Y.d, n * dn * rows, LimbMap{rows, level, L, A, dn, 0, 0}, false);
     lk::key_inner(c, Y.d, key, U->d, n, level);
@@ -192,7 +192,9 @@ static void relin_ms(bgv_ctx* c, const bgv_keys* keys, Scratch& D, Scratch& X, i
     for (int k = 0; k < K; ++k) pm = mulmod(pm, c->primes[c->prm.L + k] % qt, qt);
     pmod_top = (double)pm;
   }
-  auto U = fold_top ? ks_inner(c, keys->relin, X, n, lv, dtop, (int64_t)2 * lv * N, (int64_t)lv * N, pmod_top)
+  // With the fused inner product, that pass also runs the first pass of the inverse transform
+  // of u's top and special rows before storing them.
+  auto U = fold_top ? ks_inner(c, keys->relin, X, n, lv, dtop, (int64_t)2 * lv * N, (int64_t)lv * N, pmod_top, lv - 1)
                     : ks_inner(c, keys->relin, X, n, lv);
   // u's top row and its special rows are the K + 1 consecutive rows lv-1 .. lv+K-1
   // of every polynomial: one inverse transform brings them all to coefficient form
@@ -200,7 +202,10 @@ static void relin_ms(bgv_ctx* c, const bgv_keys* keys, Scratch& D, Scratch& X, i
   ut.grp = K + 1;
   ut.grp_stride = rows;
   ut.grp_first = lv - 1;
-  lk::ntt(c, U->d, 2 * n * (K + 1), ut, true);
+  if (fold_top)
+    lk::ntt_inverse_last_pass(c, U->d, 2 * n * (K + 1), ut);
+  else
+    lk::ntt(c, U->d, 2 * n * (K + 1), ut, true);
   if (!fold_top) {
     LimbMap top{1, 1, c->prm.L, 0, 1, lv - 1, 0};
     top.grp = 1;
