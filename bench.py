@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0
 # the bytes moved (scale 2.0) and WRITE_SIZE all of them (1.0).  The figures belong to the
 # sources they were taken on (hash below) and are reported only while those are unchanged.
 NTT_COUNTERS = {
-    "sources_sha256": "1991a95023474a3a00fe1f3e45cbab08d6ff148853ae06133389c15abd7dfdd0",
+    "sources_sha256": "2a053c8121c3404e17c5122085640352afc5ba70e0c06515db9cdff8f240c5a2",
     "sources": ('ntt.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp'),
     "units": 960,  # limbs
     "fetch_kib": [246089, 253499],
@@ -60,11 +60,11 @@ NTT_COUNTERS = {
 # summed) from the same two counter runs of `bench.py --ks-only --cts 32 --steps 3`, with the
 # copy-derived scales (profiles/product_step_n65536_b32.md).
 KS_COUNTERS = {
-    "sources_sha256": "bf5703b12649eeae8136ccc2b5424ec603a9e0634adfcb27ec553896865ba2e7",
+    "sources_sha256": "0b8ae95ac4840487c6092370f78a67a2e9743f567489cc25ce2a82b59138f0d5",
     "sources": ('ntt.hip', 'keyswitch.hip', 'kernels.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp', 'ops.cpp'),
     "units": 32,  # ciphertext pairs
-    "fetch_kib": [5363657],  # the step's 11 dispatches summed (mean of four repetitions)
-    "write_kib": [8978491],
+    "fetch_kib": [5215793],  # the step's 8 dispatches summed (mean of four repetitions)
+    "write_kib": [8683575],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
