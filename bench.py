@@ -56,14 +56,14 @@ NTT_COUNTERS = {
     "write_scale": 1.0,
 }
 
-# HBM traffic of the product step (bgv_mul, 32 ciphertext pairs at level 30: its 11 dispatches
+# HBM traffic of the product step (bgv_mul, 32 ciphertext pairs at level 30: its 8 dispatches
 # summed) from the same two counter runs of `bench.py --ks-only --cts 32 --steps 3`, with the
 # copy-derived scales (profiles/product_step_n65536_b32.md).
 KS_COUNTERS = {
     "sources_sha256": "0b8ae95ac4840487c6092370f78a67a2e9743f567489cc25ce2a82b59138f0d5",
     "sources": ('ntt.hip', 'keyswitch.hip', 'kernels.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp', 'ops.cpp'),
     "units": 32,  # ciphertext pairs
-    "fetch_kib": [5215793],  # the step's 8 dispatches summed (mean of four repetitions)
+    "fetch_kib": [5215793],  # the step's 8 dispatches summed (mean over the repetitions)
     "write_kib": [8683575],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
