@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0
 # the bytes moved (scale 2.0) and WRITE_SIZE all of them (1.0).  The figures belong to the
 # sources they were taken on (hash below) and are reported only while those are unchanged.
 NTT_COUNTERS = {
-    "sources_sha256": "2a053c8121c3404e17c5122085640352afc5ba70e0c06515db9cdff8f240c5a2",
+    "sources_sha256": "e1c7dbd56b61a16f2ae8364b229edcc76d847768deb19a41f517988c53fded3a",
     "sources": ('ntt.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp'),
     "units": 960,  # limbs
     "fetch_kib": [246089, 253499],
@@ -56,15 +56,15 @@ NTT_COUNTERS = {
     "write_scale": 1.0,
 }
 
-# HBM traffic of the product step (bgv_mul, 32 ciphertext pairs at level 30: its 8 dispatches
+# HBM traffic of the product step (bgv_mul, 32 ciphertext pairs at level 30: its 6 dispatches
 # summed) from the same two counter runs of `bench.py --ks-only --cts 32 --steps 3`, with the
 # copy-derived scales (profiles/product_step_n65536_b32.md).
 KS_COUNTERS = {
-    "sources_sha256": "0b8ae95ac4840487c6092370f78a67a2e9743f567489cc25ce2a82b59138f0d5",
+    "sources_sha256": "5011c9c28a9477665a168610ccb21cde6f5dd500a7fa3e5f6e4dafa71f45bc82",
     "sources": ('ntt.hip', 'keyswitch.hip', 'kernels.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp', 'ops.cpp'),
     "units": 32,  # ciphertext pairs
-    "fetch_kib": [5215793],  # the step's 8 dispatches summed (mean over the repetitions)
-    "write_kib": [8683575],
+    "fetch_kib": [4626420],  # the step's 6 dispatches summed (mean over the repetitions)
+    "write_kib": [7504018],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

@@ -326,6 +326,15 @@ int32_t bgv_get_ntt_chunk(const bgv_ctx* ctx);
  *   the untransformed ModUp rows are stored) or ModUp between full transforms (0).
  *   Results are identical either way.                                                 */
 bgv_status bgv_set_modup_fused(bgv_ctx* ctx, int32_t on);
+/* bgv_set_moddown_fused: how the product step (bgv_mul and the evaluator's products) runs
+ *   ModDown and the modulus switch after key switching, on rings with two-pass transforms
+ *   whose first pass has 5..8 stages and K <= 6.  Fused, the last inverse pass of u's special
+ *   and top rows, the merged correction and the first forward pass of every corrected row
+ *   run in one kernel, so the correction is never stored in coefficient form.  on = 0: never
+ *   fused (separate launches); 1 (the default): fused when the batch gives that kernel at
+ *   least 512 blocks (16 ciphertexts at N = 2^16), below which the separate launches are
+ *   faster; 2: always fused.  Other values: BGV_E_ARG.  Results are identical either way.  */
+bgv_status bgv_set_moddown_fused(bgv_ctx* ctx, int32_t on);
 /* bgv_set_ntt_coop: how two-pass transforms run.  mode 0 (the only one built): two
  *   launches per transform.  mode 1, a persistent launch that would keep each limb's
  *   intermediate in one XCD's L2, is switched off and returns BGV_E_UNSUPPORTED.     */

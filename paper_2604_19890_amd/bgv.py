@@ -115,6 +115,7 @@ _sigs = {
     "bgv_mod_switch_noalloc": [_vp, _P(_Ct), _P(_Ct)],
     "bgv_set_ntt_coop": [_vp, _i32, _i32],
     "bgv_set_modup_fused": [_vp, _i32],
+    "bgv_set_moddown_fused": [_vp, _i32],
     "bgv_filter_and_products": [_vp, _vp, _i32, _vp, _vp, _vp, _P(_Ct), _P(_Ct), _P(_Ct)],
     "bgv_filter_and_sum": [_vp, _vp, _i32, _vp, _vp, _vp, _P(_Ct), _P(_Ct), _P(_Ct)],
     "bgv_reset_stats": [_vp],
@@ -268,6 +269,11 @@ class Context:
         h = ctypes.c_void_p()
         self._check(_lib.bgv_capture_end(self.handle, ctypes.byref(h)))
         return Graph(self, h)
+
+    def set_moddown_fused(self, mode: int):
+        """The product step's ModDown and switch fused with the passes around them: 0 never, 1 (the default)
+        when the batch is large enough for the fused kernel to pay, 2 always."""
+        self._check(_lib.bgv_set_moddown_fused(self.handle, int(mode)))
 
     def set_modup_fused(self, on: bool):
         """Key switching with the fused ModUp pass (True, the default) or ModUp between full transforms."""

@@ -169,6 +169,13 @@ BGV_EXPORT bgv_status bgv_set_modup_fused(bgv_ctx* c, int32_t on) {
   return BGV_OK;
 }
 
+BGV_EXPORT bgv_status bgv_set_moddown_fused(bgv_ctx* c, int32_t on) {
+  NEED_CTX(c);
+  if (on < 0 || on > 2) return fail(c, BGV_E_ARG, "0, 1 or 2");
+  c->moddown_fused = on;
+  return BGV_OK;
+}
+
 BGV_EXPORT bgv_status bgv_set_ntt_coop(bgv_ctx* c, int32_t mode, int32_t lookahead) {
   NEED_CTX(c);
   if (mode < 0 || mode > 1 || lookahead < 0 || lookahead > 16) return fail(c, BGV_E_ARG, "mode 0/1, lookahead 0..16");

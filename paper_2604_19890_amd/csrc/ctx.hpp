@@ -61,6 +61,8 @@ struct bgv_ctx {
   int ntt_split = 0;  // stages in the first of two NTT passes (0: ceil(log N / 2))
   int schedule = 0;   // polynomial evaluation schedule (BGV_SCHED_FAST / BGV_SCHED_BASIC)
   int modup_fused = 1;  // key switching with the fused ModUp pass (1) or ModUp between full transforms (0)
+  int moddown_fused = 1;  // the product step's ModDown and switch fused with the passes around them: 0 never,
+                          // 1 when the batch gives the fused kernel two blocks per CU, 2 always
   int graphs_alive = 0;  // executable graphs referring to pool buffers (trim keeps them then)
   bool capturing = false;
   hipStream_t cap_stream = nullptr;    // capture happens here (default priority, non-blocking)
@@ -150,6 +152,13 @@ void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_c
 // true when the fused ModUp below applies (two-pass transforms whose first pass has 5..8
 // stages, digits of 1, 2, 4 or 6 primes)
 bool modup_cols_ok(const bgv_ctx* c);
+// true when the fused ModDown below applies to a batch of n ciphertexts (two-pass transforms
+// whose first pass has 5..8 stages, K <= 6, and the setting above)
+bool moddown_cols_ok(const bgv_ctx* c, int n);
+// From u [n][2][level+K][N], whose top row holds u_top + P d_top and whose top and special
+// rows have had the first pass of their inverse transform, the merged ModDown/switch
+// correction e [n][2][level-1][N] after the first pass of its forward transform
+void moddown_cols(bgv_ctx* c, const uint64_t* u, uint64_t* e, int n, int level, int t_exp);
 // From xh [n][level][N] -- x after the first pass of its inverse transform -- the ModUp output
 // y [n][dn][level+K][N] with the first forward pass done on every non-own row (as ModUp and
 // that pass would leave it); x's own-digit rows are not written
@@ -181,6 +190,8 @@ struct NttEpi {
 // with epi the last forward pass writes epi->out instead (see NttEpi)
 void ntt(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, bool inverse, const uint64_t* src = nullptr,
          const NttEpi* epi = nullptr);
+// the last pass of the forward transform alone (two-pass transforms), with the epilogue
+void ntt_forward_last_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, const NttEpi* epi);
 
 // out = a (op) b elementwise per limb; op 0 add, 1 sub; b_bcast: b has one ciphertext
 void add_sub(bgv_ctx* c, const uint64_t* a, const uint64_t* b, uint64_t* out, int n, int level, int op, bool b_bcast,

@@ -343,6 +343,165 @@ __global__ void __launch_bounds__(NT_MAX, 2) k_modup_cols(const uint64_t* __rest
   }
 }
 
+// ModDown merged with the switch, fused with the transform passes around it (the mirror of
+// k_modup_cols).  u [n][2][rows][N] holds u's top row (u_top + P d_top) and K special rows after
+// the first pass of their inverse transform.  A block takes one column block of one polynomial
+// cc = ct * 2 + comp:
+//  * the last inverse pass of the K special rows, each scaled to v_k = [u_k t^-1 Phat_k^-1]_{p_k}
+//    (N^-1 folded into the same constant), and of the top row, which gives the switch's centered
+//    w from u_top + P d_top and the ModDown conversion of the v_k at the top prime;
+//  * for every target row i < level - 1: e_i = sum_k v_k [Phat_k t P^-1]_{q_i} + t w, the first
+//    forward pass of e_i under q_i, and the store.
+// e [n][2][level-1][N] then holds what the merged correction and the first forward pass would
+// have written.  Three of the K converted rows and w's row stay in registers, the others in
+// LDS (96 KiB at K = 6); one block per CU.
+template <int LOGS, int KK>
+__global__ void __launch_bounds__(NT_MAX, 1) k_moddown_cols(const uint64_t* __restrict__ u, uint64_t* __restrict__ e,
+                                                         int logN, int level, int rows, int Lfull,
+                                                         const double* __restrict__ md,
+                                                         const double* __restrict__ mdfold,
+                                                         const double* __restrict__ tinv,
+                                                         const double* __restrict__ tmod,
+                                                         const PrimeD* __restrict__ pc, const double* __restrict__ tw,
+                                                         const double* __restrict__ itw) {
+  constexpr int S = 1 << LOGS;
+  constexpr int T = S / 16;
+  constexpr int T_LOG = LOGS - 4;
+  static_assert(T > 1, "the staged twiddles rely on the exchange barriers");
+  __shared__ double lds[NT_MAX * 16 + NT_MAX + NT_MAX];
+  __shared__ double ltw[2][S];
+  const int N = 1 << logN;
+  const int NT = blockDim.x;
+  const int SUBS = NT / T;
+  const int cc = blockIdx.y;
+  const int tmax_log = logN - 1;
+  const int tmin_log = logN - LOGS;
+  const int sl = threadIdx.x % SUBS;
+  const int tau = threadIdx.x / SUBS;
+  const int bx = (blockIdx.x + blockIdx.y) & (gridDim.x - 1);
+  const int st = bx * SUBS + sl;
+  const int lo_c = st & ((1 << tmin_log) - 1);
+  const int hi_c = st >> tmin_log;
+  const int base = (hi_c << (tmax_log + 1)) + lo_c;
+  const int g1 = base + (tau << tmin_log);
+  const int gs1_log = T_LOG + tmin_log;
+  const int g2 = base + ((16 * tau) << tmin_log);
+  const double* phat_inv = md;
+  const double* phat_mod = md + KK;
+  const double* pinv = md + KK + (size_t)KK * Lfull;
+  const uint64_t* __restrict__ ub = u + (size_t)cc * rows * N + g1;
+  // the last inverse (column) pass of one row in place on v, as the separate pass runs it
+  auto inverse_last_pass = [&](double* v, const double* __restrict__ w, double q, double qinv) {
+    __syncthreads();  // the previous row's last LDS reads are done
+#pragma unroll
+    for (int i = 0; i < 16; ++i) lds[lds_idx(sl, tau + T * i, S)] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, 16 * tau + i, S)];
+    gs_stages<T / 2>(v, w, N, g2, tmin_log, q, qinv);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) lds[lds_idx(sl, 16 * tau + i, S)] = red(v[i], q, qinv);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = lds[lds_idx(sl, tau + T * i, S)];
+    gs_stages<8>(v, w, N, g1, gs1_log, q, qinv);
+  };
+  constexpr int RS = KK < 3 ? KK : 3;  // converted rows held in registers; the rest in LDS
+  __shared__ double lsrc[(KK > RS ? KK - RS : 1) * 16 * NT_MAX];
+  double vk[RS][16];
+  auto src = [&](int k, int i) -> double {
+    return k < RS ? vk[k < RS ? k : 0][i] : lsrc[((k - RS) * 16 + i) * NT_MAX + threadIdx.x];
+  };
+#pragma unroll
+  for (int k = 0; k < KK; ++k) {
+    const int pk = Lfull + k;
+    const double q = pc[pk].q, qinv = pc[pk].qinv;
+    // N^-1 t^-1 Phat_k^-1 mod p_k
+    const double sc = canon(red(mul_lazy(canon(red(mul_lazy(pc[pk].ninv, tinv[pk], q, qinv), q, qinv), q),
+                                         phat_inv[k], q, qinv), q, qinv), q);
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = u2d(__builtin_nontemporal_load(&ub[(size_t)(level + k) * N + ((size_t)i << gs1_log)]));
+    inverse_last_pass(v, itw + (size_t)pk * N, q, qinv);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const double o = canon(red(mul_lazy(red(v[i], q, qinv), sc, q, qinv), q, qinv), q);
+      if (k < RS) vk[k < RS ? k : 0][i] = o;
+      else lsrc[((k - RS) * 16 + i) * NT_MAX + threadIdx.x] = o;
+    }
+  }
+  double wms[16];
+  {
+    const int it = level - 1;
+    const double q = pc[it].q, qinv = pc[it].qinv;
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = u2d(__builtin_nontemporal_load(&ub[(size_t)it * N + ((size_t)i << gs1_log)]));
+    inverse_last_pass(v, itw + (size_t)it * N, q, qinv);
+    const double ninv = pc[it].ninv, tm = tmod[it], pv = pinv[it], ti = tinv[it];
+    double pm[KK];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) pm[k] = phat_mod[(size_t)k * Lfull + it];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const double ut = red(mul_lazy(red(v[i], q, qinv), ninv, q, qinv), q, qinv);  // u_top + P d_top
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < KK; ++k) acc += mul_lazy(src(k, i), pm[k], q, qinv);
+      const double wt = canon(red(acc, q, qinv), q);
+      const double diff = red(ut - mul_lazy(wt, tm, q, qinv), q, qinv);
+      const double o = canon(red(mul_lazy(diff, pv, q, qinv), q, qinv), q);
+      const double w = canon(mul_lazy(o, ti, q, qinv), q);
+      wms[i] = w > (q - 1.0) * 0.5 ? w - q : w;  // centered
+    }
+  }
+  // ---- targets: the correction of every row below the top, its first forward pass, store
+  const int nt = level - 1;
+  const int per = (nt + gridDim.z - 1) / gridDim.z;
+  const int i_end = min(nt, ((int)blockIdx.z + 1) * per);
+  int i = blockIdx.z * per;
+  const bool lane_stages = (int)threadIdx.x < S;
+  if (i < i_end && lane_stages) ltw[0][threadIdx.x] = tw[(size_t)i * N + threadIdx.x];
+  __syncthreads();
+  uint64_t* __restrict__ eb = e + (size_t)cc * nt * N + g1;
+  for (int buf = 0; i < i_end; ++i, buf ^= 1) {
+    const bool stage = i + 1 < i_end && lane_stages;
+    const double pre = stage ? tw[(size_t)(i + 1) * N + threadIdx.x] : 0.0;
+    const double q = pc[i].q, qinv = pc[i].qinv;
+    double f[KK];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) f[k] = mdfold[(size_t)k * Lfull + i];
+    const double tm = tmod[i];
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < KK; ++k) a += mul_lazy(src(k, j), f[k], q, qinv);
+      const double b = mul_lazy(wms[j] < 0.0 ? wms[j] + q : wms[j], tm, q, qinv);
+      v[j] = canon(red(red(a, q, qinv) + b, q, qinv), q);
+    }
+    const double* w = ltw[buf];
+    ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) lds[lds_idx(sl, tau + T * j, S)] = red(v[j], q, qinv);
+    __syncthreads();
+    if (stage) ltw[buf ^ 1][threadIdx.x] = pre;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = lds[lds_idx(sl, 16 * tau + j, S)];
+    ct_stages<T / 2>(v, w, N, g2, tmin_log, q, qinv);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) lds[lds_idx(sl, 16 * tau + j, S)] = red(v[j], q, qinv);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = lds[lds_idx(sl, tau + T * j, S)];
+    uint64_t* ep = eb + (size_t)i * N;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) __builtin_nontemporal_store(d2u(canon(red(v[j], q, qinv), q)), &ep[(size_t)j << gs1_log]);
+  }
+}
+
 }  // namespace
 
 namespace lk {
@@ -384,6 +543,48 @@ void modup_cols(bgv_ctx* c, const uint64_t* xh, uint64_t* y, int n, int level) {
   MU_ALPHAS(8)
 #undef MU_ALPHAS
 #undef MU_CASE
+}
+
+bool moddown_cols_ok(const bgv_ctx* c, int n) {
+  int p1, p2;
+  ntt_split(c, &p1, &p2);
+  if (c->moddown_fused == 0 || p2 <= 0 || p1 < 5 || p1 > 8 || c->prm.K < 1 || c->prm.K > 6) return false;
+  if (c->moddown_fused == 2) return true;
+  // one block per CU runs (one wave per SIMD): on a smaller grid the separate launches are faster
+  // (measured at N = 2^16: the fused product step slower by 1-25% up to 8 ciphertexts, even at 16)
+  const int S = 1 << p1, T = S / 16;
+  const int NT = c->N / 16 < NT_MAX ? c->N / 16 : NT_MAX;
+  return (int64_t)((c->N / S) / (NT / T)) * n * 2 >= 512;
+}
+
+void moddown_cols(bgv_ctx* c, const uint64_t* u, uint64_t* e, int n, int level, int t_exp) {
+  int p1, p2;
+  ntt_split(c, &p1, &p2);
+  const int N = c->N, K = c->prm.K, L = c->prm.L, rows = level + K;
+  const int S = 1 << p1, T = S / 16;
+  const int NT = N / 16 < NT_MAX ? N / 16 : NT_MAX;
+  const int SUBS = NT / T;
+  // one block per CU: spread the target rows over up to 8 blocks while the grid is small
+  const int base_blocks = ((N / S) / SUBS) * n * 2;
+  int split = 1;
+  while (split < 8 && base_blocks * split < 512 && (level - 1) / (split * 2) >= 1) split *= 2;
+  dim3 grid((N / S) / SUBS, n * 2, split);
+  const double* mdfold = c->d_mdfold + (size_t)t_exp * K * L;
+  const double* tinv = c->d_tconst + (size_t)2 * t_exp * c->Ltot;
+  const double* tmod = c->d_tconst + ((size_t)2 * t_exp + 1) * c->Ltot;
+#define MD_CASE(LS, KKK)                                                                                           \
+  if (p1 == LS && K == KKK) {                                                                                      \
+    hipLaunchKernelGGL((k_moddown_cols<LS, KKK>), grid, dim3(NT), 0, c->stream, u, e, c->logN, level, rows, L,       \
+                       c->d_moddown, mdfold, tinv, tmod, c->d_prime, c->d_tw, c->d_itw);                           \
+    return;                                                                                                        \
+  }
+#define MD_KS(LS) MD_CASE(LS, 1) MD_CASE(LS, 2) MD_CASE(LS, 3) MD_CASE(LS, 4) MD_CASE(LS, 5) MD_CASE(LS, 6)
+  MD_KS(5)
+  MD_KS(6)
+  MD_KS(7)
+  MD_KS(8)
+#undef MD_KS
+#undef MD_CASE
 }
 
 void ntt_pass1_key_inner(bgv_ctx* c, uint64_t* y, const uint64_t* x, int64_t x_ct_stride, const uint64_t* key,

@@ -242,6 +242,12 @@ void ntt_inverse_last_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm) {
   launch_pass<true>(c, d, n_limbs, lm, p1, 0, 1);
 }
 
+void ntt_forward_last_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm, const NttEpi* epi) {
+  int p1, p2;
+  ntt_split(c, &p1, &p2);
+  launch_pass<false>(c, d, n_limbs, lm, p2, p1, 1, nullptr, epi);
+}
+
 void ntt_forward_first_pass(bgv_ctx* c, uint64_t* d, int n_limbs, LimbMap lm) {
   int p1, p2;
   ntt_split(c, &p1, &p2);

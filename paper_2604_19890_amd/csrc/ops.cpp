@@ -202,10 +202,15 @@ static void relin_ms(bgv_ctx* c, const bgv_keys* keys, Scratch& D, Scratch& X, i
   ut.grp = K + 1;
   ut.grp_stride = rows;
   ut.grp_first = lv - 1;
-  if (fold_top)
-    lk::ntt_inverse_last_pass(c, U->d, 2 * n * (K + 1), ut);
-  else
-    lk::ntt(c, U->d, 2 * n * (K + 1), ut, true);
+  // with the fused ModDown, the last inverse pass of those rows, the correction and its first
+  // forward pass are one kernel
+  const bool md_fused = fold_top && lk::moddown_cols_ok(c, n);
+  if (!md_fused) {
+    if (fold_top)
+      lk::ntt_inverse_last_pass(c, U->d, 2 * n * (K + 1), ut);
+    else
+      lk::ntt(c, U->d, 2 * n * (K + 1), ut, true);
+  }
   if (!fold_top) {
     LimbMap top{1, 1, c->prm.L, 0, 1, lv - 1, 0};
     top.grp = 1;
@@ -214,8 +219,11 @@ static void relin_ms(bgv_ctx* c, const bgv_keys* keys, Scratch& D, Scratch& X, i
     lk::ntt(c, D.d, 2 * n, top, true);  // d tops
   }
   Scratch E(c, (size_t)n * 2 * (lv - 1) * N);
-  lk::ms_corr(c, U->d + (size_t)lv * N, (int64_t)rows * N, U->d + (size_t)(lv - 1) * N, (int64_t)rows * N,
-              fold_top ? nullptr : dtop, (int64_t)lv * N, E.d, n, lv, t_exp);
+  if (md_fused)
+    lk::moddown_cols(c, U->d, E.d, n, lv, t_exp);
+  else
+    lk::ms_corr(c, U->d + (size_t)lv * N, (int64_t)rows * N, U->d + (size_t)(lv - 1) * N, (int64_t)rows * N,
+                fold_top ? nullptr : dtop, (int64_t)lv * N, E.d, n, lv, t_exp);
   // forward NTT of e with the final step in its last pass:
   // out_i = (d_i - e_i + u_i P^-1) q_top^-1 for i < level-1
   lk::NttEpi ep{};
@@ -227,7 +235,10 @@ static void relin_ms(bgv_ctx* c, const bgv_keys* keys, Scratch& D, Scratch& X, i
   ep.qt = c->d_msw + (size_t)(lv - 1) * c->prm.L;   // q_top^-1 mod q_i
   ep.out = out.d;
   ep.rows = lv - 1;
-  lk::ntt(c, E.d, n * 2 * (lv - 1), lm_chain(c, lv - 1), false, nullptr, &ep);
+  if (md_fused)
+    lk::ntt_forward_last_pass(c, E.d, n * 2 * (lv - 1), lm_chain(c, lv - 1), &ep);
+  else
+    lk::ntt(c, E.d, n * 2 * (lv - 1), lm_chain(c, lv - 1), false, nullptr, &ep);
 }
 
 // Relinearised product followed by one modulus switch.

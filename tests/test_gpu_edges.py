@@ -133,6 +133,15 @@ def test_unknown_schedule_is_rejected():
     c.lib.set_schedule("fast")
 
 
+def test_fusion_settings_reject_unknown_modes():
+    c = pair_tiny17()
+    G, h = c.G._lib, c.lib.handle
+    assert G.bgv_set_moddown_fused(h, 3) == 1 and G.bgv_set_moddown_fused(h, -1) == 1  # BGV_E_ARG
+    assert G.bgv_set_modup_fused(h, 2) == 1
+    for m in (0, 2, 1):
+        assert G.bgv_set_moddown_fused(h, m) == 0
+
+
 def test_noise_estimates_through_the_binding():
     """Every call that writes a batch gives it an estimate; a batch without one (noise 0) is
     lowered by rescaling switches only and still decrypts to the right values; concat keeps the

@@ -56,3 +56,53 @@ def test_fused_modup_matches_at_the_benchmark_ring():
     lo = c.lib.mod_switch_to(ga, 29)
     hi = c.lib.mul(c.keys, ga, ga)  # level 29: its noise lets lo's partner be dropped to 28
     _both(c.lib, c.keys, c.lib.mod_switch_to(lo, 28), hi)  # hi reaches 28 as a view of its limbs
+
+
+def _both_moddown(lib, keys, a, b):
+    try:
+        lib.set_moddown_fused(2)  # fused whatever the batch
+        f = lib.mul(keys, a, b)
+        lib.set_moddown_fused(0)
+        u = lib.mul(keys, a, b)
+    finally:
+        lib.set_moddown_fused(1)
+    torch.cuda.synchronize()
+    assert (f.n, f.level, f.t_exp, f.noise) == (u.n, u.level, u.t_exp, u.noise)
+    w = f.n * lib.words(f.level)
+    assert torch.equal(f.tensor[:w], u.tensor[:w]), "fused ModDown differs from the separate launches"
+    return f
+
+
+def test_fused_moddown_matches_on_a_two_pass_ring():
+    """The product step's fused ModDown (last inverse pass of u's special and top rows, the
+    merged correction and its first forward pass in one kernel) against the separate launches,
+    at every first-pass length, and against the oracle."""
+    c = pair_two_pass()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(63)
+    ga, oa = c.enc_both(g.integers(0, t, size=(3, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(3, P.ell)))
+    try:
+        for split in range(4, 7):
+            c.lib.set_ntt_split(split)
+            f = _both_moddown(c.lib, c.keys, ga, gb)
+            c.assert_equal(f, [S._mul(P, c.okeys, x, y) for x, y in zip(oa, ob)], f"product, split {split}")
+    finally:
+        c.lib.set_ntt_split(0)
+
+
+def test_fused_moddown_matches_at_the_benchmark_ring():
+    log("[fusions] ModDown N=2^16 L=30 K=6")
+    c = Pair(16, 257, 2, 30, 6, steps=(), conj=False, oracle_keys=False, hw=120)
+    P = c.P
+    g = np.random.default_rng(64)
+    ga, _ = c.enc_both(g.integers(0, P.t_full, size=(3, P.ell)), oracle=False)
+    gb, _ = c.enc_both(g.integers(0, P.t_full, size=(1, P.ell)), oracle=False)
+    _both_moddown(c.lib, c.keys, ga, gb)  # broadcast b
+    lo = c.lib.mod_switch_to(ga, 25)  # a lower level: shorter chain of targets
+    _both_moddown(c.lib, c.keys, lo, c.lib.mod_switch_to(ga, 25))
+    # 16 ciphertexts: the default setting takes the fused kernel by itself
+    gc, _ = c.enc_both(g.integers(0, P.t_full, size=(16, P.ell)), oracle=False)
+    d = c.lib.mul(c.keys, gc, gc)
+    f = _both_moddown(c.lib, c.keys, gc, gc)
+    assert torch.equal(d.tensor[:f.n * c.lib.words(f.level)], f.tensor[:f.n * c.lib.words(f.level)])
