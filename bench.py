@@ -60,11 +60,11 @@ NTT_COUNTERS = {
 # summed) from the same two counter runs of `bench.py --ks-only --cts 32 --steps 3`, with the
 # copy-derived scales (profiles/product_step_n65536_b32.md).
 KS_COUNTERS = {
-    "sources_sha256": "5011c9c28a9477665a168610ccb21cde6f5dd500a7fa3e5f6e4dafa71f45bc82",
+    "sources_sha256": "78efa455d3ef44a3461c40636ab04de1ea7188f15c5c08295fc3d8586f403a43",
     "sources": ('ntt.hip', 'keyswitch.hip', 'kernels.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp', 'ops.cpp'),
     "units": 32,  # ciphertext pairs
-    "fetch_kib": [4626420],  # the step's 6 dispatches summed (mean over the repetitions)
-    "write_kib": [7504018],
+    "fetch_kib": [4626419],  # the step's 6 dispatches summed (mean over the repetitions)
+    "write_kib": [7504045],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
