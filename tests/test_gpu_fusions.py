@@ -1,11 +1,14 @@
-"""The fused ModUp gives the same words as ModUp between full transforms.
+"""The fused ModUp and ModDown give the same words as the separate launches they replace.
 
 Key switching raises d2 to the special primes either inside the column pass of the forward
 transform (bgv_set_modup_fused on, the default) or as inverse transform, basis extension and
 forward transform in separate launches.  The two are compared on a two-pass ring small
 enough for the oracle (whose parity tests run the fused form), at every first-pass length
 the ring allows, and at the benchmark's ring (N = 2^16, 30 + 6 primes) with a broadcast
-operand and with an operand that is a view of the lower limbs of a deeper batch."""
+operand and with an operand that is a view of the lower limbs of a deeper batch.  The
+product step's ModDown and switch (bgv_set_moddown_fused: 2 always fused, 0 separate) are
+compared the same way, against the oracle on the two-pass ring, and at the benchmark's ring
+and the served mix's smaller rings at the batch sizes where the default setting fuses."""
 import numpy as np
 import pytest
 import torch
@@ -106,3 +109,18 @@ def test_fused_moddown_matches_at_the_benchmark_ring():
     d = c.lib.mul(c.keys, gc, gc)
     f = _both_moddown(c.lib, c.keys, gc, gc)
     assert torch.equal(d.tensor[:f.n * c.lib.words(f.level)], f.tensor[:f.n * c.lib.words(f.level)])
+
+
+@pytest.mark.parametrize("logN,L,K,n", [(14, 8, 2, 64), (15, 16, 4, 32)])
+def test_fused_moddown_matches_on_the_served_rings(logN, L, K, n):
+    """The served mix's smaller rings (7- and 8-stage first passes, K = 2 and 4) at the round sizes
+    the server uses there, where the default setting takes the fused kernel."""
+    log(f"[fusions] ModDown N=2^{logN} L={L} K={K} n={n}")
+    c = Pair(logN, 257, 2, L, K, steps=(), conj=False, oracle_keys=False)
+    g = np.random.default_rng(65 + logN)
+    ga, _ = c.enc_both(g.integers(0, c.P.t_full, size=(n, c.P.ell)), oracle=False)
+    gb, _ = c.enc_both(g.integers(0, c.P.t_full, size=(n, c.P.ell)), oracle=False)
+    d = c.lib.mul(c.keys, ga, gb)
+    f = _both_moddown(c.lib, c.keys, ga, gb)
+    w = f.n * c.lib.words(f.level)
+    assert torch.equal(d.tensor[:w], f.tensor[:w])
