@@ -463,7 +463,6 @@ __global__ void __launch_bounds__(NT_MAX, 1) k_moddown_cols(const uint64_t* __re
   const bool lane_stages = (int)threadIdx.x < S;
   if (i < i_end && lane_stages) ltw[0][threadIdx.x] = tw[(size_t)i * N + threadIdx.x];
   __syncthreads();
-  uint64_t* __restrict__ eb = e + (size_t)cc * nt * N + g1;
   for (int buf = 0; i < i_end; ++i, buf ^= 1) {
     const bool stage = i + 1 < i_end && lane_stages;
     const double pre = stage ? tw[(size_t)(i + 1) * N + threadIdx.x] : 0.0;
@@ -483,22 +482,21 @@ __global__ void __launch_bounds__(NT_MAX, 1) k_moddown_cols(const uint64_t* __re
     }
     const double* w = ltw[buf];
     ct_stages<8>(v, w, N, g1, gs1_log, q, qinv);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 16; ++j) lds[lds_idx(sl, tau + T * j, S)] = red(v[j], q, qinv);
+    // Every thread has left the previous row, the last reader of the other twiddle buffer: the
+    // next row's table goes there now, and the barrier after the exchange writes publishes it.
     __syncthreads();
     if (stage) ltw[buf ^ 1][threadIdx.x] = pre;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = lds[lds_idx(sl, 16 * tau + j, S)];
-    ct_stages<T / 2>(v, w, N, g2, tmin_log, q, qinv);
-#pragma unroll
-    for (int j = 0; j < 16; ++j) lds[lds_idx(sl, 16 * tau + j, S)] = red(v[j], q, qinv);
+    for (int j = 0; j < 16; ++j) lds[lds_idx(sl, tau + T * j, S)] = red(v[j], q, qinv);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = lds[lds_idx(sl, tau + T * j, S)];
-    uint64_t* ep = eb + (size_t)i * N;
+    for (int j = 0; j < 16; ++j) v[j] = lds[lds_idx(sl, 16 * tau + j, S)];
+    ct_stages<T / 2>(v, w, N, g2, tmin_log, q, qinv);
+    // stored from the second layout (16 adjacent columns per store, as from the first): without
+    // the exchange back, a row costs one barrier and 32 LDS accesses less
+    uint64_t* ep = e + (size_t)cc * nt * N + g2 + (size_t)i * N;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) __builtin_nontemporal_store(d2u(canon(red(v[j], q, qinv), q)), &ep[(size_t)j << gs1_log]);
+    for (int j = 0; j < 16; ++j) __builtin_nontemporal_store(d2u(canon(red(v[j], q, qinv), q)), &ep[(size_t)j << tmin_log]);
   }
 }
 
