@@ -60,11 +60,11 @@ NTT_COUNTERS = {
 # summed) from the same two counter runs of `bench.py --ks-only --cts 32 --steps 3`, with the
 # copy-derived scales (profiles/product_step_n65536_b32.md).
 KS_COUNTERS = {
-    "sources_sha256": "78efa455d3ef44a3461c40636ab04de1ea7188f15c5c08295fc3d8586f403a43",
+    "sources_sha256": "3d12599d906ae97b0957a12f0d9ebd83ea0da0d53894fbf8666ad94bfba00e65",
     "sources": ('ntt.hip', 'keyswitch.hip', 'kernels.hip', 'ntt_layout.hpp', 'ntt_stages.hpp', 'modarith.hpp', 'common.hpp', 'ops.cpp'),
     "units": 32,  # ciphertext pairs
-    "fetch_kib": [4626419],  # the step's 6 dispatches summed (mean over the repetitions)
-    "write_kib": [7504045],
+    "fetch_kib": [4626416],  # the step's 6 dispatches summed (mean over the repetitions)
+    "write_kib": [7504111],
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
