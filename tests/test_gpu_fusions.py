@@ -8,7 +8,8 @@ the ring allows, and at the benchmark's ring (N = 2^16, 30 + 6 primes) with a br
 operand and with an operand that is a view of the lower limbs of a deeper batch.  The
 product step's ModDown and switch (bgv_set_moddown_fused: 2 always fused, 0 separate) are
 compared the same way, against the oracle on the two-pass ring, and at the benchmark's ring
-and the served mix's smaller rings at the batch sizes where the default setting fuses."""
+and the served mix's smaller rings at the batch sizes where the default setting fuses, and for every special-prime count it is
+built for."""
 import numpy as np
 import pytest
 import torch
@@ -124,3 +125,17 @@ def test_fused_moddown_matches_on_the_served_rings(logN, L, K, n):
     f = _both_moddown(c.lib, c.keys, ga, gb)
     w = f.n * c.lib.words(f.level)
     assert torch.equal(d.tensor[:w], f.tensor[:w])
+
+
+@pytest.mark.parametrize("K", [1, 3, 5, 6])
+def test_fused_moddown_every_special_prime_count(K):
+    """The special-prime counts the fused ModDown is built for beyond those above (K = 2 and 4), on
+    a two-pass ring, against the separate launches and the oracle."""
+    log(f"[fusions] ModDown N=2^10 L=8 K={K}")
+    c = Pair(10, 17, 2, 8, K, steps=(), conj=False)
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(70 + K)
+    ga, oa = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    f = _both_moddown(c.lib, c.keys, ga, gb)
+    c.assert_equal(f, [S._mul(P, c.okeys, x, y) for x, y in zip(oa, ob)], f"product, K = {K}")
