@@ -125,6 +125,11 @@ def test_products_rotation_and_switches_on_extremal_words_n1024(names_a, names_b
     ga, gb, oa, ob = _extremal_pair(c, P.L, names_a, names_b)
     c.assert_equal(c.lib.mul_relin(c.keys, ga, gb), [B.mul_relin(P, c.okeys.relin, oa, ob)], "mul_relin")
     c.assert_equal(c.lib.mul(c.keys, ga, gb), [S._mul(P, c.okeys, oa, ob)], "product step")
+    c.lib.set_moddown_fused(2)  # the fused ModDown, which a single ciphertext does not take by default
+    try:
+        c.assert_equal(c.lib.mul(c.keys, ga, gb), [S._mul(P, c.okeys, oa, ob)], "product step, fused ModDown")
+    finally:
+        c.lib.set_moddown_fused(1)
     c.assert_equal(c.lib.rotate(c.keys, ga, 1), [B.rotate(P, c.okeys.galois, oa, 1)], "rotate")
     c.assert_equal(c.lib.mod_switch(gb), [B.mod_switch(P, ob)], "mod_switch")
     c.assert_equal(c.lib.mod_switch_to(ga, 1), [B.align(P, oa, 1)], "mod_switch_to 1")
@@ -158,5 +163,11 @@ def test_product_step_on_extremal_words_at_the_benchmark_shape():
     ref = B.mul_relin_at(P, c.okeys.relin, oa, ob, idx)
     ref_ms = B.mod_switch_cols(P, B.Ct(ref, lv, P.r))
     assert np.array_equal(c.coeff_words(prod)[0][:, :, idx], ref_ms.c), "product step"
+    c.lib.set_moddown_fused(2)
+    try:
+        prod_f = c.lib.mul(c.keys, ga, gb)
+    finally:
+        c.lib.set_moddown_fused(1)
+    assert np.array_equal(c.coeff_words(prod_f)[0][:, :, idx], ref_ms.c), "product step, fused ModDown"
     c.assert_equal(c.lib.mod_switch_to(ga, 12), [B.align(P, oa, 12)], "mod_switch_to 12 (18 drops)")
     c.assert_equal(c.lib.mod_switch(gb), [B.mod_switch(P, ob)], "mod_switch")
