@@ -8,12 +8,13 @@ the ring allows, and at the benchmark's ring (N = 2^16, 30 + 6 primes) with a br
 operand and with an operand that is a view of the lower limbs of a deeper batch.  The
 product step's ModDown and switch (bgv_set_moddown_fused: 2 always fused, 0 separate) are
 compared the same way, against the oracle on the two-pass ring, and at the benchmark's ring
-and the served mix's smaller rings at the batch sizes where the default setting fuses, and for every special-prime count it is
-built for."""
+and the served mix's smaller rings at the batch sizes where the default setting fuses, for every special-prime count it is
+built for, and at the lowest levels a product step runs at (one and two target rows)."""
 import numpy as np
 import pytest
 import torch
 
+from oracle import bgv as B
 from oracle import space as S
 from tests.gpu_ctx import Pair, log, pair_two_pass
 
@@ -139,3 +140,19 @@ def test_fused_moddown_every_special_prime_count(K):
     gb, ob = c.enc_both(g.integers(0, t, size=(2, P.ell)))
     f = _both_moddown(c.lib, c.keys, ga, gb)
     c.assert_equal(f, [S._mul(P, c.okeys, x, y) for x, y in zip(oa, ob)], f"product, K = {K}")
+
+
+@pytest.mark.parametrize("level", [2, 3])
+def test_fused_moddown_at_the_lowest_levels(level):
+    """The fused ModDown with one or two target rows (a product step at level 2 or 3), against
+    the separate launches and the oracle."""
+    c = pair_two_pass()
+    P, t = c.P, c.P.t_full
+    g = np.random.default_rng(80 + level)
+    ga, oa = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    gb, ob = c.enc_both(g.integers(0, t, size=(2, P.ell)))
+    la, lb = c.lib.mod_switch_to(ga, level), c.lib.mod_switch_to(gb, level)
+    ola = [B.align(P, x, level) for x in oa]
+    olb = [B.align(P, x, level) for x in ob]
+    f = _both_moddown(c.lib, c.keys, la, lb)
+    c.assert_equal(f, [S._mul(P, c.okeys, x, y) for x, y in zip(ola, olb)], f"product at level {level}")
