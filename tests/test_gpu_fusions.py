@@ -7,9 +7,10 @@ enough for the oracle (whose parity tests run the fused form), at every first-pa
 the ring allows, and at the benchmark's ring (N = 2^16, 30 + 6 primes) with a broadcast
 operand and with an operand that is a view of the lower limbs of a deeper batch.  The
 product step's ModDown and switch (bgv_set_moddown_fused: 2 always fused, 0 separate) are
-compared the same way, against the oracle on the two-pass ring, and at the benchmark's ring
-and the served mix's smaller rings at the batch sizes where the default setting fuses, for every special-prime count it is
-built for, and at the lowest levels a product step runs at (one and two target rows)."""
+compared the same way: against the oracle on the two-pass ring, for every special-prime
+count the kernel is built for and at the lowest levels a product step runs at (one and two
+target rows), and at the benchmark's ring and the served mix's smaller rings at the batch
+sizes where the default setting fuses."""
 import numpy as np
 import pytest
 import torch
